@@ -1,0 +1,96 @@
+"""Oracle: Nystrom spectral preconditioner and preconditioned CG on the dual
+system (FP64 CPU).
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+Nystrom construction (Section 4.2 and its appendix algorithm): with landmark
+index set I (passed in; how it is drawn is the caller's business),
+    K_II = Q Lambda_Q Q^T          (keep the positive eigenpairs, rank r)
+    U~_I = Q,  U~_C = K_CI Q Lambda_Q^{-1}
+    M = U~ Lambda_Q^{1/2} = V Sigma W^T (thin SVD)
+    U = V,  Lambda^ = Sigma^2
+Spectral preconditioner (Section 3.3):
+    P^{-1} = U (Lambda^ + lam I)^{-1} U^T + (I - U U^T) / lam
+PCG (appendix algorithm) is run on the alpha form of the dual system,
+(K + lam I) alpha = r, and the step is dtheta = -J^T alpha.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def positive_threshold(Kii, ell_factor=None):
+    """Eigenvalues kept as 'positive': > ell * u * lambda_max(K_II), u the FP64
+    unit roundoff (the paper does not fix the threshold)."""
+    ell = Kii.shape[0] if ell_factor is None else ell_factor
+    lmax = float(np.max(np.abs(np.linalg.eigvalsh(Kii)))) if Kii.size else 0.0
+    return ell * np.finfo(np.float64).eps * 0.5 * lmax
+
+
+def nystrom(K_cols, I):
+    """(U, Lambda^) from the m x ell block K[:, I] and the landmark indices."""
+    m, ell = K_cols.shape
+    Kii = K_cols[I, :]
+    Kii = 0.5 * (Kii + Kii.T)
+    lam_q, Q = np.linalg.eigh(Kii)
+    keep = lam_q > positive_threshold(Kii)
+    lam_q, Q = lam_q[keep], Q[:, keep]
+    C = np.setdiff1d(np.arange(m), I)
+    Ut = np.zeros((m, Q.shape[1]))
+    Ut[I, :] = Q
+    Ut[C, :] = K_cols[C, :] @ Q / lam_q
+    M = Ut * np.sqrt(lam_q)
+    V, S, _ = np.linalg.svd(M, full_matrices=False)
+    return V, S ** 2
+
+
+def precond_apply(U, lam_hat, lam, x):
+    """P^{-1} x for the spectral preconditioner."""
+    ux = U.T @ x
+    return U @ (ux / (lam_hat + lam)) + (x - U @ ux) / lam
+
+
+def pcg(apply_A, b, apply_Pinv, tol, maxit):
+    """Preconditioned CG (appendix algorithm) from y = 0. Stops on
+    <p, Ap> <= 0, ||r|| <= tol ||b||, rho <= 0 or non-finite values.
+    Returns (y, iterations, converged, residual history)."""
+    y = np.zeros_like(b)
+    r = b.copy()
+    z = apply_Pinv(r)
+    p = z.copy()
+    rho = float(r @ z)
+    nb = float(np.linalg.norm(b))
+    hist = [float(np.linalg.norm(r))]
+    if hist[0] <= tol * nb:
+        return y, 0, True, hist
+    for j in range(maxit):
+        Ap = apply_A(p)
+        pAp = float(p @ Ap)
+        if not (pAp > 0.0) or not np.isfinite(pAp):
+            return y, j, False, hist
+        a = rho / pAp
+        y = y + a * p
+        r = r - a * Ap
+        hist.append(float(np.linalg.norm(r)))
+        if hist[-1] <= tol * nb:
+            return y, j + 1, True, hist
+        z = apply_Pinv(r)
+        rho_new = float(r @ z)
+        if not (rho > 0.0) or not np.isfinite(rho_new):
+            return y, j + 1, False, hist
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    return y, maxit, False, hist
+
+
+def pcg_step(J, r, lam, I, tol, maxit):
+    """Matrix-free PCG step: kvp(p) = J (J^T p) + lam p (Definition 3.6),
+    Nystrom preconditioner from landmarks I. Returns (dtheta, alpha, its, ok)."""
+    K_cols = J @ J[I, :].T
+    U, lh = nystrom(K_cols, I)
+
+    def kvp(p):
+        return J @ (J.T @ p) + lam * p
+
+    alpha, its, ok, _ = pcg(kvp, r, lambda x: precond_apply(U, lh, lam, x), tol, maxit)
+    return -(J.T @ alpha), alpha, its, ok
