@@ -1,0 +1,197 @@
+/*
+ * dngd.h -- C ABI of libdngd, an MI355X (gfx950) implementation of the
+ * Dual Natural Gradient Descent step for physics-informed tanh MLPs
+ * (Jnini & Vella, "Dual Natural Gradient Descent for Scalable Training of
+ * Physics-Informed Neural Networks").
+ *
+ * Conventions for every entry point
+ *   - Return value: a dngd_status. Nothing throws across this boundary.
+ *     dngd_last_error() gives a message for the last failing call on the
+ *     calling thread.
+ *   - Pointers documented "device" must point to memory on the current HIP
+ *     device; "host" pointers to ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the legacy
+ *     default stream. Work is enqueued on it; unless a call is documented
+ *     as synchronising, it returns before the work finishes.
+ *   - The caller owns every buffer it passes in. A dngd_problem owns the
+ *     workspace it allocates and frees it in dngd_problem_destroy. Stateless
+ *     calls (dngd_gram, dngd_cholesky_solve) take their scratch from the
+ *     stream-ordered allocator of the stream's device and release it before
+ *     returning.
+ *   - A dngd_problem is not thread-safe; use one per job and one stream per
+ *     problem at a time.
+ *
+ * Parameter layout (theta, dtheta, gradients): per affine layer l = 1..L,
+ * W_l row-major [out][in], then b_l[out]; n = sum_l (w_l * w_{l-1} + w_l).
+ * Residual layout: interior points, then boundary points, then initial
+ * points; m = n_int + n_bdy + n_init (one scalar residual per point).
+ */
+#ifndef DNGD_H
+#define DNGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DNGD_OK = 0,
+  DNGD_ENOCONV = 1,   /* warning: PCG stopped at maxit or on breakdown; x holds the last iterate */
+  DNGD_EINVAL = -1,   /* bad argument; nothing was enqueued */
+  DNGD_ENOMEM = -2,   /* device allocation failed */
+  DNGD_EHIP = -3,     /* a HIP runtime call failed */
+  DNGD_ENOTPD = -4,   /* Cholesky met a non-positive pivot; info = 1-based column */
+  DNGD_ENAN = -5,     /* a non-finite value in the result */
+  DNGD_ETIMEOUT = -6  /* a kernel's bounded inter-workgroup wait expired; results invalid */
+} dngd_status;
+
+typedef enum { DNGD_F64 = 0, DNGD_F32 = 1 } dngd_dtype;
+typedef enum { DNGD_POISSON = 0, DNGD_HEAT = 1 } dngd_pde;
+typedef enum { DNGD_PLAIN = 0, DNGD_MIXED = 1 } dngd_precision;
+typedef enum { DNGD_DENSE = 0, DNGD_PCG = 1 } dngd_solver;
+
+/* Problem statement (Section 2.1 and 2.2 of the paper: the PINN loss and the
+ * residual map).  Residuals:
+ *   interior  r_i = N_int^{-1/2} (L u(x_i) - f_i),
+ *             L u = -lap u (Poisson) or u_t - kappa lap_xy u (heat),
+ *   boundary  r_j = N_bdy^{-1/2} (u(x_j) - g_j),
+ *   initial   r_k = N_init^{-1/2} (u(x_k) - g_k)   (heat only).
+ * u is a tanh MLP with widths[0] = d_in inputs and widths[L] = 1 output.
+ * Heat inputs are ordered (x_1..x_{d_in-1}, t); the Laplacian sums over the
+ * spatial coordinates. The point arrays are copied at creation. */
+typedef struct {
+  int32_t pde;            /* dngd_pde */
+  int32_t n_layers;       /* L >= 1 affine layers */
+  const int32_t* widths;  /* host, L+1 entries; 1 <= widths[0] <= 8, widths[L] == 1,
+                             hidden widths in [1, 4096] */
+  double kappa;           /* heat diffusivity (ignored for Poisson) */
+  int64_t n_int, n_bdy, n_init;  /* n_init must be 0 for Poisson */
+  const double* x_int;    /* device, n_int  x d_in, row-major */
+  const double* x_bdy;    /* device, n_bdy  x d_in */
+  const double* x_init;   /* device, n_init x d_in (may be NULL if n_init == 0) */
+  const double* f_int;    /* device, n_int  interior source f */
+  const double* g_bdy;    /* device, n_bdy  boundary value g */
+  const double* g_init;   /* device, n_init initial value */
+} dngd_problem_desc;
+
+typedef struct dngd_problem dngd_problem;
+
+/* Options of one D-NGD step. dngd_step_opts_default() fills the defaults. */
+typedef struct {
+  int32_t precision;    /* DNGD_PLAIN: FP64 J, FP64-MFMA Gram.
+                           DNGD_MIXED: FP32 J, BF16-MFMA Gram with FP32
+                           accumulation, FP64 Cholesky and refinement. */
+  int32_t solver;       /* DNGD_DENSE (Cholesky) or DNGD_PCG (Nystrom-PCG) */
+  int32_t ga;           /* 1: geodesic acceleration (Section 3.2), 0: off */
+  int32_t ir_sweeps;    /* mixed dense: iterative-refinement sweeps per solve (default 2) */
+  int32_t gram_passes;  /* mixed: 1 (bf16 x bf16), 3 (split hi/lo bf16), 0 = pick from
+                           max_i ||J_i||^2 / lambda (default 0) */
+  int32_t reserved0;
+  double eps_norm;      /* GA guard: GA only if ||v|| > eps_norm (default 0) */
+  /* PCG (solver == DNGD_PCG) */
+  int64_t n_landmarks;      /* l: number of landmark residuals (<= m) */
+  const int64_t* landmarks; /* device, l sorted distinct residual indices in [0, m) */
+  double pcg_tol;           /* stop at ||b - A y|| <= tol ||b|| (recursive residual) */
+  int64_t pcg_maxit;
+} dngd_step_opts;
+
+typedef struct {
+  double ms_total, ms_residual_jacobian, ms_gram, ms_factor, ms_solve_v, ms_fvv, ms_solve_a;
+  double vnorm, anorm;        /* ||v||_2, ||a||_2 */
+  int32_t ga_accepted;        /* 1 if dtheta = v + a/2 */
+  int32_t gram_passes_used;
+  int32_t pcg_iterations;
+  int32_t pcg_converged;
+  double ir_residual[8];      /* mixed: ||s_k|| / ||b|| before sweep k (k < ir_sweeps), v solve */
+  double max_row_norm2;       /* max_i ||J_i||^2 (mixed path) */
+  double pcg_rel_residual;    /* PCG: final recursive ||r|| / ||b|| */
+} dngd_step_stats;
+
+const char* dngd_last_error(void);
+const char* dngd_version(void);
+
+void dngd_step_opts_default(dngd_step_opts* opts);
+
+/* Create a problem handle: validates the description and copies the point
+ * and target arrays to device memory owned by the handle. */
+int dngd_problem_create(const dngd_problem_desc* desc, dngd_problem** out);
+int dngd_problem_destroy(dngd_problem* h);
+
+int64_t dngd_num_params(const dngd_problem* h);     /* n */
+int64_t dngd_num_residuals(const dngd_problem* h);  /* m */
+int64_t dngd_jacobian_ld(const dngd_problem* h);    /* recommended ldJ: n rounded up to 256 */
+
+/* Bytes of device memory dngd_step with `opts` needs beyond the caller's
+ * buffers (activations, J, K and scratch); used for admission control.
+ * Host-only, does not allocate. */
+int dngd_footprint(const dngd_problem* h, const dngd_step_opts* opts, size_t* bytes);
+
+/* Residual map and Jacobian (Section 2.2: r(theta) and J = dr/dtheta).
+ * theta: device, n FP64.  r: device, m FP64 (may be NULL).
+ * J: device, m rows of ldJ elements, row-major, row i = dr_i/dtheta in the
+ * parameter layout; j_dtype DNGD_F64 or DNGD_F32; may be NULL (residual
+ * only); columns n..ldJ-1 are written as zero. ldJ >= n, ldJ % 4 == 0. */
+int dngd_residual_jacobian(dngd_problem* h, const double* theta, double* r, void* J,
+                           int64_t ldJ, int32_t j_dtype, void* stream);
+
+/* Residual Gramian (Definition 3.3) plus damping: K = J J^T + lambda I.
+ * J: device, m x ldJ row-major, j_dtype DNGD_F64 (FP64 MFMA) or DNGD_F32
+ * (BF16 MFMA with FP32 accumulation; passes = 1 rounds J to bf16, passes = 3
+ * uses the split J = hi + lo and adds hi hi^T + hi lo^T + lo hi^T).
+ * Split-K partial sums are added in FP64 in a fixed order, so the result is
+ * deterministic. K: device, m x ldK FP64, lower triangle (i >= j) written,
+ * strict upper triangle untouched. ldK >= m. */
+int dngd_gram(int64_t m, int64_t n, const void* J, int64_t ldJ, int32_t j_dtype, int32_t passes,
+              double lambda, double* K, int64_t ldK, void* stream);
+
+/* Dense dual solve (Section 4.1): Cholesky K = L L^T and B <- K^{-1} B.
+ * K: device, m x ldK FP64; if factored == 0 the lower triangle holds the SPD
+ * matrix on entry and L on exit; if factored == 1 it already holds L.
+ * B: device, m x nrhs, column j at B + j*ldB (ldB >= m); overwritten by the
+ * solution. info: host, set to 0 on success or to the 1-based column of the
+ * first non-positive pivot (then DNGD_ENOTPD is returned and B is invalid).
+ * Synchronises `stream` when factoring (to read info). */
+int dngd_cholesky_solve(int64_t m, double* K, int64_t ldK, int32_t factored, int64_t nrhs,
+                        double* B, int64_t ldB, int64_t* info, void* stream);
+
+/* Second directional derivative of the residual along v (Section 3.2):
+ * fvv = d^2/dt^2 r(theta + t v) at t = 0. theta, v: device n FP64;
+ * fvv: device m FP64. */
+int dngd_fvv(dngd_problem* h, const double* theta, const double* v, double* fvv, void* stream);
+
+/* Matrix-free Jacobian products (the two passes of the kernel-vector product,
+ * Definition 3.6): w = J u (forward mode) and g = J^T p (reverse mode).
+ * u, g: device n FP64; w, p: device m FP64. Neither J nor K is formed. */
+int dngd_jvp(dngd_problem* h, const double* theta, const double* u, double* w, void* stream);
+int dngd_vjp(dngd_problem* h, const double* theta, const double* p, double* g, void* stream);
+
+/* Line-search losses (D-NGD workflow): losses[k] = 0.5 ||r(theta + eta_k dtheta)||^2.
+ * etas, losses: host arrays of n_eta. Synchronises `stream`. */
+int dngd_losses(dngd_problem* h, const double* theta, const double* dtheta, int32_t n_eta,
+                const double* etas, double* losses, void* stream);
+
+/* Nystrom-preconditioned CG on the dual system (Sections 3.3, 4.2):
+ * solves (J J^T + lambda I) x = b with the matrix-free kernel-vector product
+ * and the spectral preconditioner built from the landmark residuals
+ * `landmarks` (device, ell sorted distinct indices). b, x: device m FP64
+ * (x is overwritten; the iteration starts from 0). stats may be NULL.
+ * Returns DNGD_OK when ||b - A x|| <= tol ||b|| (recursive residual),
+ * DNGD_ENOCONV after maxit iterations or a breakdown. Synchronises `stream`. */
+int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda,
+                     const int64_t* landmarks, int64_t ell, double tol, int64_t maxit,
+                     const double* b, double* x, dngd_step_stats* stats, void* stream);
+
+/* One D-NGD step (dense dual solver with geodesic acceleration, Section 4.1,
+ * or the PCG step of Section 4.2): dtheta = -J^T (J J^T + lambda I)^{-1} r,
+ * plus a/2 with a = -J^T (J J^T + lambda I)^{-1} f_vv when accepted
+ * (2 ||a|| <= 0.5 ||v||). theta, dtheta: device n FP64. stats: host or NULL.
+ * Synchronises `stream` before returning. */
+int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_step_opts* opts,
+              double* dtheta, dngd_step_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DNGD_H */

@@ -1,0 +1,1088 @@
+// C ABI of libdngd (declared in include/dngd.h): problem handles, workspace
+// management and the D-NGD step pipelines built from the kernels in this
+// directory.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "../../include/dngd.h"
+#include "common.h"
+
+namespace dngd {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  set_error("%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  return (e == hipErrorOutOfMemory) ? DNGD_ENOMEM : DNGD_EHIP;
+}
+
+}  // namespace dngd
+
+using namespace dngd;
+
+// ---------------------------------------------------------------------------
+// problem handle
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct dngd_problem {
+  Geometry g;
+  RowMap rm;
+  int device = 0;
+  std::vector<void*> owned;  // freed at destroy
+  double *x_int = nullptr, *x_bdy = nullptr, *x_init = nullptr;
+  double *f_int = nullptr, *g_bdy = nullptr, *g_init = nullptr;
+  // forward activations (hidden layers h = 0..L-2)
+  double* A0 = nullptr;
+  double* Z[kMaxLayers] = {nullptr};
+  double* A[kMaxLayers] = {nullptr};
+  double* Zb[kMaxLayers] = {nullptr};
+  double* Ab[2] = {nullptr, nullptr};
+  double* seed = nullptr;
+  double* U = nullptr;
+  // tangent streams (lazy)
+  double *Z1 = nullptr, *Z2 = nullptr, *A1[2] = {nullptr, nullptr}, *A2[2] = {nullptr, nullptr};
+  // step / solver workspace (lazy, grown on demand)
+  DevBuf J, K, vecs, work, gram_work, flags_buf, small;
+  int J_dtype = -1;
+  int64_t ldJ = 0, ldK = 0;
+  unsigned epoch = 0;
+  hipEvent_t ev[8] = {nullptr};
+};
+
+namespace {
+
+int64_t act_bytes(const Geometry& g) { return g.R * (int64_t)g.max_width * (int64_t)sizeof(double); }
+
+int dmalloc(dngd_problem* h, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(e, "hipMalloc", __FILE__, __LINE__);
+  }
+  h->owned.push_back(*p);
+  return 0;
+}
+
+int ensure(dngd_problem* h, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return 0;
+  if (b.p) {
+    for (auto& q : h->owned)
+      if (q == b.p) q = nullptr;
+    DNGD_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  int rc = dmalloc(h, &b.p, bytes);
+  if (rc) return rc;
+  b.bytes = bytes;
+  return 0;
+}
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+const double* Wp(const dngd_problem* h, const double* th, int l) { return th + h->g.w_off[l]; }
+const double* Bp(const dngd_problem* h, const double* th, int l) { return th + h->g.b_off[l]; }
+
+// activation input of affine layer l
+const double* act_in(const dngd_problem* h, int l) { return l == 0 ? h->A0 : h->A[l - 1]; }
+
+// Forward pass on jets: activations of all hidden layers, output rows U, residual r.
+int forward(dngd_problem* h, const double* theta, double* r, hipStream_t s) {
+  const Geometry& g = h->g;
+  int rc = net_input_layer(s, h->rm, h->x_int, h->x_bdy, h->x_init, h->A0, g.d_in);
+  if (rc) return rc;
+  for (int l = 0; l < g.L - 1; ++l) {
+    const int win = g.widths[l], wout = g.widths[l + 1];
+    rc = gemm_f64(s, GEMM_FULL, true, true, g.R, wout, win, 1.0, act_in(h, l), win, Wp(h, theta, l),
+                  win, 0.0, h->Z[l], wout);
+    if (rc) return rc;
+    rc = net_bias_act(s, h->rm, wout, Bp(h, theta, l), h->Z[l], h->A[l]);
+    if (rc) return rc;
+  }
+  const int l = g.L - 1;
+  rc = net_rowdot(s, g.R, g.widths[l], act_in(h, l), Wp(h, theta, l), 0.0, nullptr, nullptr, h->U);
+  if (rc) return rc;
+  if (r) rc = net_residual(s, h->rm, h->U, Bp(h, theta, l), h->f_int, h->g_bdy, h->g_init, r);
+  return rc;
+}
+
+// Backward pass from per-residual weights p (null = Jacobian seeds): fills
+// seed and Zb[h] (adjoints of every hidden pre-activation).
+int backward(dngd_problem* h, const double* theta, const double* p, hipStream_t s) {
+  const Geometry& g = h->g;
+  int rc = net_seeds(s, h->rm, p, h->seed);
+  if (rc) return rc;
+  if (g.L == 1) return 0;
+  int cur = 0;
+  rc = net_outer_seed(s, g.R, g.widths[g.L - 1], h->seed, Wp(h, theta, g.L - 1), h->Ab[cur]);
+  if (rc) return rc;
+  for (int hl = g.L - 2; hl >= 0; --hl) {
+    const int w = g.widths[hl + 1];
+    rc = net_act_adjoint(s, h->rm, w, h->Z[hl], h->Ab[cur], h->Zb[hl]);
+    if (rc) return rc;
+    if (hl > 0) {
+      const int win = g.widths[hl];
+      // Abar_{hl-1} = Zb[hl] W_hl : (R x w) (w x win)
+      rc = gemm_f64(s, GEMM_FULL, true, false, g.R, win, w, 1.0, h->Zb[hl], w, Wp(h, theta, hl),
+                    win, 0.0, h->Ab[cur ^ 1], win);
+      if (rc) return rc;
+      cur ^= 1;
+    }
+  }
+  return 0;
+}
+
+int write_jacobian(dngd_problem* h, void* J, int64_t ldJ, int j_dtype, double* rownorm2,
+                   hipStream_t s, const int64_t* pidx = nullptr, int64_t nrows = 0) {
+  const Geometry& g = h->g;
+  const double* A[kMaxLayers];
+  const double* Zb[kMaxLayers];
+  for (int l = 0; l < g.L; ++l) {
+    A[l] = act_in(h, l);
+    Zb[l] = (l < g.L - 1) ? h->Zb[l] : h->seed;
+  }
+  return net_jacobian_rows(s, g, h->rm, A, Zb, h->seed, J, ldJ, j_dtype, rownorm2, pidx, nrows);
+}
+
+int ensure_tangent(dngd_problem* h) {
+  if (h->Z1) return 0;
+  const size_t b = act_bytes(h->g);
+  int rc = 0;
+  rc |= dmalloc(h, (void**)&h->Z1, b);
+  rc |= dmalloc(h, (void**)&h->Z2, b);
+  rc |= dmalloc(h, (void**)&h->A1[0], b);
+  rc |= dmalloc(h, (void**)&h->A1[1], b);
+  rc |= dmalloc(h, (void**)&h->A2[0], b);
+  rc |= dmalloc(h, (void**)&h->A2[1], b);
+  return rc ? DNGD_ENOMEM : 0;
+}
+
+// Forward t-tangent streams along direction dir (requires forward() at theta).
+// order 1: out = J dir.  order 2: out = d^2/dt^2 r(theta + t dir).
+int tangent(dngd_problem* h, const double* theta, const double* dir, int order, double* out,
+            hipStream_t s) {
+  const Geometry& g = h->g;
+  int rc = ensure_tangent(h);
+  if (rc) return rc;
+  int cur = 0;
+  const double* a1p = nullptr;  // tangent activations of the previous layer (null = 0)
+  const double* a2p = nullptr;
+  for (int l = 0; l < g.L - 1; ++l) {
+    const int win = g.widths[l], wout = g.widths[l + 1];
+    const double* a0 = act_in(h, l);
+    // Z1 = a1 W^T + a0 V^T
+    rc = gemm_f64(s, GEMM_FULL, true, true, g.R, wout, win, 1.0, a0, win, Wp(h, dir, l), win, 0.0,
+                  h->Z1, wout);
+    if (rc) return rc;
+    if (a1p) {
+      rc = gemm_f64(s, GEMM_FULL, true, true, g.R, wout, win, 1.0, a1p, win, Wp(h, theta, l), win,
+                    1.0, h->Z1, wout);
+      if (rc) return rc;
+    }
+    if (order >= 2) {
+      // Z2 = a2 W^T + 2 a1 V^T
+      if (a1p) {
+        rc = gemm_f64(s, GEMM_FULL, true, true, g.R, wout, win, 1.0, a2p, win, Wp(h, theta, l),
+                      win, 0.0, h->Z2, wout);
+        if (rc) return rc;
+        rc = gemm_f64(s, GEMM_FULL, true, true, g.R, wout, win, 2.0, a1p, win, Wp(h, dir, l), win,
+                      1.0, h->Z2, wout);
+        if (rc) return rc;
+      } else {
+        rc = fill(s, g.R * wout, 0.0, h->Z2);
+        if (rc) return rc;
+      }
+    }
+    rc = net_tangent_act(s, h->rm, wout, Bp(h, dir, l), h->Z[l], h->Z1, h->Z2, h->A1[cur],
+                         h->A2[cur], order);
+    if (rc) return rc;
+    a1p = h->A1[cur];
+    a2p = h->A2[cur];
+    cur ^= 1;
+  }
+  const int l = g.L - 1;
+  const int win = g.widths[l];
+  if (order == 1) {
+    // u1 = a1 W^T + a0 V^T (+ c on the value channel)
+    rc = net_rowdot(s, g.R, win, act_in(h, l), Wp(h, dir, l), a1p ? 1.0 : 0.0, a1p,
+                    Wp(h, theta, l), h->U);
+    if (rc) return rc;
+    return net_linear_residual(s, h->rm, h->U, Bp(h, dir, l), out);
+  }
+  if (!a1p) {  // a single affine layer: r is affine in theta
+    return fill(s, g.m, 0.0, out);
+  }
+  // u2 = a2 W^T + 2 a1 V^T (no bias term)
+  rc = net_rowdot(s, g.R, win, a2p, Wp(h, theta, l), 2.0, a1p, Wp(h, dir, l), h->U);
+  if (rc) return rc;
+  return net_linear_residual(s, h->rm, h->U, nullptr, out);
+}
+
+// theta-bar = J^T p, matrix-free (requires forward() at theta).
+int vjp(dngd_problem* h, const double* theta, const double* p, double* gout, hipStream_t s) {
+  const Geometry& g = h->g;
+  int rc = backward(h, theta, p, s);
+  if (rc) return rc;
+  // workspace for the split-K weight-gradient GEMMs and the bias column sums
+  const int64_t tiles = cdiv(g.max_width, 64) * cdiv(g.max_width, 64);
+  int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, cdiv(512, tiles)));
+  splits = (int)std::min<int64_t>(splits, std::max<int64_t>(1, g.R / 256));
+  const size_t wbytes = std::max<size_t>((size_t)splits * tiles * 64 * 64 * sizeof(double),
+                                         (size_t)64 * kMaxWidth * sizeof(double));
+  rc = ensure(h, h->work, wbytes);
+  if (rc) return rc;
+  double* work = static_cast<double*>(h->work.p);
+  for (int l = 0; l < g.L; ++l) {
+    const int win = g.widths[l], wout = g.widths[l + 1];
+    const double* zb = (l < g.L - 1) ? h->Zb[l] : h->seed;
+    // W-bar_l = Zb_l^T A_in(l): (wout x R)(R x win)
+    rc = gemm_f64(s, GEMM_FULL, false, false, wout, win, g.R, 1.0, zb, wout, act_in(h, l), win,
+                  0.0, gout + g.w_off[l], win, work, splits);
+    if (rc) return rc;
+    rc = net_colsum_value_rows(s, h->rm, wout, zb, gout + g.b_off[l], work);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// step workspace: vectors of m and n doubles plus reduction scratch
+
+struct StepVecs {
+  double *r, *alpha, *s, *fvv, *beta, *tmpm, *rownorm2;  // m each
+  double *v, *a, *t, *thtmp;                              // n each
+  double* red;   // reduction scratch (256 doubles)
+  double* scal;  // 64 device scalars
+  double* gemv_work;
+};
+
+size_t step_vec_bytes(const Geometry& g) {
+  // gemv_t scratch: J^T x (m rows, n columns) and the preconditioner's M x
+  // (at most 64 row bands of m columns)
+  const size_t gw = std::max(gemv_t_workspace_bytes(std::max<int64_t>(g.m, 1), std::max<int64_t>(g.n, 1)),
+                             (size_t)64 * (size_t)std::max<int64_t>(g.m, 1) * sizeof(double));
+  return (size_t)(7 * g.m + 4 * g.n + 64) * sizeof(double) + kReduceWorkBytes + gw;
+}
+
+int carve_vecs(dngd_problem* h, StepVecs& v) {
+  const Geometry& g = h->g;
+  int rc = ensure(h, h->vecs, step_vec_bytes(g));
+  if (rc) return rc;
+  double* p = static_cast<double*>(h->vecs.p);
+  auto take = [&](int64_t k) {
+    double* q = p;
+    p += k;
+    return q;
+  };
+  v.r = take(g.m);
+  v.alpha = take(g.m);
+  v.s = take(g.m);
+  v.fvv = take(g.m);
+  v.beta = take(g.m);
+  v.tmpm = take(g.m);
+  v.rownorm2 = take(g.m);
+  v.v = take(g.n);
+  v.a = take(g.n);
+  v.t = take(g.n);
+  v.thtmp = take(g.n);
+  v.scal = take(64);
+  v.red = take(256);
+  v.gemv_work = p;
+  return 0;
+}
+
+// small device block: solve flags, status, info
+struct Small {
+  unsigned* flags;
+  int* status;
+  int64_t* info;
+  int* ga_flag;
+};
+
+int carve_small(dngd_problem* h, int64_t mmax, Small& sm) {
+  const size_t nflags = (size_t)chol_solve_flag_count(std::max<int64_t>(mmax, 1));
+  const size_t bytes = nflags * sizeof(unsigned) + 64;
+  if (h->small.bytes < bytes) {
+    int rc = ensure(h, h->small, bytes);
+    if (rc) return rc;
+    DNGD_HIP(hipMemset(h->small.p, 0, bytes));  // flags start at epoch 0
+    h->epoch = 0;
+  }
+  char* p = static_cast<char*>(h->small.p);
+  sm.status = reinterpret_cast<int*>(p);
+  sm.ga_flag = reinterpret_cast<int*>(p + 8);
+  sm.info = reinterpret_cast<int64_t*>(p + 16);
+  sm.flags = reinterpret_cast<unsigned*>(p + 64);
+  return 0;
+}
+
+__global__ void zero_i32_kernel(int* p) { *p = 0; }
+
+int dense_solve(dngd_problem* h, const StepVecs& v, const Small& sm, const double* rhs, double* x,
+                double lambda, int ir_sweeps, const void* J, int j_dtype, double* ir_out,
+                hipStream_t s) {
+  const Geometry& g = h->g;
+  double* K = static_cast<double*>(h->K.p);
+  int rc = copy(s, g.m, rhs, x);
+  if (rc) return rc;
+  rc = chol_solve(s, g.m, K, h->ldK, x, sm.flags, &h->epoch, sm.status, nullptr);
+  if (rc) return rc;
+  for (int k = 0; k < ir_sweeps; ++k) {
+    // s = rhs - (J (J^T x) + lambda x), computed with FP32/FP64 J and FP64 accumulation
+    rc = gemv_t(s, g.m, g.n, J, h->ldJ, j_dtype, x, 1.0, v.t, v.gemv_work);
+    if (rc) return rc;
+    rc = gemv_n_residual(s, g.m, g.n, J, h->ldJ, j_dtype, v.t, rhs, x, lambda, v.s);
+    if (rc) return rc;
+    if (ir_out && k < 8) {
+      rc = sumsq(s, g.m, v.s, ir_out + k, v.red);
+      if (rc) return rc;
+    }
+    rc = chol_solve(s, g.m, K, h->ldK, v.s, sm.flags, &h->epoch, sm.status, nullptr);
+    if (rc) return rc;
+    rc = axpy(s, g.m, 1.0, v.s, x);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+// Nystrom preconditioner in Woodbury form (see dngd_nystrom_pcg)
+struct Precond {
+  double* Mt = nullptr;  // ell x m   (L_I^{-1} K_{I,:})
+  double* G = nullptr;   // ell x ell (lambda I + Mt Mt^T, Cholesky factor)
+  double* tl = nullptr;  // ell scratch vector
+  int64_t ldM = 0;
+  double delta = 0;
+  int64_t ell = 0;
+  double lambda = 0;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char* dngd_last_error(void) { return g_err; }
+const char* dngd_version(void) { return "libdngd 0.1 (gfx950)"; }
+
+void dngd_step_opts_default(dngd_step_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = DNGD_MIXED;
+  o->solver = DNGD_DENSE;
+  o->ga = 1;
+  o->ir_sweeps = 2;
+  o->gram_passes = 0;
+  o->eps_norm = 0.0;
+  o->pcg_tol = 1e-6;
+  o->pcg_maxit = 500;
+}
+
+int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
+  DNGD_REQUIRE(d && out, "dngd_problem_create: null argument");
+  *out = nullptr;
+  DNGD_REQUIRE(d->pde == DNGD_POISSON || d->pde == DNGD_HEAT, "unknown pde %d", d->pde);
+  DNGD_REQUIRE(d->n_layers >= 1 && d->n_layers <= kMaxLayers, "n_layers out of range");
+  DNGD_REQUIRE(d->widths != nullptr, "widths is null");
+  DNGD_REQUIRE(d->widths[0] >= 1 && d->widths[0] <= kMaxDin, "d_in must be in [1, %d]", kMaxDin);
+  DNGD_REQUIRE(d->widths[d->n_layers] == 1, "the network must have one output");
+  for (int l = 1; l < d->n_layers; ++l)
+    DNGD_REQUIRE(d->widths[l] >= 1 && d->widths[l] <= kMaxWidth, "hidden width out of range");
+  DNGD_REQUIRE(d->n_int >= 0 && d->n_bdy >= 0 && d->n_init >= 0, "negative point count");
+  DNGD_REQUIRE(d->n_int + d->n_bdy + d->n_init > 0, "no points");
+  DNGD_REQUIRE(d->pde == DNGD_HEAT || d->n_init == 0, "initial points need the heat equation");
+  DNGD_REQUIRE(d->pde == DNGD_POISSON || d->widths[0] >= 2, "heat needs d_in >= 2");
+  DNGD_REQUIRE((d->n_int == 0 || (d->x_int && d->f_int)) && (d->n_bdy == 0 || (d->x_bdy && d->g_bdy)) &&
+                   (d->n_init == 0 || (d->x_init && d->g_init)),
+               "null point or target array");
+  DNGD_REQUIRE(std::isfinite(d->kappa), "kappa not finite");
+
+  dngd_problem* h = new dngd_problem();
+  Geometry& g = h->g;
+  g.pde = d->pde;
+  g.L = d->n_layers;
+  int64_t off = 0;
+  g.max_width = 1;
+  for (int l = 0; l <= g.L; ++l) g.widths[l] = d->widths[l];
+  for (int l = 0; l < g.L; ++l) {
+    g.w_off[l] = off;
+    off += (int64_t)g.widths[l] * g.widths[l + 1];
+    g.b_off[l] = off;
+    off += g.widths[l + 1];
+    if (l < g.L - 1) g.max_width = std::max(g.max_width, g.widths[l + 1]);
+  }
+  g.n = off;
+  g.n_int = d->n_int;
+  g.n_bdy = d->n_bdy;
+  g.n_init = d->n_init;
+  g.m = d->n_int + d->n_bdy + d->n_init;
+  g.d_in = d->widths[0];
+  g.nlap = (g.pde == DNGD_HEAT) ? g.d_in - 1 : g.d_in;
+  g.C_int = g.d_in + 2;
+  g.R_int = g.n_int * g.C_int;
+  g.R = g.R_int + g.n_bdy + g.n_init;
+  g.kappa = d->kappa;
+  g.c_int = g.n_int ? 1.0 / std::sqrt((double)g.n_int) : 0.0;
+  g.c_bdy = g.n_bdy ? 1.0 / std::sqrt((double)g.n_bdy) : 0.0;
+  g.c_init = g.n_init ? 1.0 / std::sqrt((double)g.n_init) : 0.0;
+  h->rm = row_map(g);
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+
+  int rc = 0;
+  auto dup = [&](double** dst, const double* src, int64_t cnt) {
+    if (rc) return;
+    rc = dmalloc(h, (void**)dst, (size_t)std::max<int64_t>(cnt, 1) * sizeof(double));
+    if (!rc && cnt > 0) {
+      hipError_t e = hipMemcpy(*dst, src, (size_t)cnt * sizeof(double), hipMemcpyDefault);
+      if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy", __FILE__, __LINE__);
+    }
+  };
+  dup(&h->x_int, d->x_int, g.n_int * g.d_in);
+  dup(&h->x_bdy, d->x_bdy, g.n_bdy * g.d_in);
+  dup(&h->x_init, d->x_init, g.n_init * g.d_in);
+  dup(&h->f_int, d->f_int, g.n_int);
+  dup(&h->g_bdy, d->g_bdy, g.n_bdy);
+  dup(&h->g_init, d->g_init, g.n_init);
+  if (!rc) rc = dmalloc(h, (void**)&h->A0, (size_t)g.R * g.d_in * sizeof(double));
+  for (int l = 0; l < g.L - 1 && !rc; ++l) {
+    const size_t b = (size_t)g.R * g.widths[l + 1] * sizeof(double);
+    rc |= dmalloc(h, (void**)&h->Z[l], b);
+    if (!rc) rc = dmalloc(h, (void**)&h->A[l], b);
+    if (!rc) rc = dmalloc(h, (void**)&h->Zb[l], b);
+  }
+  if (!rc) rc = dmalloc(h, (void**)&h->Ab[0], act_bytes(g));
+  if (!rc) rc = dmalloc(h, (void**)&h->Ab[1], act_bytes(g));
+  if (!rc) rc = dmalloc(h, (void**)&h->seed, (size_t)g.R * sizeof(double));
+  if (!rc) rc = dmalloc(h, (void**)&h->U, (size_t)g.R * sizeof(double));
+  for (int e = 0; e < 8 && !rc; ++e)
+    if (hipEventCreate(&h->ev[e]) != hipSuccess) rc = DNGD_EHIP;
+  if (rc) {
+    dngd_problem_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return DNGD_OK;
+}
+
+int dngd_problem_destroy(dngd_problem* h) {
+  if (!h) return DNGD_OK;
+  hipDeviceSynchronize();
+  for (void* p : h->owned)
+    if (p) hipFree(p);
+  for (auto& e : h->ev)
+    if (e) hipEventDestroy(e);
+  delete h;
+  return DNGD_OK;
+}
+
+int64_t dngd_num_params(const dngd_problem* h) { return h ? h->g.n : -1; }
+int64_t dngd_num_residuals(const dngd_problem* h) { return h ? h->g.m : -1; }
+int64_t dngd_jacobian_ld(const dngd_problem* h) { return h ? round_up(h->g.n, 256) : -1; }
+
+int dngd_footprint(const dngd_problem* h, const dngd_step_opts* o, size_t* bytes) {
+  DNGD_REQUIRE(h && bytes, "dngd_footprint: null argument");
+  dngd_step_opts def;
+  dngd_step_opts_default(&def);
+  if (!o) o = &def;
+  const Geometry& g = h->g;
+  size_t b = 0;
+  b += (size_t)g.R * g.d_in * 8 + 2 * (size_t)act_bytes(g) + 2 * (size_t)g.R * 8;
+  for (int l = 0; l < g.L - 1; ++l) b += 3 * (size_t)g.R * g.widths[l + 1] * 8;
+  if (o->ga || o->solver == DNGD_PCG) b += 6 * (size_t)act_bytes(g);
+  b += step_vec_bytes(g);
+  if (o->solver == DNGD_DENSE) {
+    const int jd = (o->precision == DNGD_PLAIN) ? DNGD_F64 : DNGD_F32;
+    const int64_t ldJ = round_up(g.n, 256);
+    b += (size_t)g.m * ldJ * (jd == DNGD_F64 ? 8 : 4);
+    b += (size_t)g.m * g.m * 8;
+    b += gram_workspace_bytes(g.m, g.n, jd, 3, nullptr);
+  } else {
+    const int64_t ell = o->n_landmarks;
+    const int64_t ldJ = round_up(g.n, 256);
+    b += (size_t)ell * ldJ * 8 + (size_t)ell * g.m * 8 + (size_t)ell * ell * 8;
+    b += (size_t)std::min<int64_t>(g.m, 256) * ldJ * 8;
+  }
+  *bytes = b;
+  return DNGD_OK;
+}
+
+int dngd_residual_jacobian(dngd_problem* h, const double* theta, double* r, void* J, int64_t ldJ,
+                           int32_t j_dtype, void* stream) {
+  DNGD_REQUIRE(h && theta, "dngd_residual_jacobian: null argument");
+  if (J) {
+    DNGD_REQUIRE(j_dtype == DNGD_F64 || j_dtype == DNGD_F32, "bad j_dtype");
+    DNGD_REQUIRE(ldJ >= h->g.n && ldJ % 4 == 0, "ldJ must be >= n and a multiple of 4");
+  }
+  hipStream_t s = S(stream);
+  int rc = forward(h, theta, r, s);
+  if (rc) return rc;
+  if (!J) return DNGD_OK;
+  rc = backward(h, theta, nullptr, s);
+  if (rc) return rc;
+  return write_jacobian(h, J, ldJ, j_dtype, nullptr, s);
+}
+
+int dngd_gram(int64_t m, int64_t n, const void* J, int64_t ldJ, int32_t j_dtype, int32_t passes,
+              double lambda, double* K, int64_t ldK, void* stream) {
+  DNGD_REQUIRE(J && K, "dngd_gram: null pointer");
+  DNGD_REQUIRE(m > 0 && n > 0 && ldJ >= n && ldK >= m, "dngd_gram: bad sizes");
+  DNGD_REQUIRE(j_dtype == DNGD_F64 || j_dtype == DNGD_F32, "dngd_gram: bad j_dtype");
+  DNGD_REQUIRE(j_dtype == DNGD_F64 || passes == 1 || passes == 3, "dngd_gram: passes 1 or 3");
+  DNGD_REQUIRE(std::isfinite(lambda), "dngd_gram: lambda not finite");
+  DNGD_REQUIRE(j_dtype == DNGD_F64 || ldJ % 4 == 0, "dngd_gram: FP32 J needs ldJ %% 4 == 0");
+  hipStream_t s = S(stream);
+  const size_t wb = gram_workspace_bytes(m, n, j_dtype, passes, nullptr);
+  void* work = nullptr;
+  DNGD_HIP(hipMallocAsync(&work, wb, s));
+  int rc = gram_launch(s, m, n, J, ldJ, j_dtype, passes, lambda, K, ldK, work, wb);
+  hipError_t e = hipFreeAsync(work, s);
+  if (rc) return rc;
+  DNGD_HIP(e);
+  return DNGD_OK;
+}
+
+int dngd_cholesky_solve(int64_t m, double* K, int64_t ldK, int32_t factored, int64_t nrhs,
+                        double* B, int64_t ldB, int64_t* info, void* stream) {
+  DNGD_REQUIRE(K && info, "dngd_cholesky_solve: null pointer");
+  DNGD_REQUIRE(m > 0 && ldK >= m && nrhs >= 0 && (nrhs == 0 || (B && ldB >= m)),
+               "dngd_cholesky_solve: bad sizes");
+  hipStream_t s = S(stream);
+  *info = 0;
+  const size_t nflags = (size_t)chol_solve_flag_count(m);
+  char* scratch = nullptr;
+  const size_t bytes = 64 + nflags * sizeof(unsigned);
+  DNGD_HIP(hipMallocAsync((void**)&scratch, bytes, s));
+  DNGD_HIP(hipMemsetAsync(scratch, 0, bytes, s));
+  int* status = reinterpret_cast<int*>(scratch);
+  int64_t* dinfo = reinterpret_cast<int64_t*>(scratch + 16);
+  unsigned* flags = reinterpret_cast<unsigned*>(scratch + 64);
+  unsigned epoch = 0;
+  int rc = 0;
+  if (!factored) {
+    rc = chol_factor(s, m, K, ldK, dinfo, nullptr);
+    if (!rc) {
+      hipError_t e = hipMemcpyAsync(info, dinfo, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) rc = hip_fail(e, "info readback", __FILE__, __LINE__);
+    }
+  }
+  if (!rc && *info == 0) {
+    for (int64_t j = 0; j < nrhs && !rc; ++j)
+      rc = chol_solve(s, m, K, ldK, B + j * ldB, flags, &epoch, status, nullptr);
+  }
+  int hstatus = 0;
+  if (!rc && nrhs > 0 && *info == 0) {
+    hipError_t e = hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "status readback", __FILE__, __LINE__);
+  }
+  hipFreeAsync(scratch, s);
+  if (rc) return rc;
+  if (*info != 0) {
+    set_error("Cholesky: non-positive pivot at column %lld", (long long)*info);
+    return DNGD_ENOTPD;
+  }
+  if (hstatus) {
+    set_error("triangular solve: inter-workgroup wait timed out");
+    return DNGD_ETIMEOUT;
+  }
+  return DNGD_OK;
+}
+
+int dngd_fvv(dngd_problem* h, const double* theta, const double* v, double* fvv, void* stream) {
+  DNGD_REQUIRE(h && theta && v && fvv, "dngd_fvv: null argument");
+  hipStream_t s = S(stream);
+  int rc = forward(h, theta, nullptr, s);
+  if (rc) return rc;
+  return tangent(h, theta, v, 2, fvv, s);
+}
+
+int dngd_jvp(dngd_problem* h, const double* theta, const double* u, double* w, void* stream) {
+  DNGD_REQUIRE(h && theta && u && w, "dngd_jvp: null argument");
+  hipStream_t s = S(stream);
+  int rc = forward(h, theta, nullptr, s);
+  if (rc) return rc;
+  return tangent(h, theta, u, 1, w, s);
+}
+
+int dngd_vjp(dngd_problem* h, const double* theta, const double* p, double* gout, void* stream) {
+  DNGD_REQUIRE(h && theta && p && gout, "dngd_vjp: null argument");
+  hipStream_t s = S(stream);
+  int rc = forward(h, theta, nullptr, s);
+  if (rc) return rc;
+  return vjp(h, theta, p, gout, s);
+}
+
+int dngd_losses(dngd_problem* h, const double* theta, const double* dtheta, int32_t n_eta,
+                const double* etas, double* losses, void* stream) {
+  DNGD_REQUIRE(h && theta && dtheta && etas && losses && n_eta > 0 && n_eta <= 48,
+               "dngd_losses: bad argument");
+  hipStream_t s = S(stream);
+  StepVecs v;
+  int rc = carve_vecs(h, v);
+  if (rc) return rc;
+  for (int k = 0; k < n_eta && !rc; ++k) {
+    rc = copy(s, h->g.n, theta, v.thtmp);
+    if (!rc) rc = axpy(s, h->g.n, etas[k], dtheta, v.thtmp);
+    if (!rc) rc = forward(h, v.thtmp, v.tmpm, s);
+    if (!rc) rc = sumsq(s, h->g.m, v.tmpm, v.scal + k, v.red);
+  }
+  if (rc) return rc;
+  DNGD_HIP(hipMemcpyAsync(losses, v.scal, sizeof(double) * n_eta, hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < n_eta; ++k) losses[k] *= 0.5;
+  return DNGD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Nystrom-PCG (Sections 3.3, 4.2)
+//
+// The preconditioner is the paper's P^{-1} = U (L^ + lam I)^{-1} U^T +
+// (I - U U^T)/lam with U L^ U^T = K^ = K_{:,I} K_II^+ K_{I,:}. Since
+// P^{-1} = (K^ + lam I)^{-1}, it is applied here in Woodbury form without an
+// eigendecomposition: with K_II + delta I = L_I L_I^T and M^T = L_I^{-1} K_{I,:}
+// (so K^ = M M^T), P^{-1} x = (x - M (lam I + M^T M)^{-1} M^T x) / lam.
+// delta = ell * eps * max_i (K_II)_ii plays the role of the paper's "positive
+// eigenvalues" cut; it is doubled until the Cholesky of K_II succeeds.
+
+namespace {
+
+int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t* I, int64_t ell,
+              Precond& P, hipStream_t s) {
+  const Geometry& g = h->g;
+  // landmark indices: validated on the host before any kernel reads them
+  std::vector<int64_t> hI(ell);
+  DNGD_HIP(hipMemcpyAsync(hI.data(), I, ell * 8, hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
+  for (int64_t q = 0; q < ell; ++q) {
+    DNGD_REQUIRE(hI[q] >= 0 && hI[q] < g.m, "landmark index %lld out of range", (long long)hI[q]);
+    DNGD_REQUIRE(q == 0 || hI[q] > hI[q - 1], "landmarks must be sorted and distinct");
+  }
+  const int64_t ldJ = round_up(g.n, 256);
+  const int64_t ldM = round_up(g.m, 4);
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(g.m, (int64_t)(4e9 / (ldJ * 8.0))));
+  // J_I (ell x ldJ) and a chunk of J rows; Mt (ell x ldM), G (ell x ell), index list, ell scratch
+  const size_t bJI = (size_t)ell * ldJ * 8, bMt = (size_t)ell * ldM * 8, bG = (size_t)ell * ell * 8;
+  const size_t bCh = (size_t)chunk * ldJ * 8, bIdx = (size_t)std::max<int64_t>(chunk, ell) * 8;
+  int rc = ensure(h, h->J, bJI + bCh);
+  if (rc) return rc;
+  rc = ensure(h, h->K, bMt + bG + bIdx + (size_t)ell * 8);
+  if (rc) return rc;
+  double* JI = static_cast<double*>(h->J.p);
+  double* Jc = JI + (size_t)ell * ldJ;
+  P.Mt = static_cast<double*>(h->K.p);
+  P.ldM = ldM;
+  P.G = P.Mt + (size_t)ell * ldM;
+  int64_t* idx = reinterpret_cast<int64_t*>(P.G + (size_t)ell * ell);
+  P.tl = reinterpret_cast<double*>(idx + std::max<int64_t>(chunk, ell));
+  P.ell = ell;
+  P.lambda = lambda;
+  StepVecs v;
+  rc = carve_vecs(h, v);
+  if (rc) return rc;
+
+  rc = backward(h, theta, nullptr, s);
+  if (rc) return rc;
+  rc = write_jacobian(h, JI, ldJ, DNGD_F64, nullptr, s, I, ell);
+  if (rc) return rc;
+  // K_{I,:} = J_I J^T, by chunks of recomputed Jacobian rows
+  std::vector<int64_t> hidx(chunk);
+  for (int64_t c0 = 0; c0 < g.m; c0 += chunk) {
+    const int64_t cn = std::min(chunk, g.m - c0);
+    for (int64_t q = 0; q < cn; ++q) hidx[q] = c0 + q;
+    DNGD_HIP(hipMemcpyAsync(idx, hidx.data(), cn * 8, hipMemcpyHostToDevice, s));
+    rc = write_jacobian(h, Jc, ldJ, DNGD_F64, nullptr, s, idx, cn);
+    if (rc) return rc;
+    rc = gemm_f64(s, GEMM_FULL, true, true, ell, cn, g.n, 1.0, JI, ldJ, Jc, ldJ, 0.0, P.Mt + c0,
+                  ldM);
+    if (rc) return rc;
+    DNGD_HIP(hipStreamSynchronize(s));  // hidx is reused
+  }
+  // K_II (landmark columns of K_{I,:}), shifted by delta and factorised; the
+  // shift grows until the factorisation succeeds
+  double* LI = P.G;  // G's storage holds L_I until M^T is formed
+  rc = gather_cols(s, ell, P.Mt, ldM, I, LI);
+  if (rc) return rc;
+  std::vector<double> Kii((size_t)ell * ell);
+  DNGD_HIP(hipMemcpyAsync(Kii.data(), LI, Kii.size() * 8, hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
+  double dmax = 0.0;
+  for (int64_t i = 0; i < ell; ++i) dmax = std::max(dmax, Kii[(size_t)i * ell + i]);
+  double delta = (double)ell * 2.220446049250313e-16 * dmax;
+  if (!(delta > 0.0)) delta = 1e-300;
+  int64_t hinfo = 1;
+  for (int attempt = 0; attempt < 40 && hinfo != 0; ++attempt) {
+    std::vector<double> A(Kii);
+    for (int64_t i = 0; i < ell; ++i) A[(size_t)i * ell + i] += delta;
+    DNGD_HIP(hipMemcpyAsync(LI, A.data(), A.size() * 8, hipMemcpyHostToDevice, s));
+    rc = chol_factor(s, ell, LI, ell, reinterpret_cast<int64_t*>(v.scal), nullptr);
+    if (rc) return rc;
+    DNGD_HIP(hipMemcpyAsync(&hinfo, v.scal, 8, hipMemcpyDeviceToHost, s));
+    DNGD_HIP(hipStreamSynchronize(s));
+    if (hinfo != 0) delta *= 4.0;
+  }
+  DNGD_REQUIRE(hinfo == 0, "Nystrom: K_II could not be factorised");
+  P.delta = delta;
+  // Mt = L_I^{-1} K_{I,:}
+  rc = trsm_lower_left(s, ell, LI, ell, g.m, P.Mt, ldM);
+  if (rc) return rc;
+  // G = lam I + Mt Mt^T, factorised
+  const size_t gw = gram_workspace_bytes(ell, g.m, DNGD_F64, 1, nullptr);
+  rc = ensure(h, h->gram_work, gw);
+  if (rc) return rc;
+  rc = gram_launch(s, ell, g.m, P.Mt, ldM, DNGD_F64, 1, lambda, P.G, ell, h->gram_work.p, gw);
+  if (rc) return rc;
+  rc = chol_factor(s, ell, P.G, ell, reinterpret_cast<int64_t*>(v.scal), nullptr);
+  if (rc) return rc;
+  DNGD_HIP(hipMemcpyAsync(&hinfo, v.scal, 8, hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
+  DNGD_REQUIRE(hinfo == 0, "Nystrom: lam I + M^T M not positive definite");
+  return 0;
+}
+
+// z = P^{-1} x
+int precond_apply(dngd_problem* h, const Precond& P, const StepVecs& v, const Small& sm,
+                  const double* x, double* z, double* tl, hipStream_t s) {
+  const Geometry& g = h->g;
+  // tl = -(M^T x)
+  int rc = gemv_n_residual(s, P.ell, g.m, P.Mt, P.ldM, DNGD_F64, x, nullptr, nullptr, 0.0, tl);
+  if (rc) return rc;
+  rc = chol_solve(s, P.ell, P.G, P.ell, tl, sm.flags, &h->epoch, sm.status, nullptr);
+  if (rc) return rc;
+  // z = M tl = -(M (lam + M^T M)^{-1} M^T x); finish: z = (x + z_neg...) handled by sign
+  rc = gemv_t(s, P.ell, g.m, P.Mt, P.ldM, DNGD_F64, tl, -1.0, z, v.gemv_work);
+  if (rc) return rc;
+  return woodbury_finish(s, g.m, x, 1.0 / P.lambda, z);
+}
+
+int kvp(dngd_problem* h, const double* theta, double lambda, const StepVecs& v, const double* p,
+        double* w, hipStream_t s) {
+  int rc = vjp(h, theta, p, v.t, s);
+  if (rc) return rc;
+  rc = tangent(h, theta, v.t, 1, w, s);
+  if (rc) return rc;
+  return axpy(s, h->g.m, lambda, p, w);
+}
+
+int read_scalars(double* host, const double* dev, int n, hipStream_t s) {
+  DNGD_HIP(hipMemcpyAsync(host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+// PCG (appendix algorithm) on (J J^T + lam I) y = b from y = 0.
+// Work vectors: y -> x (output); r = v.s; z = v.tmpm; p = v.beta; Ap = v.fvv.
+int pcg_solve(dngd_problem* h, const double* theta, const Precond& P, const StepVecs& v,
+              const Small& sm, const double* b, double* x, double tol, int64_t maxit,
+              int* iters, double* relres, hipStream_t s) {
+  const Geometry& g = h->g;
+  double* r = v.s;
+  double* z = v.tmpm;
+  double* p = v.rownorm2;
+  double* Ap = v.alpha;
+  double* tlv = P.tl;
+  int rc = fill(s, g.m, 0.0, x);
+  if (!rc) rc = copy(s, g.m, b, r);
+  if (!rc) rc = precond_apply(h, P, v, sm, r, z, tlv, s);
+  if (!rc) rc = copy(s, g.m, z, p);
+  if (!rc) rc = dot(s, g.m, r, z, v.scal + 0, v.red);
+  if (!rc) rc = sumsq(s, g.m, b, v.scal + 1, v.red);
+  if (rc) return rc;
+  double hs[2];
+  rc = read_scalars(hs, v.scal, 2, s);
+  if (rc) return rc;
+  double rho = hs[0];
+  const double nb = std::sqrt(hs[1]);
+  *iters = 0;
+  *relres = 1.0;
+  if (nb == 0.0) {
+    *relres = 0.0;
+    return DNGD_OK;
+  }
+  for (int64_t j = 0; j < maxit; ++j) {
+    rc = kvp(h, theta, P.lambda, v, p, Ap, s);
+    if (!rc) rc = dot(s, g.m, p, Ap, v.scal + 2, v.red);
+    if (rc) return rc;
+    double pAp;
+    rc = read_scalars(&pAp, v.scal + 2, 1, s);
+    if (rc) return rc;
+    if (!(pAp > 0.0) || !std::isfinite(pAp)) return DNGD_ENOCONV;
+    const double a = rho / pAp;
+    rc = axpy(s, g.m, a, p, x);
+    if (!rc) rc = axpy(s, g.m, -a, Ap, r);
+    if (!rc) rc = sumsq(s, g.m, r, v.scal + 3, v.red);
+    if (rc) return rc;
+    double rr;
+    rc = read_scalars(&rr, v.scal + 3, 1, s);
+    if (rc) return rc;
+    *iters = (int)(j + 1);
+    *relres = std::sqrt(rr) / nb;
+    if (std::sqrt(rr) <= tol * nb) return DNGD_OK;
+    rc = precond_apply(h, P, v, sm, r, z, tlv, s);
+    if (!rc) rc = dot(s, g.m, r, z, v.scal + 4, v.red);
+    if (rc) return rc;
+    double rho_new;
+    rc = read_scalars(&rho_new, v.scal + 4, 1, s);
+    if (rc) return rc;
+    if (!(rho > 0.0) || !std::isfinite(rho_new)) return DNGD_ENOCONV;
+    rc = xpby(s, g.m, z, rho_new / rho, p);
+    if (rc) return rc;
+    rho = rho_new;
+  }
+  return DNGD_ENOCONV;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda, const int64_t* landmarks,
+                     int64_t ell, double tol, int64_t maxit, const double* b, double* x,
+                     dngd_step_stats* stats, void* stream) {
+  DNGD_REQUIRE(h && theta && landmarks && b && x, "dngd_nystrom_pcg: null argument");
+  DNGD_REQUIRE(ell >= 1 && ell <= h->g.m, "dngd_nystrom_pcg: ell out of range");
+  DNGD_REQUIRE(lambda > 0.0 && std::isfinite(lambda), "dngd_nystrom_pcg: lambda must be > 0");
+  DNGD_REQUIRE(tol >= 0.0 && maxit >= 0, "dngd_nystrom_pcg: bad tol/maxit");
+  hipStream_t s = S(stream);
+  StepVecs v;
+  Small sm;
+  int rc = carve_vecs(h, v);
+  if (!rc) rc = carve_small(h, std::max<int64_t>(h->g.m, ell), sm);
+  if (!rc) rc = forward(h, theta, nullptr, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, sm.status);
+  Precond P;
+  rc = pcg_build(h, theta, lambda, landmarks, ell, P, s);
+  if (rc) return rc;
+  int its = 0;
+  double rel = 1.0;
+  const int st = pcg_solve(h, theta, P, v, sm, b, x, tol, maxit, &its, &rel, s);
+  if (st < 0) return st;
+  int hstatus = 0;
+  DNGD_HIP(hipMemcpyAsync(&hstatus, sm.status, sizeof(int), hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->pcg_iterations = its;
+    stats->pcg_converged = (st == DNGD_OK);
+    stats->pcg_rel_residual = rel;
+  }
+  if (hstatus) {
+    set_error("triangular solve: inter-workgroup wait timed out");
+    return DNGD_ETIMEOUT;
+  }
+  return st;
+}
+
+int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_step_opts* opts,
+              double* dtheta, dngd_step_stats* stats, void* stream) {
+  DNGD_REQUIRE(h && theta && dtheta, "dngd_step: null argument");
+  DNGD_REQUIRE(lambda > 0.0 && std::isfinite(lambda), "dngd_step: lambda must be > 0");
+  dngd_step_opts def;
+  dngd_step_opts_default(&def);
+  const dngd_step_opts& o = opts ? *opts : def;
+  DNGD_REQUIRE(o.precision == DNGD_PLAIN || o.precision == DNGD_MIXED, "bad precision");
+  DNGD_REQUIRE(o.solver == DNGD_DENSE || o.solver == DNGD_PCG, "bad solver");
+  DNGD_REQUIRE(o.ir_sweeps >= 0 && o.ir_sweeps <= 8, "ir_sweeps must be in [0, 8]");
+  DNGD_REQUIRE(o.gram_passes == 0 || o.gram_passes == 1 || o.gram_passes == 3, "bad gram_passes");
+  const Geometry& g = h->g;
+  hipStream_t s = S(stream);
+  StepVecs v;
+  Small sm;
+  int rc = carve_vecs(h, v);
+  if (!rc) rc = carve_small(h, std::max<int64_t>(g.m, o.solver == DNGD_PCG ? o.n_landmarks : 0), sm);
+  if (rc) return rc;
+  dngd_step_stats st;
+  std::memset(&st, 0, sizeof(st));
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, sm.status);
+  DNGD_HIP(hipEventRecord(h->ev[0], s));
+
+  if (o.solver == DNGD_PCG) {
+    DNGD_REQUIRE(o.landmarks && o.n_landmarks >= 1 && o.n_landmarks <= g.m, "PCG needs landmarks");
+    rc = forward(h, theta, v.r, s);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[1], s));
+    Precond P;
+    rc = pcg_build(h, theta, lambda, o.landmarks, o.n_landmarks, P, s);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[2], s));
+    // the dual solution alpha goes to v.fvv (pcg_solve works in s, tmpm, rownorm2, alpha)
+    int its = 0;
+    double rel = 1.0;
+    const int pst =
+        pcg_solve(h, theta, P, v, sm, v.r, v.fvv, o.pcg_tol, o.pcg_maxit, &its, &rel, s);
+    if (pst < 0) return pst;
+    // dtheta = -J^T alpha (matrix-free reverse pass)
+    rc = vjp(h, theta, v.fvv, v.v, s);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[3], s));
+    rc = fill(s, g.n, 0.0, dtheta);
+    if (!rc) rc = axpy(s, g.n, -1.0, v.v, dtheta);
+    if (!rc) rc = sumsq(s, g.n, dtheta, v.scal + 8, v.red);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[7], s));
+    DNGD_HIP(hipEventSynchronize(h->ev[7]));
+    double vn2 = 0;
+    DNGD_HIP(hipMemcpy(&vn2, v.scal + 8, 8, hipMemcpyDeviceToHost));
+    int hstatus = 0;
+    DNGD_HIP(hipMemcpy(&hstatus, sm.status, sizeof(int), hipMemcpyDeviceToHost));
+    float ms = 0;
+    hipEventElapsedTime(&ms, h->ev[0], h->ev[7]);
+    st.ms_total = ms;
+    hipEventElapsedTime(&ms, h->ev[1], h->ev[2]);
+    st.ms_factor = ms;
+    hipEventElapsedTime(&ms, h->ev[2], h->ev[3]);
+    st.ms_solve_v = ms;
+    st.vnorm = std::sqrt(vn2);
+    st.pcg_iterations = its;
+    st.pcg_converged = (pst == DNGD_OK);
+    st.pcg_rel_residual = rel;
+    if (stats) *stats = st;
+    if (hstatus) {
+      set_error("triangular solve: inter-workgroup wait timed out");
+      return DNGD_ETIMEOUT;
+    }
+    return pst;
+  }
+
+  // ---------------- dense dual solver ----------------
+  const int jd = (o.precision == DNGD_PLAIN) ? DNGD_F64 : DNGD_F32;
+  const int64_t ldJ = round_up(g.n, 256);
+  rc = ensure(h, h->J, (size_t)g.m * ldJ * (jd == DNGD_F64 ? 8 : 4));
+  if (!rc) rc = ensure(h, h->K, (size_t)g.m * g.m * 8);
+  if (rc) return rc;
+  h->ldJ = ldJ;
+  h->ldK = g.m;
+  h->J_dtype = jd;
+  void* J = h->J.p;
+  double* K = static_cast<double*>(h->K.p);
+
+  // residual + Jacobian (Section 2.2)
+  rc = forward(h, theta, v.r, s);
+  if (!rc) rc = backward(h, theta, nullptr, s);
+  if (!rc) rc = write_jacobian(h, J, ldJ, jd, v.rownorm2, s);
+  if (rc) return rc;
+  DNGD_HIP(hipEventRecord(h->ev[1], s));
+
+  // Gram K = J J^T + lam I
+  int passes = 1;
+  if (jd == DNGD_F32) {
+    passes = o.gram_passes;
+    // max_i ||J_i||^2: decides the bf16 split when passes == 0 (auto)
+    std::vector<double> rn(g.m);
+    DNGD_HIP(hipMemcpyAsync(rn.data(), v.rownorm2, g.m * 8, hipMemcpyDeviceToHost, s));
+    DNGD_HIP(hipStreamSynchronize(s));
+    double dmax = 0.0;
+    for (double x : rn) dmax = std::max(dmax, x);
+    st.max_row_norm2 = dmax;
+    if (passes == 0) {
+      // bf16 unit roundoff 2^-8 times sqrt(D / lam) estimates the refinement
+      // contraction of a 1-pass Gram; split when it would exceed 1/50.
+      passes = (std::ldexp(1.0, -8) * std::sqrt(dmax / lambda) > 0.02) ? 3 : 1;
+    }
+  }
+  st.gram_passes_used = passes;
+  const size_t gw = gram_workspace_bytes(g.m, g.n, jd, passes, nullptr);
+  rc = ensure(h, h->gram_work, gw);
+  if (!rc) rc = gram_launch(s, g.m, g.n, J, ldJ, jd, passes, lambda, K, g.m, h->gram_work.p, gw);
+  if (rc) return rc;
+  DNGD_HIP(hipEventRecord(h->ev[2], s));
+
+  // Cholesky of K + lam I
+  rc = chol_factor(s, g.m, K, g.m, sm.info, nullptr);
+  if (rc) return rc;
+  DNGD_HIP(hipEventRecord(h->ev[3], s));
+
+  // alpha = (K + lam I)^{-1} r (+ refinement), v = -J^T alpha
+  const int ir = (jd == DNGD_F32) ? o.ir_sweeps : 0;
+  rc = dense_solve(h, v, sm, v.r, v.alpha, lambda, ir, J, jd, v.scal + 16, s);
+  if (!rc) rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.alpha, -1.0, v.v, v.gemv_work);
+  if (rc) return rc;
+  DNGD_HIP(hipEventRecord(h->ev[4], s));
+
+  if (o.ga) {
+    // f_vv along v (Section 3.2), beta = (K + lam I)^{-1} f_vv, a = -J^T beta
+    rc = tangent(h, theta, v.v, 2, v.fvv, s);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[5], s));
+    rc = dense_solve(h, v, sm, v.fvv, v.beta, lambda, ir, J, jd, nullptr, s);
+    if (!rc) rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.beta, -1.0, v.a, v.gemv_work);
+    if (!rc) rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
+    if (!rc) rc = sumsq(s, g.n, v.a, v.scal + 1, v.red);
+    if (!rc) rc = ga_combine(s, g.n, v.v, v.a, v.scal, o.eps_norm, dtheta, sm.ga_flag);
+    if (rc) return rc;
+  } else {
+    DNGD_HIP(hipEventRecord(h->ev[5], s));
+    rc = copy(s, g.n, v.v, dtheta);
+    if (!rc) rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
+    if (rc) return rc;
+  }
+  if (ir > 0) {
+    rc = sumsq(s, g.m, v.r, v.scal + 15, v.red);
+    if (rc) return rc;
+  }
+  DNGD_HIP(hipEventRecord(h->ev[6], s));
+  DNGD_HIP(hipEventSynchronize(h->ev[6]));
+
+  double sc[32];
+  DNGD_HIP(hipMemcpy(sc, v.scal, sizeof(sc), hipMemcpyDeviceToHost));
+  int64_t info = 0;
+  int hstatus = 0, gaf = 0;
+  DNGD_HIP(hipMemcpy(&info, sm.info, 8, hipMemcpyDeviceToHost));
+  DNGD_HIP(hipMemcpy(&hstatus, sm.status, sizeof(int), hipMemcpyDeviceToHost));
+  DNGD_HIP(hipMemcpy(&gaf, sm.ga_flag, sizeof(int), hipMemcpyDeviceToHost));
+  float ms = 0;
+  hipEventElapsedTime(&ms, h->ev[0], h->ev[6]);
+  st.ms_total = ms;
+  hipEventElapsedTime(&ms, h->ev[0], h->ev[1]);
+  st.ms_residual_jacobian = ms;
+  hipEventElapsedTime(&ms, h->ev[1], h->ev[2]);
+  st.ms_gram = ms;
+  hipEventElapsedTime(&ms, h->ev[2], h->ev[3]);
+  st.ms_factor = ms;
+  hipEventElapsedTime(&ms, h->ev[3], h->ev[4]);
+  st.ms_solve_v = ms;
+  hipEventElapsedTime(&ms, h->ev[4], h->ev[5]);
+  st.ms_fvv = ms;
+  hipEventElapsedTime(&ms, h->ev[5], h->ev[6]);
+  st.ms_solve_a = ms;
+  st.vnorm = std::sqrt(sc[0]);
+  st.anorm = o.ga ? std::sqrt(sc[1]) : 0.0;
+  st.ga_accepted = o.ga ? gaf : 0;
+  if (ir > 0) {
+    const double nr = std::sqrt(sc[15]);
+    for (int k = 0; k < ir && k < 8; ++k) st.ir_residual[k] = nr > 0 ? std::sqrt(sc[16 + k]) / nr : 0;
+  }
+  if (stats) *stats = st;
+  if (info != 0) {
+    set_error("Cholesky of K + lambda I: non-positive pivot at column %lld", (long long)info);
+    return DNGD_ENOTPD;
+  }
+  if (hstatus) {
+    set_error("triangular solve: inter-workgroup wait timed out");
+    return DNGD_ETIMEOUT;
+  }
+  if (!std::isfinite(st.vnorm) || !std::isfinite(st.anorm)) {
+    set_error("non-finite step");
+    return DNGD_ENAN;
+  }
+  return DNGD_OK;
+}
+
+}  // extern "C"

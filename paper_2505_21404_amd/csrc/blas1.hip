@@ -1,0 +1,325 @@
+// HBM-bound vector kernels of the dense dual step (Section 4.1): the
+// recovery product J^T y (velocity and acceleration, alpha form of the dual
+// recovery formula), the refinement residual s = r - J (J^T x) - lambda x,
+// deterministic norms and the geodesic-acceleration acceptance rule.
+//
+// J^T y: J is m x ldJ row-major, so a column sum is a strided reduction.
+// Each thread owns 4 adjacent columns (one 16-byte FP32 / 32-byte FP64 load
+// per row, coalesced across the wave) and a contiguous band of rows; the
+// per-band partial sums are added in FP64 in band order by a second kernel.
+// J t: 8 rows per workgroup so each slab of t (FP64, 2x the bytes of an FP32
+// row slab) is loaded once for 8 rows.
+#include "common.h"
+
+namespace dngd {
+
+namespace {
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  __device__ static inline void load(const float* p, double (&v)[4]) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  }
+};
+template <>
+struct Vec4<double> {
+  __device__ static inline void load(const double* p, double (&v)[4]) {
+    const double2 x = *reinterpret_cast<const double2*>(p);
+    const double2 y = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_t_partial_kernel(int64_t m, int64_t n,
+                                                             const T* __restrict__ J, int64_t ldJ,
+                                                             const double* __restrict__ x,
+                                                             int64_t rows_per, double* __restrict__ part) {
+  const int64_t c = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+  const int64_t r1 = min(m, r0 + rows_per);
+  double acc[4] = {0, 0, 0, 0};
+  if (c < n) {
+    for (int64_t r = r0; r < r1; ++r) {
+      double v[4];
+      Vec4<T>::load(J + r * ldJ + c, v);
+      const double xr = x[r];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += v[e] * xr;
+    }
+    double* out = part + (int64_t)blockIdx.y * n;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (c + e < n) out[c + e] = acc[e];
+  }
+}
+
+__global__ __launch_bounds__(256) void gemv_t_reduce_kernel(int64_t n, int splits,
+                                                            const double* __restrict__ part,
+                                                            double alpha, double* __restrict__ y) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < splits; ++k) s += part[(int64_t)k * n + c];
+  y[c] = alpha * s;
+}
+
+constexpr int GN_ROWS = 8;
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_n_kernel(int64_t m, int64_t n, const T* __restrict__ J,
+                                                     int64_t ldJ, const double* __restrict__ t,
+                                                     const double* __restrict__ r,
+                                                     const double* __restrict__ x, double lam,
+                                                     double* __restrict__ out) {
+  __shared__ double red[4][GN_ROWS];
+  const int64_t row0 = (int64_t)blockIdx.x * GN_ROWS;
+  double acc[GN_ROWS];
+#pragma unroll
+  for (int q = 0; q < GN_ROWS; ++q) acc[q] = 0.0;
+  for (int64_t k = (int64_t)threadIdx.x * 4; k < n; k += 1024) {
+    double tv[4];
+    const bool full = (k + 3 < n);
+    if (full) {
+      Vec4<double>::load(t + k, tv);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tv[e] = (k + e < n) ? t[k + e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < GN_ROWS; ++q) {
+      const int64_t row = row0 + q;
+      if (row < m) {
+        double v[4];
+        if (full) {
+          Vec4<T>::load(J + row * ldJ + k, v);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = (k + e < n) ? (double)J[row * ldJ + k + e] : 0.0;
+        }
+        acc[q] += v[0] * tv[0] + v[1] * tv[1] + v[2] * tv[2] + v[3] * tv[3];
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < GN_ROWS; ++q) {
+    double s = acc[q];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) red[wave][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < GN_ROWS) {
+    const int q = threadIdx.x;
+    const int64_t row = row0 + q;
+    if (row < m) {
+      const double jt = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+      double o = -jt;
+      if (r) o += r[row];
+      if (x) o -= lam * x[row];
+      out[row] = o;
+    }
+  }
+}
+
+constexpr int SS_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void sumsq_partial_kernel(int64_t n, const double* __restrict__ x,
+                                                            double* __restrict__ part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)SS_BLOCKS * 256)
+    s += x[i] * x[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void sumsq_final_kernel(const double* __restrict__ part,
+                                                          double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = part[threadIdx.x];  // SS_BLOCKS == 256
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void dot_partial_kernel(int64_t n, const double* __restrict__ x,
+                                                          const double* __restrict__ y,
+                                                          double* __restrict__ part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)SS_BLOCKS * 256)
+    s += x[i] * y[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// z = (x - z) * inv_lam
+__global__ void woodbury_finish_kernel(int64_t n, const double* __restrict__ x, double inv_lam,
+                                       double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) z[i] = (x[i] - z[i]) * inv_lam;
+}
+
+// out[i*ell + j] = A[i*lda + idx[j]]  (i, j < ell)
+__global__ void gather_cols_kernel(int64_t ell, const double* __restrict__ A, int64_t lda,
+                                   const int64_t* __restrict__ idx, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ell * ell) return;
+  const int64_t i = e / ell, j = e % ell;
+  out[e] = A[i * lda + idx[j]];
+}
+
+// y = x + beta * y
+__global__ void xpby_kernel(int64_t n, const double* __restrict__ x, double beta,
+                            double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = x[i] + beta * y[i];
+}
+
+__global__ void axpy_kernel(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+__global__ void copy_kernel(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+__global__ void fill_kernel(int64_t n, double v, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+__global__ void ga_combine_kernel(int64_t n, const double* __restrict__ v, const double* __restrict__ a,
+                                  const double* __restrict__ norms2, double eps,
+                                  double* __restrict__ dtheta, int* flag_out) {
+  const double vn = sqrt(norms2[0]);
+  const double an = sqrt(norms2[1]);
+  const bool acc = (vn > eps) && (2.0 * an <= 0.5 * vn);
+  const double coef = acc ? 0.5 : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dtheta[i] = v[i] + coef * a[i];
+  if (i == 0 && flag_out) *flag_out = acc ? 1 : 0;
+}
+
+int gemv_t_splits(int64_t m, int64_t n) {
+  const int64_t cb = cdiv(n, 1024);
+  int64_t s = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, cb));
+  s = std::min<int64_t>(s, cdiv(m, 32));
+  s = std::min<int64_t>(s, 64);
+  return (int)std::max<int64_t>(1, s);
+}
+
+}  // namespace
+
+size_t gemv_t_workspace_bytes(int64_t m, int64_t n) {
+  return (size_t)gemv_t_splits(m, n) * (size_t)n * sizeof(double);
+}
+
+int gemv_t(hipStream_t s, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
+           const double* x, double alpha, double* y, double* work) {
+  DNGD_REQUIRE(ldJ % 4 == 0, "gemv_t: ldJ %% 4 != 0");
+  const int S = gemv_t_splits(m, n);
+  const int64_t rows_per = cdiv(m, S);
+  dim3 grid((unsigned)cdiv(n, 1024), (unsigned)S);
+  if (j_dtype == 0)
+    hipLaunchKernelGGL(gemv_t_partial_kernel<double>, grid, dim3(256), 0, s, m, n,
+                       static_cast<const double*>(J), ldJ, x, rows_per, work);
+  else
+    hipLaunchKernelGGL(gemv_t_partial_kernel<float>, grid, dim3(256), 0, s, m, n,
+                       static_cast<const float*>(J), ldJ, x, rows_per, work);
+  DNGD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(gemv_t_reduce_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, S,
+                     work, alpha, y);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int gemv_n_residual(hipStream_t s, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
+                    const double* t, const double* r, const double* x, double lam, double* out) {
+  DNGD_REQUIRE(ldJ % 4 == 0, "gemv_n: ldJ %% 4 != 0");
+  dim3 grid((unsigned)cdiv(m, GN_ROWS));
+  if (j_dtype == 0)
+    hipLaunchKernelGGL(gemv_n_kernel<double>, grid, dim3(256), 0, s, m, n,
+                       static_cast<const double*>(J), ldJ, t, r, x, lam, out);
+  else
+    hipLaunchKernelGGL(gemv_n_kernel<float>, grid, dim3(256), 0, s, m, n,
+                       static_cast<const float*>(J), ldJ, t, r, x, lam, out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int sumsq(hipStream_t s, int64_t n, const double* x, double* out, double* work) {
+  hipLaunchKernelGGL(sumsq_partial_kernel, dim3(SS_BLOCKS), dim3(256), 0, s, n, x, work);
+  DNGD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sumsq_final_kernel, dim3(1), dim3(256), 0, s, work, out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int dot(hipStream_t s, int64_t n, const double* x, const double* y, double* out, double* work) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(SS_BLOCKS), dim3(256), 0, s, n, x, y, work);
+  DNGD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sumsq_final_kernel, dim3(1), dim3(256), 0, s, work, out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int gather_cols(hipStream_t s, int64_t ell, const double* A, int64_t lda, const int64_t* idx,
+                double* out) {
+  hipLaunchKernelGGL(gather_cols_kernel, dim3((unsigned)cdiv(ell * ell, 256)), dim3(256), 0, s, ell,
+                     A, lda, idx, out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int woodbury_finish(hipStream_t s, int64_t n, const double* x, double inv_lam, double* z) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(woodbury_finish_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, x,
+                     inv_lam, z);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int xpby(hipStream_t s, int64_t n, const double* x, double beta, double* y) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(xpby_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, x, beta, y);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, a, x, y);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+int copy(hipStream_t s, int64_t n, const double* x, double* y) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, x, y);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+int fill(hipStream_t s, int64_t n, double v, double* y) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, v, y);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+int ga_combine(hipStream_t s, int64_t n, const double* v, const double* a, const double* norms2,
+               double eps, double* dtheta, int* flag_out) {
+  hipLaunchKernelGGL(ga_combine_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, v, a,
+                     norms2, eps, dtheta, flag_out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+}  // namespace dngd

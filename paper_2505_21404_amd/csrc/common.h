@@ -1,0 +1,181 @@
+// Internal declarations shared by the libdngd sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+namespace dngd {
+
+// ---------------------------------------------------------------------------
+// error reporting (thread-local message, status codes of dngd.h)
+
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define DNGD_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) return ::dngd::hip_fail(e_, #call, __FILE__, __LINE__); \
+  } while (0)
+
+#define DNGD_LAUNCH_CHECK()                                                   \
+  do {                                                                        \
+    hipError_t e_ = hipGetLastError();                                        \
+    if (e_ != hipSuccess) return ::dngd::hip_fail(e_, "kernel launch", __FILE__, __LINE__); \
+  } while (0)
+
+#define DNGD_REQUIRE(cond, ...)                                               \
+  do {                                                                        \
+    if (!(cond)) { ::dngd::set_error(__VA_ARGS__); return -1; }               \
+  } while (0)
+
+constexpr int kMaxDin = 8;        // input dimension limit (channels = d_in + 2)
+constexpr int kMaxChannels = kMaxDin + 2;
+constexpr int kMaxLayers = 16;
+constexpr int kMaxWidth = 4096;
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+// ---------------------------------------------------------------------------
+// network geometry on the "jet row" layout.
+//
+// Every collocation point contributes C rows to the activation matrices: an
+// interior point carries value, d_in input-gradient and one Laplacian channel
+// (C_int = d_in + 2); a boundary or initial point carries its value only.
+// Rows: interior point i, channel c -> i*C_int + c; then boundary points;
+// then initial points. Activations of layer l are R x w_l FP64 row-major.
+
+struct Geometry {
+  int pde = 0;
+  int L = 0;                 // affine layers
+  int widths[kMaxLayers + 1] = {0};
+  int64_t w_off[kMaxLayers] = {0};  // offset of W_l in theta
+  int64_t b_off[kMaxLayers] = {0};  // offset of b_l in theta
+  int64_t n = 0;             // parameters
+  int64_t m = 0;             // residuals
+  int64_t n_int = 0, n_bdy = 0, n_init = 0;
+  int d_in = 0;
+  int nlap = 0;              // Laplacian coordinates (d_in, or d_in - 1 for heat)
+  int C_int = 0;             // channels per interior point
+  int64_t R_int = 0;         // n_int * C_int
+  int64_t R = 0;             // total jet rows
+  double kappa = 0.0;
+  double c_int = 0.0, c_bdy = 0.0, c_init = 0.0;  // N^{-1/2} class scales
+  int max_width = 0;
+};
+
+// Device-side description of where a point's rows are and how its residual
+// is formed from the output jet. Passed by value to kernels.
+struct RowMap {
+  int64_t n_int, n_bdy, n_init;
+  int64_t R_int;
+  int C_int;
+  int d_in;
+  int nlap;
+  int pde;
+  double kappa, c_int, c_bdy, c_init;
+};
+
+RowMap row_map(const Geometry& g);
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA GEMM: C = alpha * op(A) * op(B)^T-ish + beta * C (see gemm_f64.hip)
+
+enum GemmMode { GEMM_FULL = 0, GEMM_SYRK_LOWER = 1, GEMM_PARTIAL_LOWER = 2 };
+
+// op(A) is M x K: a_kcontig -> A[m*lda + k], else A[k*lda + m].
+// op(B) is N x K: b_kcontig -> B[n*ldb + k], else B[k*ldb + n].
+// C[m*ldc + n] = alpha * sum_k opA[m][k] opB[n][k] + beta * C  (GEMM_FULL)
+// GEMM_SYRK_LOWER: only tiles/elements with m >= n (square M == N).
+// GEMM_PARTIAL_LOWER: lower tiles, split-K; tile partials to `work`.
+int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
+             int64_t K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+             double beta, double* C, int64_t ldc, double* work = nullptr, int splits = 1);
+
+// Lower-triangular tile count for an M x M matrix with tile edge T.
+int64_t lower_tiles(int64_t M, int tile);
+
+// ---------------------------------------------------------------------------
+// Gram (gram.hip)
+
+size_t gram_workspace_bytes(int64_t m, int64_t n, int j_dtype, int passes, int* splits_out);
+int gram_launch(hipStream_t s, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
+                int passes, double lambda, double* K, int64_t ldK, void* work, size_t work_bytes);
+
+// ---------------------------------------------------------------------------
+// Cholesky and triangular solves (chol.hip)
+
+size_t chol_workspace_bytes(int64_t m);
+// Factor the lower triangle in place; *dinfo (device int64) = 0 or first bad column (1-based).
+int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, void* work);
+// Solve L L^T x = b in place for one vector; `flags` is an int array of
+// chol_solve_flag_count(m) entries (zero-initialised once), `epoch` a value
+// never used before with these flags; `dstatus` an int receiving timeout errors.
+int64_t chol_solve_flag_count(int64_t m);
+// B <- L^{-1} B for lower-triangular L (ell x ell) and B (ell x N row-major, ldB)
+int trsm_lower_left(hipStream_t s, int64_t ell, const double* L, int64_t ldL, int64_t N, double* B,
+                    int64_t ldB);
+int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, double* b, unsigned* flags,
+               unsigned* epoch, int* dstatus, double* tmp);
+
+// ---------------------------------------------------------------------------
+// vector kernels (blas1.hip)
+
+// y = alpha * J^T x  (J m x ldJ, FP32 or FP64), deterministic split-M
+size_t gemv_t_workspace_bytes(int64_t m, int64_t n);
+int gemv_t(hipStream_t s, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
+           const double* x, double alpha, double* y, double* work);
+// out = r - J t - lam * x   (any of r, x may be null -> treated as 0); out has m entries
+int gemv_n_residual(hipStream_t s, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
+                    const double* t, const double* r, const double* x, double lam, double* out);
+// deterministic sum of squares of n values -> *out (device double)
+int sumsq(hipStream_t s, int64_t n, const double* x, double* out, double* work);
+int axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);  // y += a x
+int xpby(hipStream_t s, int64_t n, const double* x, double beta, double* y);  // y = x + beta y
+// deterministic dot product -> *out (device); work holds 256 doubles
+int dot(hipStream_t s, int64_t n, const double* x, const double* y, double* out, double* work);
+// z = (x - z) / lam  (last step of the Woodbury form of the preconditioner)
+int woodbury_finish(hipStream_t s, int64_t n, const double* x, double inv_lam, double* z);
+// out[i*ell + j] = A[i*lda + idx[j]] for i, j < ell (idx values < lda)
+int gather_cols(hipStream_t s, int64_t ell, const double* A, int64_t lda, const int64_t* idx,
+                double* out);
+constexpr size_t kReduceWorkBytes = 256 * sizeof(double);
+int copy(hipStream_t s, int64_t n, const double* x, double* y);
+int fill(hipStream_t s, int64_t n, double v, double* y);
+// dtheta = v + coef * a with coef = 0.5 if ||v|| > eps and 2||a|| <= 0.5 ||v|| else 0;
+// norms2 = {||v||^2, ||a||^2} on device; flag_out (device int) = accepted.
+int ga_combine(hipStream_t s, int64_t n, const double* v, const double* a, const double* norms2,
+               double eps, double* dtheta, int* flag_out);
+
+// ---------------------------------------------------------------------------
+// network kernels (net.hip)
+
+int net_input_layer(hipStream_t s, const RowMap& rm, const double* x_int, const double* x_bdy,
+                    const double* x_init, double* A0, int d_in);
+int net_bias_act(hipStream_t s, const RowMap& rm, int w, const double* b, double* Z, double* A);
+int net_act_adjoint(hipStream_t s, const RowMap& rm, int w, const double* Z, const double* Abar,
+                    double* Zbar);
+int net_rowdot(hipStream_t s, int64_t R, int w, const double* X, const double* wv, double beta,
+               const double* Y, const double* wv2, double* out);
+int net_residual(hipStream_t s, const RowMap& rm, const double* U, const double* bias,
+                 const double* f_int, const double* g_bdy, const double* g_init, double* r);
+int net_linear_residual(hipStream_t s, const RowMap& rm, const double* U, const double* bias,
+                        double* out);
+int net_seeds(hipStream_t s, const RowMap& rm, const double* p, double* seed);
+int net_outer_seed(hipStream_t s, int64_t R, int w, const double* seed, const double* wL,
+                   double* Abar);
+// pidx == null: all m rows; else row q of J is point pidx[q] (q < nrows)
+int net_jacobian_rows(hipStream_t s, const Geometry& g, const RowMap& rm, const double* const* A,
+                      const double* const* Zbar, const double* seed, void* J, int64_t ldJ,
+                      int j_dtype, double* rownorm2, const int64_t* pidx = nullptr,
+                      int64_t nrows = 0);
+int net_tangent_act(hipStream_t s, const RowMap& rm, int w, const double* b1, const double* Z0,
+                    double* Z1, double* Z2, double* A1, double* A2, int order);
+int net_colsum_value_rows(hipStream_t s, const RowMap& rm, int w, const double* Zbar, double* out,
+                          double* work);
+
+}  // namespace dngd

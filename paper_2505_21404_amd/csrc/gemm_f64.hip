@@ -1,0 +1,287 @@
+// FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// Used for the tanh-MLP layer products on the jet-row activations (forward,
+// adjoint and t-tangent streams), the plain FP64 residual Gramian
+// K = J J^T (Definition 3.3) and the trailing update of the blocked Cholesky
+// factorisation (dense dual solver, Section 4.1).
+//
+// Tiling: 256 threads = 4 waves in a 2 x 2 grid; a workgroup owns a BM x BN
+// tile of C, a wave (BM/2) x (BN/2), i.e. (BM/32) x (BN/32) MFMA 16x16
+// accumulators. K advances 16 at a time through LDS stored k-major
+// (As[k][m]), so each group of 16 lanes reads 128 contiguous bytes per
+// fragment load (conflict-free). The next K slab is prefetched into
+// registers while the current one feeds the MFMAs.
+#include "common.h"
+
+namespace dngd {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int KS = 16;  // K step
+constexpr int kPartialFull = 3;  // split-K full GEMM: tile partials, then gemm_reduce_full
+
+__device__ inline void tri_decode(int64_t t, int64_t& i, int64_t& j) {
+  int64_t ii = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+  while (ii * (ii + 1) / 2 > t) --ii;
+  i = ii;
+  j = t - ii * (ii + 1) / 2;
+}
+
+// Load a (rows x KS) slab of op(X) (rows along M or N) into registers.
+// kcontig: X[row*ld + k]; else X[k*ld + row].
+template <int ROWS, bool KCONTIG>
+struct SlabLoader {
+  static constexpr int PER = ROWS * KS / 256;  // doubles per thread
+  __device__ static inline void load(double (&r)[PER], const double* __restrict__ X, int64_t ld,
+                                     int64_t row0, int64_t nrows, int64_t k0, int64_t kend) {
+    const int t = threadIdx.x;
+    if (KCONTIG) {
+      // thread -> one row, PER consecutive k
+      constexpr int PARTS = 256 / ROWS;
+      const int row = t % ROWS;
+      const int part = t / ROWS;
+      const int64_t gr = row0 + row;
+      const int64_t kb = k0 + part * PER;
+      const bool rok = gr < nrows;
+      const double* p = X + (rok ? gr : 0) * ld;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int64_t k = kb + e;
+        r[e] = (rok && k < kend) ? p[k] : 0.0;
+      }
+      (void)PARTS;
+    } else {
+      // thread -> one k, PER consecutive rows
+      constexpr int TPK = ROWS / PER;  // threads per k row
+      const int k = t / TPK;
+      const int rb = (t % TPK) * PER;
+      const int64_t gk = k0 + k;
+      const bool kok = gk < kend;
+      const double* p = X + (kok ? gk : 0) * ld;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int64_t gr = row0 + rb + e;
+        r[e] = (kok && gr < nrows) ? p[gr] : 0.0;
+      }
+    }
+  }
+  __device__ static inline void store(const double (&r)[PER], double (*S)[ROWS]) {
+    const int t = threadIdx.x;
+    if (KCONTIG) {
+      const int row = t % ROWS;
+      const int part = t / ROWS;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) S[part * PER + e][row] = r[e];
+    } else {
+      constexpr int TPK = ROWS / PER;
+      const int k = t / TPK;
+      const int rb = (t % TPK) * PER;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) S[k][rb + e] = r[e];
+    }
+  }
+};
+
+template <int BM, int BN, bool AK, bool BKC, int MODE>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(
+    int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
+    const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
+    double* __restrict__ work, int64_t k_per_split, int64_t ntiles) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  __shared__ double As[KS][BM];
+  __shared__ double Bs[KS][BN];
+
+  constexpr bool PARTIAL = (MODE == GEMM_PARTIAL_LOWER || MODE == kPartialFull);
+  int64_t tm, tn;
+  if (MODE == GEMM_FULL || MODE == kPartialFull) {
+    tm = blockIdx.x;
+    tn = blockIdx.y;
+  } else {
+    tri_decode(blockIdx.x, tm, tn);
+  }
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int split = (MODE == GEMM_PARTIAL_LOWER) ? blockIdx.y : ((MODE == kPartialFull) ? blockIdx.z : 0);
+  const int64_t kbeg = PARTIAL ? (int64_t)split * k_per_split : 0;
+  const int64_t kend = PARTIAL ? min(K, kbeg + k_per_split) : K;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  f64x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  using LA = SlabLoader<BM, AK>;
+  using LB = SlabLoader<BN, BKC>;
+  double ra[LA::PER], rb[LB::PER];
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg + KS - 1) / KS : 0;
+  if (nk > 0) {
+    LA::load(ra, A, lda, m0, M, kbeg, kend);
+    LB::load(rb, B, ldb, n0, N, kbeg, kend);
+  }
+  for (int64_t it = 0; it < nk; ++it) {
+    LA::store(ra, As);
+    LB::store(rb, Bs);
+    __syncthreads();
+    if (it + 1 < nk) {
+      const int64_t k0 = kbeg + (it + 1) * KS;
+      LA::load(ra, A, lda, m0, M, k0, kend);
+      LB::load(rb, B, ldb, n0, N, k0, kend);
+    }
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      double a[TM], b[TN];
+      const int kr = kk + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[kr][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[kr][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: accumulator element v of tile (i, j) is C[row][col] with
+  // row = 16 i + lane / 16 + 4 v, col = 16 j + lane % 16 (wave-relative;
+  // lane layout of v_mfma_f64_16x16x4f64 checked on the device)
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rl = wm * WM + i * 16 + (lane >> 4) + 4 * v;
+        const int cl = wn * WN + j * 16 + (lane & 15);
+        const double x = acc[i][j][v];
+        if (MODE == GEMM_PARTIAL_LOWER) {
+          work[(((int64_t)split * ntiles + blockIdx.x) * BM + rl) * BN + cl] = x;
+        } else if (MODE == kPartialFull) {
+          const int64_t tile = ((int64_t)split * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+          work[(tile * BM + rl) * BN + cl] = x;
+        } else {
+          const int64_t row = m0 + rl, col = n0 + cl;
+          if (row < M && col < N && (MODE == GEMM_FULL || row >= col)) {
+            double* p = C + row * ldc + col;
+            *p = (beta == 0.0) ? alpha * x : alpha * x + beta * *p;
+          }
+        }
+      }
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_reduce_full_kernel(int64_t M, int64_t N, int splits,
+                                                               const double* __restrict__ work,
+                                                               double alpha, double beta,
+                                                               double* __restrict__ C, int64_t ldc) {
+  const int e = (blockIdx.z * 256 + threadIdx.x);
+  const int rl = e / BN, cl = e % BN;
+  const int64_t row = (int64_t)blockIdx.x * BM + rl, col = (int64_t)blockIdx.y * BN + cl;
+  if (row >= M || col >= N) return;
+  double s = 0.0;
+  for (int sp = 0; sp < splits; ++sp) {
+    const int64_t tile = ((int64_t)sp * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    s += work[(tile * BM + rl) * BN + cl];
+  }
+  double* p = C + row * ldc + col;
+  *p = (beta == 0.0) ? alpha * s : alpha * s + beta * *p;
+}
+
+template <int BM, int BN, bool AK, bool BKC>
+int launch_split_full(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha,
+                      const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                      double* C, int64_t ldc, double* work, int splits) {
+  const int64_t kps = round_up(cdiv(K, splits), KS);
+  dim3 grid((unsigned)cdiv(M, BM), (unsigned)cdiv(N, BN), (unsigned)splits);
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, AK, BKC, kPartialFull>), grid, dim3(256), 0, s, M, N,
+                     K, alpha, A, lda, B, ldb, beta, C, ldc, work, kps, (int64_t)0);
+  DNGD_LAUNCH_CHECK();
+  dim3 g2(grid.x, grid.y, BM * BN / 256);
+  hipLaunchKernelGGL((gemm_reduce_full_kernel<BM, BN>), g2, dim3(256), 0, s, M, N, splits, work,
+                     alpha, beta, C, ldc);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+template <int BM, int BN, bool AK, bool BKC, int MODE>
+int launch(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+           int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+           double* work, int splits) {
+  dim3 grid;
+  int64_t ntiles = 0, kps = K;
+  if (MODE == GEMM_FULL) {
+    grid = dim3((unsigned)cdiv(M, BM), (unsigned)cdiv(N, BN), 1);
+  } else {
+    ntiles = lower_tiles(M, BM);
+    kps = (MODE == GEMM_PARTIAL_LOWER) ? round_up(cdiv(K, splits), KS) : K;
+    grid = dim3((unsigned)ntiles, (MODE == GEMM_PARTIAL_LOWER) ? (unsigned)splits : 1u, 1);
+  }
+  if (grid.x == 0 || grid.y == 0) return 0;
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, AK, BKC, MODE>), grid, dim3(256), 0, s, M, N, K,
+                     alpha, A, lda, B, ldb, beta, C, ldc, work, kps, ntiles);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+}  // namespace
+
+int64_t lower_tiles(int64_t M, int tile) {
+  const int64_t t = cdiv(M, tile);
+  return t * (t + 1) / 2;
+}
+
+int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
+             int64_t K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+             double beta, double* C, int64_t ldc, double* work, int splits) {
+  if (M <= 0 || N <= 0) return 0;
+  if (mode == GEMM_PARTIAL_LOWER) {
+    return launch<128, 128, true, true, GEMM_PARTIAL_LOWER>(s, M, N, K, alpha, A, lda, B, ldb,
+                                                             beta, C, ldc, work, splits);
+  }
+  if (mode == GEMM_SYRK_LOWER) {
+    if (M >= 1024)
+      return launch<128, 128, true, true, GEMM_SYRK_LOWER>(s, M, N, K, alpha, A, lda, B, ldb,
+                                                            beta, C, ldc, work, 1);
+    return launch<64, 64, true, true, GEMM_SYRK_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta,
+                                                        C, ldc, work, 1);
+  }
+  if (splits > 1) {
+    DNGD_REQUIRE(work != nullptr, "gemm_f64: split-K needs a workspace");
+#define DNGD_SPLIT_CASE(AKV, BKV)                                                            \
+    if (a_kcontig == AKV && b_kcontig == BKV)                                                \
+      return launch_split_full<64, 64, AKV, BKV>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, \
+                                                 ldc, work, splits);
+    DNGD_SPLIT_CASE(true, true)
+    DNGD_SPLIT_CASE(true, false)
+    DNGD_SPLIT_CASE(false, true)
+    DNGD_SPLIT_CASE(false, false)
+#undef DNGD_SPLIT_CASE
+  }
+  const bool big = (cdiv(M, 128) * cdiv(N, 128)) >= 512;
+#define DNGD_GEMM_CASE(AKV, BKV)                                                               \
+  if (a_kcontig == AKV && b_kcontig == BKV) {                                                  \
+    if (big)                                                                                   \
+      return launch<128, 128, AKV, BKV, GEMM_FULL>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, \
+                                                   ldc, work, 1);                              \
+    return launch<64, 64, AKV, BKV, GEMM_FULL>(s, M, N, K, alpha, A, lda, B, ldb, beta, C,     \
+                                               ldc, work, 1);                                  \
+  }
+  DNGD_GEMM_CASE(true, true)
+  DNGD_GEMM_CASE(true, false)
+  DNGD_GEMM_CASE(false, true)
+  DNGD_GEMM_CASE(false, false)
+#undef DNGD_GEMM_CASE
+  return -1;
+}
+
+}  // namespace dngd

@@ -1,0 +1,567 @@
+// tanh-MLP kernels on the jet-row layout: the residual map and its
+// derivatives (Section 2.2), with input Laplacians in forward mode.
+//
+// A point's jet is its value, input gradient and input Laplacian; through an
+// affine layer each channel is multiplied by W (the bias only enters the
+// value), and through tanh:
+//   a.v = s0,  a.g = s1 z.g,  a.l = s1 z.l + s2 |z.g|^2_lap
+// with s_k the k-th derivative of tanh at z.v and |.|^2_lap summing the
+// Laplacian coordinates only. The layer products run on the FP64 matrix
+// cores (gemm_f64.hip); the kernels here are the per-(point, neuron)
+// elementwise stages, the output row dots and the Jacobian row writer.
+#include "common.h"
+
+namespace dngd {
+
+namespace {
+
+struct Tanh {
+  double s0, s1, s2, s3, s4;
+  __device__ inline Tanh(double z, int order) {
+    s0 = tanh(z);
+    s1 = 1.0 - s0 * s0;
+    s2 = -2.0 * s0 * s1;
+    s3 = (order >= 3) ? s1 * (6.0 * s0 * s0 - 2.0) : 0.0;
+    s4 = (order >= 4) ? 8.0 * s0 * s1 * (2.0 - 3.0 * s0 * s0) : 0.0;
+  }
+};
+
+// point p -> (first jet row, channel count)
+__device__ inline void point_rows(const RowMap& rm, int64_t p, int64_t& base, int& C) {
+  if (p < rm.n_int) {
+    base = p * rm.C_int;
+    C = rm.C_int;
+  } else {
+    base = rm.R_int + (p - rm.n_int);
+    C = 1;
+  }
+}
+
+__global__ void input_layer_kernel(RowMap rm, const double* __restrict__ xi,
+                                   const double* __restrict__ xb, const double* __restrict__ x0,
+                                   double* __restrict__ A0) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const int d = rm.d_in;
+  int64_t base;
+  int C;
+  point_rows(rm, p, base, C);
+  const double* x;
+  if (p < rm.n_int) x = xi + p * d;
+  else if (p < rm.n_int + rm.n_bdy) x = xb + (p - rm.n_int) * d;
+  else x = x0 + (p - rm.n_int - rm.n_bdy) * d;
+  for (int k = 0; k < d; ++k) A0[base * d + k] = x[k];
+  if (C > 1) {
+    for (int c = 0; c < d; ++c)
+      for (int k = 0; k < d; ++k) A0[(base + 1 + c) * d + k] = (c == k) ? 1.0 : 0.0;
+    for (int k = 0; k < d; ++k) A0[(base + 1 + d) * d + k] = 0.0;
+  }
+}
+
+// forward jet activation: Z.v += b; A = tanh-jet(Z)
+__global__ __launch_bounds__(256) void bias_act_kernel(RowMap rm, int w, const double* __restrict__ b,
+                                                       double* __restrict__ Z,
+                                                       double* __restrict__ A) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= npts * w) return;
+  const int64_t p = idx / w;
+  const int o = (int)(idx % w);
+  int64_t base;
+  int C;
+  point_rows(rm, p, base, C);
+  double* z = Z + base * w + o;
+  double* a = A + base * w + o;
+  const double zv = z[0] + (b ? b[o] : 0.0);
+  z[0] = zv;
+  const Tanh s(zv, 2);
+  a[0] = s.s0;
+  if (C > 1) {
+    const int d = rm.d_in;
+    double gg = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double g = z[(int64_t)(1 + k) * w];
+      if (k < rm.nlap) gg += g * g;
+      a[(int64_t)(1 + k) * w] = s.s1 * g;
+    }
+    const double zl = z[(int64_t)(1 + d) * w];
+    a[(int64_t)(1 + d) * w] = s.s1 * zl + s.s2 * gg;
+  }
+}
+
+// adjoint of the jet activation: Zbar from Abar and Z (with bias)
+__global__ __launch_bounds__(256) void act_adjoint_kernel(RowMap rm, int w,
+                                                          const double* __restrict__ Z,
+                                                          const double* __restrict__ Ab,
+                                                          double* __restrict__ Zb) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= npts * w) return;
+  const int64_t p = idx / w;
+  const int o = (int)(idx % w);
+  int64_t base;
+  int C;
+  point_rows(rm, p, base, C);
+  const double* z = Z + base * w + o;
+  const double* ab = Ab + base * w + o;
+  double* zb = Zb + base * w + o;
+  const Tanh s(z[0], 3);
+  if (C == 1) {
+    zb[0] = ab[0] * s.s1;
+    return;
+  }
+  const int d = rm.d_in;
+  const double abl = ab[(int64_t)(1 + d) * w];
+  const double zl = z[(int64_t)(1 + d) * w];
+  double gg = 0.0, ag = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double g = z[(int64_t)(1 + k) * w];
+    const double agk = ab[(int64_t)(1 + k) * w];
+    if (k < rm.nlap) gg += g * g;
+    ag += agk * g;
+    zb[(int64_t)(1 + k) * w] = s.s1 * agk + ((k < rm.nlap) ? 2.0 * s.s2 * abl * g : 0.0);
+  }
+  zb[0] = ab[0] * s.s1 + s.s2 * ag + abl * (s.s2 * zl + s.s3 * gg);
+  zb[(int64_t)(1 + d) * w] = s.s1 * abl;
+}
+
+// out[row] = X[row] . wv + beta * Y[row] . wv2   (one wave per row)
+__global__ __launch_bounds__(256) void rowdot_kernel(int64_t R, int w, const double* __restrict__ X,
+                                                     const double* __restrict__ wv, double beta,
+                                                     const double* __restrict__ Y,
+                                                     const double* __restrict__ wv2,
+                                                     double* __restrict__ out) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= R) return;
+  double s = 0.0;
+  for (int k = lane; k < w; k += 64) {
+    s += X[row * w + k] * wv[k];
+    if (Y) s += beta * Y[row * w + k] * wv2[k];
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) out[row] = s;
+}
+
+// interior operator on an output jet: -lap u (Poisson) or u_t - kappa lap u (heat)
+__device__ inline double interior_op(const RowMap& rm, const double* U, int64_t base) {
+  const double lap = U[base + 1 + rm.d_in];
+  if (rm.pde == 0) return -lap;
+  return U[base + rm.d_in] - rm.kappa * lap;  // channel 1 + (d_in - 1) is d/dt
+}
+
+__global__ void residual_kernel(RowMap rm, const double* __restrict__ U,
+                                const double* __restrict__ bias_p, const double* __restrict__ f,
+                                const double* __restrict__ g, const double* __restrict__ g0,
+                                double* __restrict__ r) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const double bias = bias_p ? bias_p[0] : 0.0;  // output bias: value channel only
+  int64_t base;
+  int C;
+  point_rows(rm, p, base, C);
+  double v;
+  if (p < rm.n_int) {
+    v = rm.c_int * (interior_op(rm, U, base) - (f ? f[p] : 0.0));
+  } else if (p < rm.n_int + rm.n_bdy) {
+    v = rm.c_bdy * (U[base] + bias - (g ? g[p - rm.n_int] : 0.0));
+  } else {
+    v = rm.c_init * (U[base] + bias - (g0 ? g0[p - rm.n_int - rm.n_bdy] : 0.0));
+  }
+  r[p] = v;
+}
+
+// per-row backward seeds: d r_p / d (output channel) times p_p (1 if p == null)
+__global__ void seeds_kernel(RowMap rm, const double* __restrict__ pv, double* __restrict__ seed) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const double s = pv ? pv[p] : 1.0;
+  int64_t base;
+  int C;
+  point_rows(rm, p, base, C);
+  if (p < rm.n_int) {
+    for (int c = 0; c < C; ++c) seed[base + c] = 0.0;
+    if (rm.pde == 0) {
+      seed[base + 1 + rm.d_in] = -rm.c_int * s;
+    } else {
+      seed[base + rm.d_in] = rm.c_int * s;
+      seed[base + 1 + rm.d_in] = -rm.kappa * rm.c_int * s;
+    }
+  } else if (p < rm.n_int + rm.n_bdy) {
+    seed[base] = rm.c_bdy * s;
+  } else {
+    seed[base] = rm.c_init * s;
+  }
+}
+
+__global__ void outer_seed_kernel(int64_t R, int w, const double* __restrict__ seed,
+                                  const double* __restrict__ wL, double* __restrict__ Ab) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= R * w) return;
+  Ab[idx] = seed[idx / w] * wL[idx % w];
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian rows: J[p][W_l[o][k]] = sum_c Zbar_l[p,c][o] A_{l-1}[p,c][k],
+// J[p][b_l[o]] = Zbar_l[p,value][o]. One workgroup per point.
+
+struct JacLayers {
+  const double* A[kMaxLayers];     // A_{l-1}: R x w_{l-1}
+  const double* Zb[kMaxLayers];    // Zbar_l:  R x w_l  (seed for the output layer)
+  int win[kMaxLayers], wout[kMaxLayers];
+  int64_t woff[kMaxLayers], boff[kMaxLayers];
+  int L;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void jacobian_rows_kernel(RowMap rm, JacLayers jl, T* __restrict__ J,
+                                                            int64_t ldJ, int64_t n,
+                                                            double* __restrict__ rownorm2,
+                                                            const int64_t* __restrict__ pidx) {
+  __shared__ double red[4];
+  const int64_t p = pidx ? pidx[blockIdx.x] : (int64_t)blockIdx.x;
+  int64_t base;
+  int C;
+  point_rows(rm, p, base, C);
+  T* row = J + (int64_t)blockIdx.x * ldJ;
+  const int t = threadIdx.x;
+  double ss = 0.0;
+  for (int l = 0; l < jl.L; ++l) {
+    const int win = jl.win[l], wout = jl.wout[l];
+    const double* A = jl.A[l] + base * win;
+    const double* Zb = jl.Zb[l] + base * wout;
+    const int nq = (win + 3) >> 2;
+    int tpr = 1;
+    while (tpr < nq && tpr < 256) tpr <<= 1;
+    const int rpp = 256 / tpr;
+    T* W = row + jl.woff[l];
+    for (int q0 = 0; q0 < nq; q0 += tpr) {
+      const int q = q0 + (t % tpr);
+      const bool qok = q < nq;
+      double a[kMaxChannels][4];
+#pragma unroll
+      for (int c = 0; c < kMaxChannels; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = 4 * q + e;
+          a[c][e] = (qok && c < C && k < win) ? A[(int64_t)c * win + k] : 0.0;
+        }
+      if (qok) {
+        for (int o = t / tpr; o < wout; o += rpp) {
+          double v[4] = {0, 0, 0, 0};
+#pragma unroll
+          for (int c = 0; c < kMaxChannels; ++c) {
+            if (c < C) {
+              const double zc = Zb[(int64_t)c * wout + o];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) v[e] += zc * a[c][e];
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int k = 4 * q + e;
+            if (k < win) {
+              W[(int64_t)o * win + k] = (T)v[e];
+              const double vr = (double)(T)v[e];
+              ss += vr * vr;
+            }
+          }
+        }
+      }
+    }
+    T* B = row + jl.boff[l];
+    for (int o = t; o < wout; o += 256) {
+      const double v = Zb[o];
+      B[o] = (T)v;
+      const double vr = (double)(T)v;
+      ss += vr * vr;
+    }
+  }
+  for (int64_t k = n + t; k < ldJ; k += 256) row[k] = (T)0;
+  if (rownorm2) {
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+    if ((t & 63) == 0) red[t >> 6] = ss;
+    __syncthreads();
+    if (t == 0) rownorm2[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// t-tangent streams (f_vv and J u): given Z0 and the layer products
+// Z1 = W a1 + V a0 (+ c on the value channel, added here) and Z2 = W a2 + 2 V a1,
+//   a1 = s'(z0) z1,  a2 = s'(z0) z2 + s''(z0) z1 z1
+// where s'(z0), s''(z0) are jets (function rule) and products follow the
+// jet product rule.
+
+template <int D>
+struct Jet {
+  double v, g[D], l;
+};
+
+template <int D>
+__device__ inline void jet_load(Jet<D>& j, const double* z, int64_t w, int C) {
+  j.v = z[0];
+#pragma unroll
+  for (int k = 0; k < D; ++k) j.g[k] = (C > 1) ? z[(int64_t)(1 + k) * w] : 0.0;
+  j.l = (C > 1) ? z[(int64_t)(1 + D) * w] : 0.0;
+}
+template <int D>
+__device__ inline void jet_store(const Jet<D>& j, double* a, int64_t w, int C) {
+  a[0] = j.v;
+  if (C > 1) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) a[(int64_t)(1 + k) * w] = j.g[k];
+    a[(int64_t)(1 + D) * w] = j.l;
+  }
+}
+template <int D>
+__device__ inline Jet<D> jet_mul(const Jet<D>& p, const Jet<D>& q, int nlap) {
+  Jet<D> r;
+  r.v = p.v * q.v;
+  double cross = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    r.g[k] = p.v * q.g[k] + q.v * p.g[k];
+    if (k < nlap) cross += p.g[k] * q.g[k];
+  }
+  r.l = p.v * q.l + q.v * p.l + 2.0 * cross;
+  return r;
+}
+// jet of phi(z) given phi(z.v), phi'(z.v), phi''(z.v)
+template <int D>
+__device__ inline Jet<D> jet_fn(double f0, double f1, double f2, const Jet<D>& z, int nlap) {
+  Jet<D> r;
+  r.v = f0;
+  double gg = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    r.g[k] = f1 * z.g[k];
+    if (k < nlap) gg += z.g[k] * z.g[k];
+  }
+  r.l = f1 * z.l + f2 * gg;
+  return r;
+}
+
+// Boundary / initial rows carry only the value channel; their gradient and
+// Laplacian entries are zero in the jets above, so the same formulas apply.
+template <int D>
+__global__ __launch_bounds__(256) void tangent_act_kernel(RowMap rm, int w, const double* __restrict__ b1,
+                                                          const double* __restrict__ Z0,
+                                                          double* __restrict__ Z1,
+                                                          const double* __restrict__ Z2,
+                                                          double* __restrict__ A1,
+                                                          double* __restrict__ A2, int order) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= npts * w) return;
+  const int64_t p = idx / w;
+  const int o = (int)(idx % w);
+  int64_t base;
+  int C;
+  point_rows(rm, p, base, C);
+  const int nl = rm.nlap;
+  const int64_t off = base * w + o;
+  Jet<D> z0, z1;
+  jet_load(z0, Z0 + off, w, C);
+  jet_load(z1, Z1 + off, w, C);
+  if (b1) z1.v += b1[o];
+  const Tanh s(z0.v, order >= 2 ? 4 : 3);
+  const Jet<D> P = jet_fn(s.s1, s.s2, s.s3, z0, nl);  // jet of tanh'(z0)
+  const Jet<D> a1 = jet_mul(P, z1, nl);
+  jet_store(a1, A1 + off, w, C);
+  if (order >= 2) {
+    Jet<D> z2;
+    jet_load(z2, Z2 + off, w, C);
+    const Jet<D> Q = jet_fn(s.s2, s.s3, s.s4, z0, nl);  // jet of tanh''(z0)
+    const Jet<D> t1 = jet_mul(P, z2, nl);
+    const Jet<D> t2 = jet_mul(Q, jet_mul(z1, z1, nl), nl);
+    Jet<D> a2;
+    a2.v = t1.v + t2.v;
+#pragma unroll
+    for (int k = 0; k < D; ++k) a2.g[k] = t1.g[k] + t2.g[k];
+    a2.l = t1.l + t2.l;
+    jet_store(a2, A2 + off, w, C);
+  }
+}
+
+// sum over the value rows of Zbar (bias gradients), deterministic 2 passes
+__global__ __launch_bounds__(256) void colsum_partial_kernel(RowMap rm, int w,
+                                                             const double* __restrict__ Zb,
+                                                             int64_t pts_per,
+                                                             double* __restrict__ part) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= w) return;
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  const int64_t p0 = (int64_t)blockIdx.y * pts_per;
+  const int64_t p1 = min(npts, p0 + pts_per);
+  double s = 0.0;
+  for (int64_t p = p0; p < p1; ++p) {
+    int64_t base;
+    int C;
+    point_rows(rm, p, base, C);
+    s += Zb[base * w + o];
+  }
+  part[(int64_t)blockIdx.y * w + o] = s;
+}
+
+__global__ void colsum_reduce_kernel(int w, int S, const double* __restrict__ part,
+                                     double* __restrict__ out) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= w) return;
+  double s = 0.0;
+  for (int k = 0; k < S; ++k) s += part[(int64_t)k * w + o];
+  out[o] = s;
+}
+
+}  // namespace
+
+RowMap row_map(const Geometry& g) {
+  RowMap r;
+  r.n_int = g.n_int;
+  r.n_bdy = g.n_bdy;
+  r.n_init = g.n_init;
+  r.R_int = g.R_int;
+  r.C_int = g.C_int;
+  r.d_in = g.d_in;
+  r.nlap = g.nlap;
+  r.pde = g.pde;
+  r.kappa = g.kappa;
+  r.c_int = g.c_int;
+  r.c_bdy = g.c_bdy;
+  r.c_init = g.c_init;
+  return r;
+}
+
+static inline unsigned blocks_for(int64_t n, int bs = 256) { return (unsigned)cdiv(n, bs); }
+
+int net_input_layer(hipStream_t s, const RowMap& rm, const double* xi, const double* xb,
+                    const double* x0, double* A0, int) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  hipLaunchKernelGGL(input_layer_kernel, dim3(blocks_for(npts, 128)), dim3(128), 0, s, rm, xi, xb,
+                     x0, A0);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_bias_act(hipStream_t s, const RowMap& rm, int w, const double* b, double* Z, double* A) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  hipLaunchKernelGGL(bias_act_kernel, dim3(blocks_for(npts * w)), dim3(256), 0, s, rm, w, b, Z, A);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_act_adjoint(hipStream_t s, const RowMap& rm, int w, const double* Z, const double* Ab,
+                    double* Zb) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  hipLaunchKernelGGL(act_adjoint_kernel, dim3(blocks_for(npts * w)), dim3(256), 0, s, rm, w, Z, Ab,
+                     Zb);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_rowdot(hipStream_t s, int64_t R, int w, const double* X, const double* wv, double beta,
+               const double* Y, const double* wv2, double* out) {
+  hipLaunchKernelGGL(rowdot_kernel, dim3(blocks_for(R, 4)), dim3(256), 0, s, R, w, X, wv, beta, Y,
+                     wv2, out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_residual(hipStream_t s, const RowMap& rm, const double* U, const double* bias,
+                 const double* f, const double* g, const double* g0, double* r) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  hipLaunchKernelGGL(residual_kernel, dim3(blocks_for(npts)), dim3(256), 0, s, rm, U, bias, f, g,
+                     g0, r);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_linear_residual(hipStream_t s, const RowMap& rm, const double* U, const double* bias,
+                        double* out) {
+  return net_residual(s, rm, U, bias, nullptr, nullptr, nullptr, out);
+}
+
+int net_seeds(hipStream_t s, const RowMap& rm, const double* p, double* seed) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  hipLaunchKernelGGL(seeds_kernel, dim3(blocks_for(npts)), dim3(256), 0, s, rm, p, seed);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_outer_seed(hipStream_t s, int64_t R, int w, const double* seed, const double* wL,
+                   double* Ab) {
+  hipLaunchKernelGGL(outer_seed_kernel, dim3(blocks_for(R * w)), dim3(256), 0, s, R, w, seed, wL,
+                     Ab);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_jacobian_rows(hipStream_t s, const Geometry& g, const RowMap& rm, const double* const* A,
+                      const double* const* Zb, const double* seed, void* J, int64_t ldJ,
+                      int j_dtype, double* rownorm2, const int64_t* pidx, int64_t nrows) {
+  JacLayers jl;
+  jl.L = g.L;
+  for (int l = 0; l < g.L; ++l) {
+    jl.A[l] = A[l];
+    jl.Zb[l] = (l == g.L - 1) ? seed : Zb[l];
+    jl.win[l] = g.widths[l];
+    jl.wout[l] = g.widths[l + 1];
+    jl.woff[l] = g.w_off[l];
+    jl.boff[l] = g.b_off[l];
+  }
+  dim3 grid((unsigned)(pidx ? nrows : g.m));
+  if (grid.x == 0) return 0;
+  if (j_dtype == 0)
+    hipLaunchKernelGGL(jacobian_rows_kernel<double>, grid, dim3(256), 0, s, rm, jl,
+                       static_cast<double*>(J), ldJ, g.n, rownorm2, pidx);
+  else
+    hipLaunchKernelGGL(jacobian_rows_kernel<float>, grid, dim3(256), 0, s, rm, jl,
+                       static_cast<float*>(J), ldJ, g.n, rownorm2, pidx);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_tangent_act(hipStream_t s, const RowMap& rm, int w, const double* b1, const double* Z0,
+                    double* Z1, double* Z2, double* A1, double* A2, int order) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  const dim3 grid(blocks_for(npts * w));
+  switch (rm.d_in) {
+#define DNGD_TANGENT_CASE(DV)                                                                  \
+  case DV:                                                                                    \
+    hipLaunchKernelGGL(tangent_act_kernel<DV>, grid, dim3(256), 0, s, rm, w, b1, Z0, Z1, Z2, A1, \
+                       A2, order);                                                            \
+    break;
+    DNGD_TANGENT_CASE(1)
+    DNGD_TANGENT_CASE(2)
+    DNGD_TANGENT_CASE(3)
+    DNGD_TANGENT_CASE(4)
+    DNGD_TANGENT_CASE(5)
+    DNGD_TANGENT_CASE(6)
+    DNGD_TANGENT_CASE(7)
+    DNGD_TANGENT_CASE(8)
+#undef DNGD_TANGENT_CASE
+    default:
+      set_error("tangent: d_in %d unsupported", rm.d_in);
+      return -1;
+  }
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_colsum_value_rows(hipStream_t s, const RowMap& rm, int w, const double* Zb, double* out,
+                          double* work) {
+  const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  const int S = (int)std::min<int64_t>(64, std::max<int64_t>(1, cdiv(npts, 256)));
+  const int64_t per = cdiv(npts, S);
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3(blocks_for(w), S), dim3(256), 0, s, rm, w, Zb,
+                     per, work);
+  DNGD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(colsum_reduce_kernel, dim3(blocks_for(w)), dim3(256), 0, s, w, S, work, out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+}  // namespace dngd

@@ -1,0 +1,191 @@
+"""GPU parity of each C-ABI entry point against the FP64 CPU oracle, on
+seeded inputs at sizes that span several tiles and ragged tails."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+from oracle import network as N
+from oracle import step as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def D():
+    from paper_2505_21404_amd import dngd
+    return dngd
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def tiny(kind):
+    if kind == "poisson":
+        return W.poisson_problem([2, 20, 17, 1], 37, 11, "sinsin", 5)
+    if kind == "heat":
+        return W.heat_problem([3, 24, 9, 1], 29, 7, 6, 0.1, 6)
+    if kind == "poisson5":
+        return W.poisson_problem([5, 33, 65, 40, 1], 70, 30, "sumsin_half", 7)
+    raise KeyError(kind)
+
+
+def rand_theta(widths, seed, scale=0.7):
+    return scale * np.random.default_rng(seed).standard_normal(N.n_params(widths))
+
+
+@pytest.mark.parametrize("kind", ["poisson", "heat", "poisson5"])
+def test_residual_jacobian_f64(kind):
+    p = tiny(kind)
+    th = rand_theta(p.widths, 1)
+    say("case residual_jacobian_f64", kind, p.widths, p.m)
+    prob = D().Problem.from_workload(p)
+    r, J = prob.residual_jacobian(th, D().F64)
+    torch.cuda.synchronize()
+    r_o = N.residual(p, th)
+    J_o = N.jacobian(p, th)
+    assert rel(r.cpu().numpy(), r_o) <= 1e-12
+    Jg = J.cpu().numpy()
+    assert np.all(Jg[:, p.n_params:] == 0.0)
+    assert np.abs(Jg[:, :p.n_params] - J_o).max() <= 1e-12 * np.abs(J_o).max()
+
+
+@pytest.mark.parametrize("kind", ["poisson", "heat"])
+def test_jacobian_f32(kind):
+    p = tiny(kind)
+    th = rand_theta(p.widths, 2)
+    say("case jacobian_f32", kind)
+    prob = D().Problem.from_workload(p)
+    _, J = prob.residual_jacobian(th, D().F32)
+    J_o = N.jacobian(p, th)
+    Jg = J.cpu().numpy().astype(np.float64)[:, :p.n_params]
+    # one rounding to FP32 of an FP64 value: |err| <= 2^-24 |J| (+ tiny FP64 slack)
+    assert np.all(np.abs(Jg - J_o) <= 2.0 ** -24 * np.abs(J_o) + 1e-300 + 1e-13 * np.abs(J_o).max())
+
+
+@pytest.mark.parametrize("kind", ["poisson", "heat", "poisson5"])
+def test_fvv_jvp_vjp(kind):
+    p = tiny(kind)
+    th = rand_theta(p.widths, 3)
+    v = rand_theta(p.widths, 4, 0.3)
+    pv = np.random.default_rng(5).standard_normal(p.m)
+    say("case fvv_jvp_vjp", kind)
+    prob = D().Problem.from_workload(p)
+    f = prob.fvv(th, v).cpu().numpy()
+    Jv = prob.jvp(th, v).cpu().numpy()
+    Jtp = prob.vjp(th, pv).cpu().numpy()
+    J_o = N.jacobian(p, th)
+    assert rel(f, N.fvv(p, th, v)) <= 1e-11
+    assert rel(Jv, J_o @ v) <= 1e-12
+    assert rel(Jtp, J_o.T @ pv) <= 1e-12
+
+
+@pytest.mark.parametrize("m,n", [(1, 5), (63, 130), (129, 1000), (300, 4099), (517, 20000)])
+def test_gram_f64(m, n):
+    say("case gram_f64", m, n)
+    rng = np.random.default_rng(m * 7 + n)
+    J = rng.standard_normal((m, n))
+    ld = (n + 3) // 4 * 4
+    Jp = np.zeros((m, ld))
+    Jp[:, :n] = J
+    lam = 0.25
+    K = D().gram(torch.tensor(Jp, device="cuda"), n, lam).cpu().numpy()
+    ref = S.gram(J) + lam * np.eye(m)
+    low = np.tril_indices(m)
+    assert np.abs(K[low] - ref[low]).max() <= 1e-12 * np.abs(ref).max()
+    assert np.all(np.triu(K, 1) == 0.0)
+
+
+@pytest.mark.parametrize("passes", [1, 3])
+@pytest.mark.parametrize("m,n", [(70, 333), (300, 5003), (700, 20000)])
+def test_gram_bf16(m, n, passes):
+    say("case gram_bf16", m, n, passes)
+    rng = np.random.default_rng(m + n + passes)
+    J = (rng.standard_normal((m, n)) * rng.uniform(0.1, 3.0, size=(m, 1))).astype(np.float32)
+    ld = (n + 3) // 4 * 4
+    Jp = np.zeros((m, ld), dtype=np.float32)
+    Jp[:, :n] = J
+    K = D().gram(torch.tensor(Jp, device="cuda"), n, 0.0, passes=passes).cpu().numpy()
+    Jt = torch.tensor(J)
+    hi = Jt.to(torch.bfloat16).to(torch.float64)
+    lo = (Jt - hi.to(torch.float32)).to(torch.bfloat16).to(torch.float64)
+    if passes == 1:
+        ref = (hi @ hi.T).numpy()
+    else:
+        ref = (hi @ hi.T + hi @ lo.T + lo @ hi.T).numpy()
+    a = np.abs(J.astype(np.float64))
+    bound = (a @ a.T) * (n ** 0.5 * 2.0 ** -22) + 1e-30   # FP32 accumulation
+    low = np.tril_indices(m)
+    assert np.all(np.abs(K[low] - ref[low]) <= bound[low])
+    # and the split really carries ~16 bits: distance to the exact FP64 Gram
+    exact = J.astype(np.float64) @ J.astype(np.float64).T
+    err = np.abs(K[low] - exact[low]).max() / np.abs(exact).max()
+    assert err <= (2e-2 if passes == 1 else 2e-4), err
+
+
+@pytest.mark.parametrize("m", [1, 2, 63, 64, 65, 130, 700])
+def test_cholesky_solve(m):
+    say("case cholesky_solve", m)
+    rng = np.random.default_rng(m)
+    B = rng.standard_normal((m, m + 5))
+    A = B @ B.T / (m + 5) + 0.1 * np.eye(m)
+    rhs = rng.standard_normal((2, m))
+    K = torch.tensor(A, device="cuda")
+    X = torch.tensor(rhs, device="cuda").contiguous()
+    info = D().cholesky_solve(K, X)
+    assert info == 0
+    ref = sla.cho_solve(sla.cho_factor(A, lower=True), rhs.T).T
+    assert rel(X.cpu().numpy(), ref) <= 1e-12
+    L = np.tril(K.cpu().numpy())
+    assert np.abs(L @ L.T - A).max() <= 1e-12 * np.abs(A).max()
+    # a second solve with the stored factor
+    X2 = torch.tensor(rhs[:1], device="cuda").contiguous()
+    assert D().cholesky_solve(K, X2, factored=True) == 0
+    assert rel(X2.cpu().numpy(), ref[:1]) <= 1e-12
+
+
+def test_cholesky_reports_failing_pivot():
+    say("case cholesky_not_pd")
+    m = 150
+    A = np.eye(m)
+    A[97, 97] = -1.0
+    K = torch.tensor(A, device="cuda")
+    X = torch.ones(1, m, dtype=torch.float64, device="cuda")
+    assert D().cholesky_solve(K, X) == 98
+
+
+@pytest.mark.parametrize("kind", ["poisson", "heat", "poisson5"])
+@pytest.mark.parametrize("prec", ["plain", "mixed"])
+def test_step_small(kind, prec):
+    p = tiny(kind)
+    th = rand_theta(p.widths, 8, 0.5)
+    lam = 1e-3
+    say("case step_small", kind, prec)
+    d = D()
+    prob = d.Problem.from_workload(p)
+    ref = S.dense_step(p, th, lam, ga=True)
+    o = d.step_opts(precision=d.PLAIN if prec == "plain" else d.MIXED, ga=True, gram_passes=3)
+    dth, st = prob.step(th, lam, o)
+    tol = 1e-10 if prec == "plain" else 1e-4
+    assert rel(dth.cpu().numpy(), ref.dtheta) <= tol
+    assert st.ga_accepted == int(ref.accepted)
+
+
+def test_losses_match_oracle():
+    p = tiny("heat")
+    th = rand_theta(p.widths, 9, 0.5)
+    dth = rand_theta(p.widths, 10, 0.1)
+    say("case losses")
+    prob = D().Problem.from_workload(p)
+    etas = [1.0, 0.5, 0.25, 2.0 ** -30]
+    got = prob.losses(th, dth, etas)
+    ref = [N.loss(p, th + e * dth) for e in etas]
+    assert rel(got, ref) <= 1e-12
