@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""D-NGD step benchmark on one MI355X.
+
+Workload: the 5-D Poisson problem -lap u = f on [0,1]^5 with
+u* = sum_i sin(pi x_i / 2), tanh MLP 5-256-256-256-1 (133,377 parameters),
+4,000 interior + 1,000 boundary uniform points (m = 5,000), Glorot init,
+lambda = min(L(theta_0), 1e-5). Inputs are seeded synthetic data built by
+``workloads`` and are resident in HBM before timing starts.
+
+A step is one call of the dense dual solver with geodesic acceleration
+(dngd_step): residual and Jacobian, Gram, Cholesky, solves with refinement,
+velocity, f_vv, acceleration and the acceptance rule. ``value`` is mixed
+precision steps/s (FP32 J, BF16-MFMA Gram, FP64 Cholesky + 2 refinement
+sweeps); the plain FP64 path is timed on the same GPU and reported beside it,
+as are the 31-point line search and the resulting optimiser iterations/s.
+
+Prints one JSON line. ``--gpus N`` with N > 1 is refused: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16
+MFMA_F64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--gram-passes", type=int, default=0)
+    ap.add_argument("--ir-sweeps", type=int, default=2)
+    ap.add_argument("--only-mixed", action="store_true", help="profiling: mixed steps only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="profiling: 3 device copies of 1 GiB (calibrates the HBM byte counters)")
+    return ap.parse_args()
+
+
+def copy_calibration(torch):
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": x.numel() * 8, "launches": 3}))
+
+
+def timed_steps(prob, th, lam, opts, steps, warmup, torch):
+    for _ in range(warmup):
+        prob.step(th, lam, opts)
+    torch.cuda.synchronize()
+    walls, stats = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        dth, st = prob.step(th, lam, opts)   # synchronises its stream before returning
+        walls.append((time.perf_counter() - s0) * 1e3)
+        stats.append(st.as_dict())
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return total, walls, stats, dth
+
+
+def p99(xs):
+    xs = sorted(xs)
+    k = max(0, min(len(xs) - 1, int(round(0.99 * (len(xs) - 1)))))
+    return xs[k]
+
+
+def cpu_baseline(seed_theta, lam, frac=5):
+    """The oracle (unchanged) timed on the host cores on a bounded sample: the
+    same network and parameters with 1/frac of the collocation points
+    (m = 1000 of 5000). Each phase is timed and scaled to m = 5000 by its
+    cost in m: residual, Jacobian, f_vv and J^T products ~ m, Gram and
+    triangular solves ~ m^2, Cholesky ~ m^3."""
+    import numpy as np
+    import scipy.linalg as sla
+    from threadpoolctl import threadpool_info
+    import workloads as W
+    from oracle import network as N, step as S
+    full = W.config(1)
+    p = W.config(1, scale=dict(n_int=full.n_int // frac, n_bdy=full.n_bdy // frac))
+    th = seed_theta
+    t = {}
+
+    def clock(name, fn):
+        t0 = time.perf_counter()
+        out = fn()
+        t[name] = time.perf_counter() - t0
+        return out
+
+    r = clock("residual", lambda: N.residual(p, th))
+    J = clock("jacobian", lambda: N.jacobian(p, th))
+    K = clock("gram", lambda: S.gram(J))
+    ch = clock("cholesky", lambda: S.cholesky(K, lam))
+    alpha = clock("solve_v", lambda: S.solve(ch, r))
+    v = clock("jt_v", lambda: -(J.T @ alpha))
+    f = clock("fvv", lambda: N.fvv(p, th, v))
+    beta = clock("solve_a", lambda: S.solve(ch, f))
+    clock("jt_a", lambda: -(J.T @ beta))
+    s = float(frac)
+    scale = {"residual": s, "jacobian": s, "gram": s * s, "cholesky": s ** 3, "solve_v": s * s,
+             "jt_v": s, "fvv": s, "solve_a": s * s, "jt_a": s}
+    est = sum(t[k] * scale[k] for k in t)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": 1.0 / est, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle dense step (r, J, K, Cholesky, v, f_vv, a) on m={p.m} of the "
+                      f"m=5000 points (same network, n=133377); phases timed "
+                      f"{ {k: round(x, 3) for k, x in t.items()} } s, scaled by m, m^2, m^3 "
+                      f"to m=5000: {est:.1f} s/step"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: --gpus {a.gpus} refused: this build runs the D-NGD step on one GPU "
+              "only (no multi-GPU path).", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    if a.copy_calibration:
+        copy_calibration(torch)
+        return 0
+    import workloads as W
+    from paper_2505_21404_amd import dngd as D
+
+    p = W.config(1)
+    th0 = W.glorot_theta(p.widths, 0)
+    prob = D.Problem.from_workload(p)
+    th = torch.tensor(th0, device="cuda")
+    r0 = prob.residual(th)
+    L0 = 0.5 * float((r0 * r0).sum())
+    lam = min(L0, W.LAMBDA_CAP[1])
+
+    mixed = D.step_opts(precision=D.MIXED, ga=True, ir_sweeps=a.ir_sweeps,
+                        gram_passes=a.gram_passes)
+    tot, walls, stats, dth_mixed = timed_steps(prob, th, lam, mixed, a.steps, a.warmup, torch)
+    if a.only_mixed:
+        print(json.dumps({"steps": a.steps, "ms_per_step": tot * 1e3 / a.steps}))
+        return 0
+
+    m, n = prob.m, prob.n
+    gram_flops = float(m) * (m + 1) * n       # algorithmic: lower-triangle syrk
+    gk = [s["ms_gram_kernel"] for s in stats]
+    gk_avg = sum(gk) / len(gk)
+    achieved = gram_flops / (gk_avg * 1e-3) / 1e12
+
+    out = {
+        "metric": "D-NGD steps/s (mixed vs FP64 plain, same GPU); Gram TFLOP/s; p99 step ms",
+        "value": a.steps / tot,
+        "unit": "steps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": tot * 1e3 / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-mfma/f32-J/f64-solve",
+        "data": "synthetic (seeded uniform collocation points, Glorot init)",
+        "config": {"workload": "poisson5d_mlp5-256x3-1_m5000_dense_ga", "m": m, "n": n,
+                   "lambda": lam, "gram_passes": stats[-1]["gram_passes_used"],
+                   "ir_sweeps": a.ir_sweeps},
+        "p50_step_ms": statistics.median(walls),
+        "p99_step_ms": p99(walls),
+        "gram_tflops": achieved,
+        "phase_ms_median": {k: statistics.median(s[k] for s in stats) for k in (
+            "ms_residual_jacobian", "ms_gram", "ms_gram_kernel", "ms_factor", "ms_solve_v",
+            "ms_fvv", "ms_solve_a")},
+        "ir_residual": stats[-1]["ir_residual"][:a.ir_sweeps],
+        "ga_accepted": stats[-1]["ga_accepted"],
+        "roofline": {"bound": "mfma", "kernel": "gram_bf16_kernel", "achieved": achieved,
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_launch": gram_flops, "avg_launch_ms": gk_avg},
+    }
+
+    if not a.no_plain:
+        plain = D.step_opts(precision=D.PLAIN, ga=True)
+        ptot, pwalls, pstats, dth_plain = timed_steps(prob, th, lam, plain, a.plain_steps, 1,
+                                                      torch)
+        pg = statistics.median(s["ms_gram_kernel"] for s in pstats)
+        out["plain"] = {"steps_per_s": a.plain_steps / ptot, "p50_step_ms": statistics.median(pwalls),
+                        "p99_step_ms": p99(pwalls),
+                        "gram_tflops": gram_flops / (pg * 1e-3) / 1e12,
+                        "gram_frac_of_f64_peak": gram_flops / (pg * 1e-3) / 1e12 / MFMA_F64_PEAK_TFLOPS,
+                        "phase_ms_median": {k: statistics.median(s[k] for s in pstats) for k in (
+                            "ms_residual_jacobian", "ms_gram", "ms_factor", "ms_solve_v",
+                            "ms_fvv", "ms_solve_a")}}
+        out["speedup_mixed_vs_plain"] = out["value"] / out["plain"]["steps_per_s"]
+        dm, dp = dth_mixed.cpu().numpy(), dth_plain.cpu().numpy()
+        out["mixed_vs_plain_rel_err"] = float(np.linalg.norm(dm - dp) / np.linalg.norm(dp))
+
+    # line search (31 points, D-NGD workflow) and full optimiser iterations/s
+    etas = [2.0 ** -k for k in range(31)]
+    ls = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        prob.losses(th, dth_mixed, etas)
+        ls.append((time.perf_counter() - t0) * 1e3)
+    out["line_search_ms"] = statistics.median(ls)
+    out["optimizer_iters_per_s"] = 1e3 / (out["ms_per_step"] + out["line_search_ms"])
+
+    # parity against the stored oracle step of this workload (tests/golden)
+    gold = os.path.join(ROOT, "tests", "golden", "config1_step.npz")
+    if os.path.exists(gold):
+        g = np.load(gold)
+        if abs(float(g["lam"]) - lam) <= 1e-12 * lam:
+            ref = g["dtheta"]
+            dm = dth_mixed.cpu().numpy()
+            out["mixed_vs_oracle_rel_err"] = float(np.linalg.norm(dm - ref) / np.linalg.norm(ref))
+            if "plain" in out:
+                dp = dth_plain.cpu().numpy()
+                out["plain_vs_oracle_rel_err"] = float(np.linalg.norm(dp - ref)
+                                                       / np.linalg.norm(ref))
+
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(th0, lam)
+    print(json.dumps(out), flush=True)
+    prob.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

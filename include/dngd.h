@@ -107,6 +107,7 @@ typedef struct {
   double ir_residual[8];      /* mixed: ||s_k|| / ||b|| before sweep k (k < ir_sweeps), v solve */
   double max_row_norm2;       /* max_i ||J_i||^2 (mixed path) */
   double pcg_rel_residual;    /* PCG: final recursive ||r|| / ||b|| */
+  double ms_gram_kernel;      /* the Gram contraction kernel alone (HIP events on `stream`) */
 } dngd_step_stats;
 
 const char* dngd_last_error(void);

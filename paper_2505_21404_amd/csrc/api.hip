@@ -55,11 +55,10 @@ struct dngd_problem {
   // tangent streams (lazy)
   double *Z1 = nullptr, *Z2 = nullptr, *A1[2] = {nullptr, nullptr}, *A2[2] = {nullptr, nullptr};
   // step / solver workspace (lazy, grown on demand)
-  DevBuf J, K, vecs, work, gram_work, flags_buf, small;
+  DevBuf J, K, vecs, work, gram_work, solve_aux, small;
   int J_dtype = -1;
   int64_t ldJ = 0, ldK = 0;
-  unsigned epoch = 0;
-  hipEvent_t ev[8] = {nullptr};
+  hipEvent_t ev[10] = {nullptr};
 };
 
 namespace {
@@ -264,7 +263,7 @@ int vjp(dngd_problem* h, const double* theta, const double* p, double* gout, hip
 
 struct StepVecs {
   double *r, *alpha, *s, *fvv, *beta, *tmpm, *rownorm2;  // m each
-  double *v, *a, *t, *thtmp;                              // n each
+  double *v, *a, *t, *thtmp;                                      // n each
   double* red;   // reduction scratch (256 doubles)
   double* scal;  // 64 device scalars
   double* gemv_work;
@@ -305,41 +304,31 @@ int carve_vecs(dngd_problem* h, StepVecs& v) {
   return 0;
 }
 
-// small device block: solve flags, status, info
+// small device block: Cholesky info and the GA acceptance flag
 struct Small {
-  unsigned* flags;
-  int* status;
   int64_t* info;
   int* ga_flag;
 };
 
-int carve_small(dngd_problem* h, int64_t mmax, Small& sm) {
-  const size_t nflags = (size_t)chol_solve_flag_count(std::max<int64_t>(mmax, 1));
-  const size_t bytes = nflags * sizeof(unsigned) + 64;
-  if (h->small.bytes < bytes) {
-    int rc = ensure(h, h->small, bytes);
-    if (rc) return rc;
-    DNGD_HIP(hipMemset(h->small.p, 0, bytes));  // flags start at epoch 0
-    h->epoch = 0;
-  }
+int carve_small(dngd_problem* h, Small& sm) {
+  int rc = ensure(h, h->small, 64);
+  if (rc) return rc;
   char* p = static_cast<char*>(h->small.p);
-  sm.status = reinterpret_cast<int*>(p);
+  sm.info = reinterpret_cast<int64_t*>(p);
   sm.ga_flag = reinterpret_cast<int*>(p + 8);
-  sm.info = reinterpret_cast<int64_t*>(p + 16);
-  sm.flags = reinterpret_cast<unsigned*>(p + 64);
   return 0;
 }
 
-__global__ void zero_i32_kernel(int* p) { *p = 0; }
 
 int dense_solve(dngd_problem* h, const StepVecs& v, const Small& sm, const double* rhs, double* x,
                 double lambda, int ir_sweeps, const void* J, int j_dtype, double* ir_out,
                 hipStream_t s) {
   const Geometry& g = h->g;
   double* K = static_cast<double*>(h->K.p);
+  const double* aux = static_cast<const double*>(h->solve_aux.p);
   int rc = copy(s, g.m, rhs, x);
   if (rc) return rc;
-  rc = chol_solve(s, g.m, K, h->ldK, x, sm.flags, &h->epoch, sm.status, nullptr);
+  rc = chol_solve(s, g.m, K, h->ldK, aux, x);
   if (rc) return rc;
   for (int k = 0; k < ir_sweeps; ++k) {
     // s = rhs - (J (J^T x) + lambda x), computed with FP32/FP64 J and FP64 accumulation
@@ -351,7 +340,7 @@ int dense_solve(dngd_problem* h, const StepVecs& v, const Small& sm, const doubl
       rc = sumsq(s, g.m, v.s, ir_out + k, v.red);
       if (rc) return rc;
     }
-    rc = chol_solve(s, g.m, K, h->ldK, v.s, sm.flags, &h->epoch, sm.status, nullptr);
+    rc = chol_solve(s, g.m, K, h->ldK, aux, v.s);
     if (rc) return rc;
     rc = axpy(s, g.m, 1.0, v.s, x);
     if (rc) return rc;
@@ -363,7 +352,8 @@ int dense_solve(dngd_problem* h, const StepVecs& v, const Small& sm, const doubl
 struct Precond {
   double* Mt = nullptr;  // ell x m   (L_I^{-1} K_{I,:})
   double* G = nullptr;   // ell x ell (lambda I + Mt Mt^T, Cholesky factor)
-  double* tl = nullptr;  // ell scratch vector
+  double* tl = nullptr;    // ell scratch vector
+  double* Gaux = nullptr;  // solve workspace for chol(G)
   int64_t ldM = 0;
   double delta = 0;
   int64_t ell = 0;
@@ -469,7 +459,7 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   if (!rc) rc = dmalloc(h, (void**)&h->Ab[1], act_bytes(g));
   if (!rc) rc = dmalloc(h, (void**)&h->seed, (size_t)g.R * sizeof(double));
   if (!rc) rc = dmalloc(h, (void**)&h->U, (size_t)g.R * sizeof(double));
-  for (int e = 0; e < 8 && !rc; ++e)
+  for (int e = 0; e < 10 && !rc; ++e)
     if (hipEventCreate(&h->ev[e]) != hipSuccess) rc = DNGD_EHIP;
   if (rc) {
     dngd_problem_destroy(h);
@@ -509,12 +499,13 @@ int dngd_footprint(const dngd_problem* h, const dngd_step_opts* o, size_t* bytes
     const int jd = (o->precision == DNGD_PLAIN) ? DNGD_F64 : DNGD_F32;
     const int64_t ldJ = round_up(g.n, 256);
     b += (size_t)g.m * ldJ * (jd == DNGD_F64 ? 8 : 4);
-    b += (size_t)g.m * g.m * 8;
+    b += (size_t)g.m * g.m * 8 + chol_solve_aux_bytes(g.m) + 64;
     b += gram_workspace_bytes(g.m, g.n, jd, 3, nullptr);
   } else {
     const int64_t ell = o->n_landmarks;
     const int64_t ldJ = round_up(g.n, 256);
-    b += (size_t)ell * ldJ * 8 + (size_t)ell * g.m * 8 + (size_t)ell * ell * 8;
+    b += (size_t)ell * ldJ * 8 + (size_t)ell * g.m * 8 + (size_t)ell * ell * 8 +
+         chol_solve_aux_bytes(ell);
     b += (size_t)std::min<int64_t>(g.m, 256) * ldJ * 8;
   }
   *bytes = b;
@@ -563,15 +554,11 @@ int dngd_cholesky_solve(int64_t m, double* K, int64_t ldK, int32_t factored, int
                "dngd_cholesky_solve: bad sizes");
   hipStream_t s = S(stream);
   *info = 0;
-  const size_t nflags = (size_t)chol_solve_flag_count(m);
   char* scratch = nullptr;
-  const size_t bytes = 64 + nflags * sizeof(unsigned);
+  const size_t bytes = 64 + chol_solve_aux_bytes(m);
   DNGD_HIP(hipMallocAsync((void**)&scratch, bytes, s));
-  DNGD_HIP(hipMemsetAsync(scratch, 0, bytes, s));
-  int* status = reinterpret_cast<int*>(scratch);
-  int64_t* dinfo = reinterpret_cast<int64_t*>(scratch + 16);
-  unsigned* flags = reinterpret_cast<unsigned*>(scratch + 64);
-  unsigned epoch = 0;
+  int64_t* dinfo = reinterpret_cast<int64_t*>(scratch);
+  double* aux = reinterpret_cast<double*>(scratch + 64);
   int rc = 0;
   if (!factored) {
     rc = chol_factor(s, m, K, ldK, dinfo, nullptr);
@@ -581,25 +568,15 @@ int dngd_cholesky_solve(int64_t m, double* K, int64_t ldK, int32_t factored, int
       if (e != hipSuccess) rc = hip_fail(e, "info readback", __FILE__, __LINE__);
     }
   }
-  if (!rc && *info == 0) {
-    for (int64_t j = 0; j < nrhs && !rc; ++j)
-      rc = chol_solve(s, m, K, ldK, B + j * ldB, flags, &epoch, status, nullptr);
-  }
-  int hstatus = 0;
-  if (!rc && nrhs > 0 && *info == 0) {
-    hipError_t e = hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) rc = hip_fail(e, "status readback", __FILE__, __LINE__);
+  if (!rc && *info == 0 && nrhs > 0) {
+    rc = chol_prepare_solve(s, m, K, ldK, aux);
+    for (int64_t j = 0; j < nrhs && !rc; ++j) rc = chol_solve(s, m, K, ldK, aux, B + j * ldB);
   }
   hipFreeAsync(scratch, s);
   if (rc) return rc;
   if (*info != 0) {
     set_error("Cholesky: non-positive pivot at column %lld", (long long)*info);
     return DNGD_ENOTPD;
-  }
-  if (hstatus) {
-    set_error("triangular solve: inter-workgroup wait timed out");
-    return DNGD_ETIMEOUT;
   }
   return DNGD_OK;
 }
@@ -683,7 +660,7 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
   const size_t bCh = (size_t)chunk * ldJ * 8, bIdx = (size_t)std::max<int64_t>(chunk, ell) * 8;
   int rc = ensure(h, h->J, bJI + bCh);
   if (rc) return rc;
-  rc = ensure(h, h->K, bMt + bG + bIdx + (size_t)ell * 8);
+  rc = ensure(h, h->K, bMt + bG + bIdx + (size_t)ell * 8 + chol_solve_aux_bytes(ell));
   if (rc) return rc;
   double* JI = static_cast<double*>(h->J.p);
   double* Jc = JI + (size_t)ell * ldJ;
@@ -692,6 +669,7 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
   P.G = P.Mt + (size_t)ell * ldM;
   int64_t* idx = reinterpret_cast<int64_t*>(P.G + (size_t)ell * ell);
   P.tl = reinterpret_cast<double*>(idx + std::max<int64_t>(chunk, ell));
+  P.Gaux = P.tl + ell;
   P.ell = ell;
   P.lambda = lambda;
   StepVecs v;
@@ -754,7 +732,7 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
   DNGD_HIP(hipMemcpyAsync(&hinfo, v.scal, 8, hipMemcpyDeviceToHost, s));
   DNGD_HIP(hipStreamSynchronize(s));
   DNGD_REQUIRE(hinfo == 0, "Nystrom: lam I + M^T M not positive definite");
-  return 0;
+  return chol_prepare_solve(s, ell, P.G, ell, P.Gaux);
 }
 
 // z = P^{-1} x
@@ -764,7 +742,7 @@ int precond_apply(dngd_problem* h, const Precond& P, const StepVecs& v, const Sm
   // tl = -(M^T x)
   int rc = gemv_n_residual(s, P.ell, g.m, P.Mt, P.ldM, DNGD_F64, x, nullptr, nullptr, 0.0, tl);
   if (rc) return rc;
-  rc = chol_solve(s, P.ell, P.G, P.ell, tl, sm.flags, &h->epoch, sm.status, nullptr);
+  rc = chol_solve(s, P.ell, P.G, P.ell, P.Gaux, tl);
   if (rc) return rc;
   // z = M tl = -(M (lam + M^T M)^{-1} M^T x); finish: z = (x + z_neg...) handled by sign
   rc = gemv_t(s, P.ell, g.m, P.Mt, P.ldM, DNGD_F64, tl, -1.0, z, v.gemv_work);
@@ -864,10 +842,9 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda, const 
   StepVecs v;
   Small sm;
   int rc = carve_vecs(h, v);
-  if (!rc) rc = carve_small(h, std::max<int64_t>(h->g.m, ell), sm);
+  if (!rc) rc = carve_small(h, sm);
   if (!rc) rc = forward(h, theta, nullptr, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, sm.status);
   Precond P;
   rc = pcg_build(h, theta, lambda, landmarks, ell, P, s);
   if (rc) return rc;
@@ -875,17 +852,11 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda, const 
   double rel = 1.0;
   const int st = pcg_solve(h, theta, P, v, sm, b, x, tol, maxit, &its, &rel, s);
   if (st < 0) return st;
-  int hstatus = 0;
-  DNGD_HIP(hipMemcpyAsync(&hstatus, sm.status, sizeof(int), hipMemcpyDeviceToHost, s));
   DNGD_HIP(hipStreamSynchronize(s));
   if (stats) {
     stats->pcg_iterations = its;
     stats->pcg_converged = (st == DNGD_OK);
     stats->pcg_rel_residual = rel;
-  }
-  if (hstatus) {
-    set_error("triangular solve: inter-workgroup wait timed out");
-    return DNGD_ETIMEOUT;
   }
   return st;
 }
@@ -906,11 +877,10 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   StepVecs v;
   Small sm;
   int rc = carve_vecs(h, v);
-  if (!rc) rc = carve_small(h, std::max<int64_t>(g.m, o.solver == DNGD_PCG ? o.n_landmarks : 0), sm);
+  if (!rc) rc = carve_small(h, sm);
   if (rc) return rc;
   dngd_step_stats st;
   std::memset(&st, 0, sizeof(st));
-  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, sm.status);
   DNGD_HIP(hipEventRecord(h->ev[0], s));
 
   if (o.solver == DNGD_PCG) {
@@ -940,8 +910,6 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     DNGD_HIP(hipEventSynchronize(h->ev[7]));
     double vn2 = 0;
     DNGD_HIP(hipMemcpy(&vn2, v.scal + 8, 8, hipMemcpyDeviceToHost));
-    int hstatus = 0;
-    DNGD_HIP(hipMemcpy(&hstatus, sm.status, sizeof(int), hipMemcpyDeviceToHost));
     float ms = 0;
     hipEventElapsedTime(&ms, h->ev[0], h->ev[7]);
     st.ms_total = ms;
@@ -954,10 +922,6 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     st.pcg_converged = (pst == DNGD_OK);
     st.pcg_rel_residual = rel;
     if (stats) *stats = st;
-    if (hstatus) {
-      set_error("triangular solve: inter-workgroup wait timed out");
-      return DNGD_ETIMEOUT;
-    }
     return pst;
   }
 
@@ -1000,12 +964,16 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   st.gram_passes_used = passes;
   const size_t gw = gram_workspace_bytes(g.m, g.n, jd, passes, nullptr);
   rc = ensure(h, h->gram_work, gw);
-  if (!rc) rc = gram_launch(s, g.m, g.n, J, ldJ, jd, passes, lambda, K, g.m, h->gram_work.p, gw);
+  if (!rc)
+    rc = gram_launch(s, g.m, g.n, J, ldJ, jd, passes, lambda, K, g.m, h->gram_work.p, gw, h->ev[8],
+                     h->ev[9]);
   if (rc) return rc;
   DNGD_HIP(hipEventRecord(h->ev[2], s));
 
   // Cholesky of K + lam I
-  rc = chol_factor(s, g.m, K, g.m, sm.info, nullptr);
+  rc = ensure(h, h->solve_aux, chol_solve_aux_bytes(g.m));
+  if (!rc) rc = chol_factor(s, g.m, K, g.m, sm.info, nullptr);
+  if (!rc) rc = chol_prepare_solve(s, g.m, K, g.m, static_cast<double*>(h->solve_aux.p));
   if (rc) return rc;
   DNGD_HIP(hipEventRecord(h->ev[3], s));
 
@@ -1043,9 +1011,8 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   double sc[32];
   DNGD_HIP(hipMemcpy(sc, v.scal, sizeof(sc), hipMemcpyDeviceToHost));
   int64_t info = 0;
-  int hstatus = 0, gaf = 0;
+  int gaf = 0;
   DNGD_HIP(hipMemcpy(&info, sm.info, 8, hipMemcpyDeviceToHost));
-  DNGD_HIP(hipMemcpy(&hstatus, sm.status, sizeof(int), hipMemcpyDeviceToHost));
   DNGD_HIP(hipMemcpy(&gaf, sm.ga_flag, sizeof(int), hipMemcpyDeviceToHost));
   float ms = 0;
   hipEventElapsedTime(&ms, h->ev[0], h->ev[6]);
@@ -1054,6 +1021,8 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   st.ms_residual_jacobian = ms;
   hipEventElapsedTime(&ms, h->ev[1], h->ev[2]);
   st.ms_gram = ms;
+  hipEventElapsedTime(&ms, h->ev[8], h->ev[9]);
+  st.ms_gram_kernel = ms;
   hipEventElapsedTime(&ms, h->ev[2], h->ev[3]);
   st.ms_factor = ms;
   hipEventElapsedTime(&ms, h->ev[3], h->ev[4]);
@@ -1073,10 +1042,6 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   if (info != 0) {
     set_error("Cholesky of K + lambda I: non-positive pivot at column %lld", (long long)info);
     return DNGD_ENOTPD;
-  }
-  if (hstatus) {
-    set_error("triangular solve: inter-workgroup wait timed out");
-    return DNGD_ETIMEOUT;
   }
   if (!std::isfinite(st.vnorm) || !std::isfinite(st.anorm)) {
     set_error("non-finite step");

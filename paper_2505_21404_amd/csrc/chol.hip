@@ -2,23 +2,18 @@
 // K~ = K + lambda I and the forward / backward substitutions.
 //
 // Factorisation: right-looking, block width 64.
-//   panel kernel  one wave per 64 rows of the current block column. Every
-//                 wave factors the 64 x 64 diagonal block in LDS (left-looking
-//                 by columns, lane i owns row i), wave 0 writes L11, the others
-//                 solve their rows of L21 = A21 L11^-T by substitution.
+//   panel kernel  one 256-thread workgroup per 64 rows of the current block
+//                 column. Every workgroup factors the 64 x 64 diagonal block
+//                 in LDS (left-looking by columns, 4 lanes per row sharing each
+//                 dot product), workgroup 0 writes L11 and the reciprocal
+//                 pivots, the others solve their rows of L21 = A21 L11^-T.
 //   update        A22 -= L21 L21^T on the FP64 matrix cores (lower tiles).
 // A non-positive or non-finite pivot records its 1-based column in *info
 // (first failure wins) and poisons the rest of the factor with NaN.
 //
-// Substitutions: one kernel per triangle. Workgroup q owns the 64-row block q.
-// It accumulates L[q, k] y_k for every earlier block k as soon as block k has
-// published y_k (a per-block flag set with release semantics after the data
-// is written), then solves its 64 x 64 diagonal block in one wave with
-// readlane broadcasts and publishes y_q. Workgroup q only ever waits on
-// workgroups with a smaller index, which are dispatched first; the grid is at
-// most m/64 workgroups. Every wait is bounded: after ~2^24 polls the
-// workgroup records DNGD_ETIMEOUT in *status, still publishes its flag (so the
-// rest of the grid drains) and the host reports the failure.
+// Solves: blocked forward / backward substitution with inverted diagonal
+// blocks (see chol_prepare_solve below); every kernel is independent of the
+// others' progress (no inter-workgroup waiting).
 #include "common.h"
 
 namespace dngd {
@@ -27,42 +22,60 @@ namespace {
 
 constexpr int NB = 64;
 
-__device__ inline double readlane_d(double x, int lane) {
-  union {
-    double d;
-    int i[2];
-  } u, o;
-  u.d = x;
-  o.i[0] = __builtin_amdgcn_readlane(u.i[0], lane);
-  o.i[1] = __builtin_amdgcn_readlane(u.i[1], lane);
-  return o.d;
+// 256 threads: row i of the 64-row block is owned by the 4 lanes 4i..4i+3 of
+// one wave, each summing every 4th term of a dot product; two xor-shuffles
+// complete the sum in all 4 lanes.
+__device__ inline double dot4(const double* a, const double* b, int len, int sub) {
+  double s0 = 0.0, s1 = 0.0;
+  int k = sub;
+  for (; k + 4 < len; k += 8) {
+    s0 += a[k] * b[k];
+    s1 += a[k + 4] * b[k + 4];
+  }
+  if (k < len) s0 += a[k] * b[k];
+  double s = s0 + s1;
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  return s;
 }
 
-__global__ __launch_bounds__(64) void potrf_panel_kernel(int64_t m, double* __restrict__ K,
-                                                         int64_t ldK, int64_t j0,
-                                                         int64_t* __restrict__ info) {
+__global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __restrict__ K,
+                                                          int64_t ldK, int64_t j0,
+                                                          int64_t* __restrict__ info,
+                                                          double* __restrict__ dinv) {
   // Ld: the diagonal block, factored in place (lower part). X: this
   // workgroup's 64 panel rows below it (workgroups >= 1).
   __shared__ double Ld[NB][NB + 1];
   __shared__ double X[NB][NB + 1];
-  const int lane = threadIdx.x;
+  __shared__ double rinv[NB];
+  __shared__ double sdiag;
+  const int t = threadIdx.x;
+  const int row = t >> 2, sub = t & 3;
   const int nb = (int)min<int64_t>(NB, m - j0);
 
-  // ---- load the diagonal block (identity padding beyond m)
-  for (int k = 0; k < NB; ++k) {
-    double v = 0.0;
-    if (lane < nb && k <= lane && k < nb) v = K[(j0 + lane) * ldK + j0 + k];
-    if (lane >= nb && k == lane) v = 1.0;
-    Ld[lane][k] = v;
+  // ---- load the diagonal block, coalesced (identity padding beyond m)
+  {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = q * 256 + t, i = e / NB, k = e % NB;
+      v[q] = (i < nb && k <= i) ? K[(j0 + i) * ldK + j0 + k] : ((i >= nb && k == i) ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = q * 256 + t;
+      Ld[e / NB][e % NB] = v[q];
+    }
   }
   __syncthreads();
-  // ---- left-looking factorisation, lane i owns row i:
+  // ---- left-looking factorisation by columns:
   //      s_i = A_ij - sum_{k<j} L_ik L_jk ;  L_jj = sqrt(s_j) ;  L_ij = s_i / L_jj
   int bad = -1;
   for (int j = 0; j < NB; ++j) {
-    double sij = Ld[lane][j];
-    for (int k = 0; k < j; ++k) sij -= Ld[lane][k] * Ld[j][k];
-    const double d = __shfl(sij, j);
+    const double sij = Ld[row][j] - dot4(&Ld[row][0], &Ld[j][0], j, sub);
+    if (row == j && sub == 0) sdiag = sij;
+    __syncthreads();
+    const double d = sdiag;
     double ljj;
     if (d > 0.0 && __builtin_isfinite(d)) {
       ljj = sqrt(d);
@@ -70,147 +83,171 @@ __global__ __launch_bounds__(64) void potrf_panel_kernel(int64_t m, double* __re
       if (bad < 0) bad = j;
       ljj = __builtin_nan("");
     }
-    if (lane == j) Ld[lane][j] = ljj;
-    else if (lane > j) Ld[lane][j] = sij / ljj;
+    const double inv = 1.0 / ljj;
+    if (sub == 0) {
+      if (row == j) {
+        Ld[j][j] = ljj;
+        rinv[j] = inv;
+      } else if (row > j) {
+        Ld[row][j] = sij * inv;
+      }
+    }
     __syncthreads();
   }
 
   if (blockIdx.x == 0) {
-    if (lane < nb)
-      for (int k = 0; k <= lane; ++k) K[(j0 + lane) * ldK + j0 + k] = Ld[lane][k];
-    if (lane == 0 && bad >= 0 && bad < nb) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = q * 256 + t, i = e / NB, k = e % NB;
+      if (i < nb && k <= i) K[(j0 + i) * ldK + j0 + k] = Ld[i][k];
+    }
+    if (t < nb && dinv) dinv[j0 + t] = rinv[t];
+    if (t == 0 && bad >= 0 && bad < nb) {
       unsigned long long* p = reinterpret_cast<unsigned long long*>(info);
       atomicCAS(p, 0ull, (unsigned long long)(j0 + bad + 1));
     }
     return;
   }
 
-  // ---- L21 rows: x L11^T = a  (forward substitution; lane owns one row)
-  const int64_t row = j0 + (int64_t)blockIdx.x * NB + lane;
-  const bool rok = row < m;
-  for (int k = 0; k < NB; ++k) X[lane][k] = (rok && k < nb) ? K[row * ldK + j0 + k] : 0.0;
+  // ---- L21 rows: x L11^T = a  (forward substitution; 4 lanes per row)
+  const int64_t r0 = j0 + (int64_t)blockIdx.x * NB;
+  {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = q * 256 + t, i = e / NB, k = e % NB;
+      v[q] = (r0 + i < m && k < nb) ? K[(r0 + i) * ldK + j0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = q * 256 + t;
+      X[e / NB][e % NB] = v[q];
+    }
+  }
   __syncthreads();
   for (int j = 0; j < NB; ++j) {
-    double sx = X[lane][j];
-    for (int k = 0; k < j; ++k) sx -= X[lane][k] * Ld[j][k];
-    X[lane][j] = sx / Ld[j][j];
+    const double x = (X[row][j] - dot4(&X[row][0], &Ld[j][0], j, sub)) * rinv[j];
+    if (sub == 0) X[row][j] = x;
+    __syncthreads();
   }
-  if (rok)
-    for (int k = 0; k < nb; ++k) K[row * ldK + j0 + k] = X[lane][k];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = q * 256 + t, i = e / NB, k = e % NB;
+    if (r0 + i < m && k < nb) K[(r0 + i) * ldK + j0 + k] = X[i][k];
+  }
 }
 
 __global__ void set_i64_kernel(int64_t* p, int64_t v) { *p = v; }
 
 // ---------------------------------------------------------------------------
-// chained substitutions
+// Solves with the factor: L and L^T are applied block by block with explicit
+// inverses of their NBI x NBI diagonal blocks (D_q = L_qq^{-1}), so every step
+// is a bandwidth-bound matrix-vector product:
+//   forward   y_q = D_q b_q ;  b_{>q} -= L_{>q,q} y_q
+//   backward  x_q = D_q^T y_q ;  y_{<q} -= L_{q,<q}^T x_q
+// The D_q are built after the factorisation: 64 x 64 diagonal blocks are
+// inverted directly, then doubled up with
+//   inv([A 0; B C]) = [A^{-1} 0; -C^{-1} (B A^{-1}) C^{-1}]
+// (two batched FP64-MFMA GEMMs per doubling level).
 
-__device__ inline bool wait_flag(const unsigned* f, unsigned epoch, int* status) {
-  unsigned spins = 0;
-  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-    __builtin_amdgcn_s_sleep(1);
-    if (++spins > (1u << 24)) {
-      atomicOr(status, 1);
-      return false;
-    }
-  }
-  return true;
+// D_q <- lower part of L_qq, identity beyond m and zero above the diagonal.
+__global__ void blkdiag_copy_kernel(int64_t m, const double* __restrict__ L, int64_t ldL,
+                                    int64_t nbi, double* __restrict__ D) {
+  const int64_t q = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nbi * nbi) return;
+  const int64_t i = e / nbi, k = e % nbi;
+  const int64_t gi = q * nbi + i, gk = q * nbi + k;
+  double v;
+  if (gi < m) v = (k <= i) ? L[gi * ldL + gk] : 0.0;
+  else v = (i == k) ? 1.0 : 0.0;
+  D[q * nbi * nbi + e] = v;
 }
 
-__device__ inline void publish(unsigned* f, unsigned epoch) {
-  __hip_atomic_store(f, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// L y = b, b overwritten by y. 256 threads; block q = blockIdx.x.
-__global__ __launch_bounds__(256) void trsv_lower_kernel(int64_t m, const double* __restrict__ L,
-                                                         int64_t ldL, double* b, unsigned* flags,
-                                                         unsigned epoch, int* status) {
-  __shared__ double part[4][NB];
-  const int t = threadIdx.x;
-  const int64_t q = blockIdx.x;
-  const int i = t >> 2, quarter = t & 3;
-  const int64_t row = q * NB + i;
-  const bool rok = row < m;
-  double acc = 0.0;
-  for (int64_t k = 0; k < q; ++k) {
-    wait_flag(flags + k, epoch, status);
-    const double* lp = L + (rok ? row : 0) * ldL + k * NB + quarter * 16;
-    const double* yp = b + k * NB + quarter * 16;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc += (rok ? lp[e] : 0.0) * yp[e];
-  }
-  acc += __shfl_xor(acc, 1);
-  acc += __shfl_xor(acc, 2);
-  if (quarter == 0) part[0][i] = acc;
+// In-place inverse of every 64 x 64 diagonal block of the D_q: lane c
+// computes column c by forward substitution.
+__global__ __launch_bounds__(64) void tri_inv64_kernel(int64_t nbi, double* __restrict__ D) {
+  __shared__ double Lb[NB][NB + 1];
+  __shared__ double Xb[NB][NB + 1];
+  const int c = threadIdx.x;
+  const int64_t q = blockIdx.y, p = blockIdx.x;
+  double* base = D + q * nbi * nbi + p * NB * (nbi + 1);
+  for (int i = 0; i < NB; ++i) Lb[i][c] = base[i * nbi + c];
   __syncthreads();
-  if (t < 64) {
-    const int lane = t;
-    const int64_t r = q * NB + lane;
-    const bool ok = r < m;
-    double rhs = ok ? (b[r] - part[0][lane]) : 0.0;
-    double rowv[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      const int64_t c = q * NB + k;
-      rowv[k] = (ok && k <= lane && c < m) ? L[r * ldL + c] : ((!ok && k == lane) ? 1.0 : 0.0);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const double yj = readlane_d(rhs, j) / readlane_d(rowv[j], j);
-      if (lane == j) rhs = yj;
-      else if (lane > j) rhs -= rowv[j] * yj;
-    }
-    if (ok) b[r] = rhs;
-    __threadfence();
-    if (lane == 0) publish(flags + q, epoch);
-  }
-}
-
-// L^T x = y, y overwritten by x. Workgroup w handles block q = nblk-1-w.
-__global__ __launch_bounds__(256) void trsv_upper_kernel(int64_t m, const double* __restrict__ L,
-                                                         int64_t ldL, double* b, unsigned* flags,
-                                                         unsigned epoch, int* status) {
-  __shared__ double part[4][NB];
-  const int64_t nblk = (m + NB - 1) / NB;
-  const int t = threadIdx.x;
-  const int64_t q = nblk - 1 - blockIdx.x;
-  const int j = t & 63, wave = t >> 6;
-  const int64_t col = q * NB + j;
-  const bool cok = col < m;
-  double acc = 0.0;
-  for (int64_t k = nblk - 1; k > q; --k) {
-    wait_flag(flags + k, epoch, status);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int64_t r = k * NB + wave * 16 + e;
-      if (r < m) {
-        const double xv = b[r];
-        acc += (cok ? L[r * ldL + col] : 0.0) * xv;
+  for (int i = 0; i < NB; ++i) {
+    double x;
+    if (i < c) {
+      x = 0.0;
+    } else if (i == c) {
+      x = 1.0 / Lb[c][c];
+    } else {
+      double s0 = 0.0, s1 = 0.0;
+      int k = c;
+      for (; k + 1 < i; k += 2) {
+        s0 += Lb[i][k] * Xb[k][c];
+        s1 += Lb[i][k + 1] * Xb[k + 1][c];
       }
+      if (k < i) s0 += Lb[i][k] * Xb[k][c];
+      x = -(s0 + s1) / Lb[i][i];
     }
+    Xb[i][c] = x;
   }
-  part[wave][j] = acc;
+  for (int i = 0; i < NB; ++i) base[i * nbi + c] = Xb[i][c];
+}
+
+// y[r] = alpha * sum_k A[r][k] x[k] + beta * y[r]   (r < M; 8 rows per workgroup)
+__global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t M, int64_t K,
+                                                        const double* __restrict__ A, int64_t lda,
+                                                        const double* __restrict__ x, double alpha,
+                                                        double beta, double* __restrict__ y) {
+  __shared__ double red[4][8];
+  const int64_t r0 = (int64_t)blockIdx.x * 8;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int64_t k = threadIdx.x; k < K; k += 256) {
+    const double xv = x[k];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (r0 + q < M) acc[q] += A[(r0 + q) * lda + k] * xv;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    double v = acc[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[wave][q] = v;
+  }
   __syncthreads();
-  if (t < 64) {
-    const int lane = t;
-    const int64_t r = q * NB + lane;
-    const bool ok = r < m;
-    double rhs = ok ? (b[r] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]))
-                    : 0.0;
-    double colv[NB];  // colv[k] = L[q*NB + k][q*NB + lane]
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      const int64_t rr = q * NB + k;
-      colv[k] = (ok && k >= lane && rr < m) ? L[rr * ldL + r] : ((!ok && k == lane) ? 1.0 : 0.0);
+  if (threadIdx.x < 8 && r0 + threadIdx.x < M) {
+    const int q = threadIdx.x;
+    const double v = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    y[r0 + q] = (beta == 0.0) ? alpha * v : alpha * v + beta * y[r0 + q];
+  }
+}
+
+// y[c] = alpha * sum_r A[r][c] x[r] + beta * y[c]   (r < M, c < K; 64 columns per workgroup)
+__global__ __launch_bounds__(256) void gemv_cols_kernel(int64_t M, int64_t K,
+                                                        const double* __restrict__ A, int64_t lda,
+                                                        const double* __restrict__ x, double alpha,
+                                                        double beta, double* __restrict__ y) {
+  __shared__ double red[4][64];
+  const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * 64 + cl;
+  double s0 = 0.0, s1 = 0.0;
+  if (c < K) {
+    int64_t r = rg;
+    for (; r + 4 < M; r += 8) {
+      s0 += A[r * lda + c] * x[r];
+      s1 += A[(r + 4) * lda + c] * x[r + 4];
     }
-#pragma unroll
-    for (int jj = NB - 1; jj >= 0; --jj) {
-      const double xj = readlane_d(rhs, jj) / readlane_d(colv[jj], jj);
-      if (lane == jj) rhs = xj;
-      else if (lane < jj) rhs -= colv[jj] * xj;
-    }
-    if (ok) b[r] = rhs;
-    __threadfence();
-    if (lane == 0) publish(flags + q, epoch);
+    if (r < M) s0 += A[r * lda + c] * x[r];
+  }
+  red[rg][cl] = s0 + s1;
+  __syncthreads();
+  if (rg == 0 && c < K) {
+    const double v = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+    y[c] = (beta == 0.0) ? alpha * v : alpha * v + beta * y[c];
   }
 }
 
@@ -243,6 +280,24 @@ __global__ __launch_bounds__(64) void trsm_diag_kernel(int64_t ell, const double
 
 }  // namespace
 
+int gemv_rows(hipStream_t s, int64_t M, int64_t K, const double* A, int64_t lda, const double* x,
+              double alpha, double beta, double* y) {
+  if (M <= 0) return 0;
+  hipLaunchKernelGGL(gemv_rows_kernel, dim3((unsigned)cdiv(M, 8)), dim3(256), 0, s, M, K, A, lda,
+                     x, alpha, beta, y);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int gemv_cols(hipStream_t s, int64_t M, int64_t K, const double* A, int64_t lda, const double* x,
+              double alpha, double beta, double* y) {
+  if (K <= 0) return 0;
+  hipLaunchKernelGGL(gemv_cols_kernel, dim3((unsigned)cdiv(K, 64)), dim3(256), 0, s, M, K, A, lda,
+                     x, alpha, beta, y);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
 int trsm_lower_left(hipStream_t s, int64_t ell, const double* L, int64_t ldL, int64_t N, double* B,
                     int64_t ldB) {
   const int64_t nblk = cdiv(ell, NB);
@@ -263,40 +318,97 @@ int trsm_lower_left(hipStream_t s, int64_t ell, const double* L, int64_t ldL, in
 
 size_t chol_workspace_bytes(int64_t) { return 0; }
 
-int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, void*) {
+int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, double* dinv) {
+  // Block columns of width NB2 = 4 NB. Inside one, each 64-wide panel is
+  // factored (diagonal block + the rows below) and applied to the remaining
+  // columns of the same block column; the trailing matrix then receives one
+  // rank-NB2 update on the matrix cores.
+  constexpr int NB2 = 4 * NB;
   hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, dinfo, (int64_t)0);
   DNGD_LAUNCH_CHECK();
-  for (int64_t j0 = 0; j0 < m; j0 += NB) {
-    const int64_t rows = m - j0;
-    const unsigned nblk = (unsigned)cdiv(rows, NB);
-    hipLaunchKernelGGL(potrf_panel_kernel, dim3(nblk), dim3(64), 0, s, m, K, ldK, j0, dinfo);
-    DNGD_LAUNCH_CHECK();
-    const int64_t rest = rows - NB;
+  for (int64_t jb = 0; jb < m; jb += NB2) {
+    const int64_t jend = std::min<int64_t>(m, jb + NB2);
+    for (int64_t j0 = jb; j0 < jend; j0 += NB) {
+      const int64_t rows = m - j0;
+      const unsigned nblk = (unsigned)cdiv(rows, NB);
+      hipLaunchKernelGGL(potrf_panel_kernel, dim3(nblk), dim3(256), 0, s, m, K, ldK, j0, dinfo,
+                         dinv);
+      DNGD_LAUNCH_CHECK();
+      const int64_t c0 = j0 + NB;            // first column still to update in this block
+      if (c0 < jend) {
+        // A[c0:m, c0:jend] -= L[c0:m, j0:j0+NB] L[c0:jend, j0:j0+NB]^T  (lower part)
+        int rc = gemm_f64(s, GEMM_FULL_LOWER, true, true, m - c0, jend - c0, NB, -1.0,
+                          K + c0 * ldK + j0, ldK, K + c0 * ldK + j0, ldK, 1.0, K + c0 * ldK + c0,
+                          ldK);
+        if (rc) return rc;
+      }
+    }
+    const int64_t rest = m - jend;
     if (rest > 0) {
-      double* A21 = K + (j0 + NB) * ldK + j0;
-      double* A22 = K + (j0 + NB) * ldK + j0 + NB;
-      int rc = gemm_f64(s, GEMM_SYRK_LOWER, true, true, rest, rest, NB, -1.0, A21, ldK, A21, ldK,
-                        1.0, A22, ldK);
+      const double* L21 = K + jend * ldK + jb;
+      double* A22 = K + jend * ldK + jend;
+      int rc = gemm_f64(s, GEMM_SYRK_LOWER, true, true, rest, rest, jend - jb, -1.0, L21, ldK,
+                        L21, ldK, 1.0, A22, ldK);
       if (rc) return rc;
     }
   }
   return 0;
 }
 
-int64_t chol_solve_flag_count(int64_t m) { return 2 * cdiv(m, NB); }
+int64_t chol_solve_block(int64_t m) {
+  int64_t nbi = NB;
+  while (nbi < m && nbi < 1024) nbi *= 2;
+  return nbi;
+}
 
-int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, double* b, unsigned* flags,
-               unsigned* epoch, int* dstatus, double*) {
-  const int64_t nblk = cdiv(m, NB);
-  const unsigned e1 = ++(*epoch);
-  hipLaunchKernelGGL(trsv_lower_kernel, dim3((unsigned)nblk), dim3(256), 0, s, m, L, ldL, b, flags,
-                     e1, dstatus);
+size_t chol_solve_aux_bytes(int64_t m) {
+  const int64_t nbi = chol_solve_block(m), nb = cdiv(m, nbi);
+  return (size_t)(2 * nb * nbi * nbi + m) * sizeof(double);
+}
+
+int chol_prepare_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, double* aux) {
+  const int64_t nbi = chol_solve_block(m), nb = cdiv(m, nbi);
+  double* D = aux;
+  double* T = aux + nb * nbi * nbi;
+  hipLaunchKernelGGL(blkdiag_copy_kernel, dim3((unsigned)cdiv(nbi * nbi, 256), (unsigned)nb),
+                     dim3(256), 0, s, m, L, ldL, nbi, D);
   DNGD_LAUNCH_CHECK();
-  const unsigned e2 = ++(*epoch);
-  hipLaunchKernelGGL(trsv_upper_kernel, dim3((unsigned)nblk), dim3(256), 0, s, m, L, ldL, b,
-                     flags + nblk, e2, dstatus);
+  hipLaunchKernelGGL(tri_inv64_kernel, dim3((unsigned)(nbi / NB), (unsigned)nb), dim3(64), 0, s,
+                     nbi, D);
   DNGD_LAUNCH_CHECK();
+  for (int64_t sz = NB; sz < nbi; sz *= 2) {
+    const int64_t pairs = nbi / (2 * sz);
+    const int64_t in = 2 * sz * (nbi + 1), out = nbi * nbi;
+    // T = B A^{-1}   (B: rows [sz, 2sz) x cols [0, sz) of the pair)
+    int rc = gemm_f64_batched(s, true, false, sz, sz, sz, 1.0, D + sz * nbi, nbi, out, in, D, nbi,
+                              out, in, 0.0, T + sz * nbi, nbi, out, in, nb, pairs);
+    if (rc) return rc;
+    // X = -C^{-1} T  written over B
+    rc = gemm_f64_batched(s, true, false, sz, sz, sz, -1.0, D + sz * (nbi + 1), nbi, out, in,
+                          T + sz * nbi, nbi, out, in, 0.0, D + sz * nbi, nbi, out, in, nb, pairs);
+    if (rc) return rc;
+  }
   return 0;
+}
+
+int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, const double* aux,
+               double* b) {
+  const int64_t nbi = chol_solve_block(m), nb = cdiv(m, nbi);
+  const double* D = aux;
+  double* y = const_cast<double*>(aux) + 2 * nb * nbi * nbi;
+  int rc = 0;
+  for (int64_t q = 0; q < nb && !rc; ++q) {
+    const int64_t r0 = q * nbi, mq = std::min(nbi, m - r0), rest = m - r0 - mq;
+    rc = gemv_rows(s, mq, mq, D + q * nbi * nbi, nbi, b + r0, 1.0, 0.0, y + r0);
+    if (!rc && rest > 0)
+      rc = gemv_rows(s, rest, mq, L + (r0 + mq) * ldL + r0, ldL, y + r0, -1.0, 1.0, b + r0 + mq);
+  }
+  for (int64_t q = nb - 1; q >= 0 && !rc; --q) {
+    const int64_t r0 = q * nbi, mq = std::min(nbi, m - r0);
+    rc = gemv_cols(s, mq, mq, D + q * nbi * nbi, nbi, y + r0, 1.0, 0.0, b + r0);
+    if (!rc && r0 > 0) rc = gemv_cols(s, mq, r0, L + r0 * ldL, ldL, b + r0, -1.0, 1.0, y);
+  }
+  return rc;
 }
 
 }  // namespace dngd

@@ -85,7 +85,12 @@ RowMap row_map(const Geometry& g);
 // ---------------------------------------------------------------------------
 // FP64 MFMA GEMM: C = alpha * op(A) * op(B)^T-ish + beta * C (see gemm_f64.hip)
 
-enum GemmMode { GEMM_FULL = 0, GEMM_SYRK_LOWER = 1, GEMM_PARTIAL_LOWER = 2 };
+enum GemmMode {
+  GEMM_FULL = 0,
+  GEMM_SYRK_LOWER = 1,     // square, lower tiles only, writes row >= col
+  GEMM_PARTIAL_LOWER = 2,  // lower tiles, split-K partials to work
+  GEMM_FULL_LOWER = 4      // all tiles, writes only elements with row >= col
+};
 
 // op(A) is M x K: a_kcontig -> A[m*lda + k], else A[k*lda + m].
 // op(B) is N x K: b_kcontig -> B[n*ldb + k], else B[k*ldb + n].
@@ -96,6 +101,14 @@ int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64
              int64_t K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
              double beta, double* C, int64_t ldc, double* work = nullptr, int splits = 1);
 
+// Batched GEMM_FULL: matrix z = (z / n_inner, z % n_inner) starts at
+// A + zo * a_out + zi * a_in (likewise B, C); n_outer * n_inner matrices.
+int gemm_f64_batched(hipStream_t s, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
+                     int64_t K, double alpha, const double* A, int64_t lda, int64_t a_out,
+                     int64_t a_in, const double* B, int64_t ldb, int64_t b_out, int64_t b_in,
+                     double beta, double* C, int64_t ldc, int64_t c_out, int64_t c_in,
+                     int64_t n_outer, int64_t n_inner);
+
 // Lower-triangular tile count for an M x M matrix with tile edge T.
 int64_t lower_tiles(int64_t M, int tile);
 
@@ -103,24 +116,37 @@ int64_t lower_tiles(int64_t M, int tile);
 // Gram (gram.hip)
 
 size_t gram_workspace_bytes(int64_t m, int64_t n, int j_dtype, int passes, int* splits_out);
+// ev_begin/ev_end (optional) are recorded on `s` around the contraction kernel alone
 int gram_launch(hipStream_t s, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
-                int passes, double lambda, double* K, int64_t ldK, void* work, size_t work_bytes);
+                int passes, double lambda, double* K, int64_t ldK, void* work, size_t work_bytes,
+                hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 
 // ---------------------------------------------------------------------------
 // Cholesky and triangular solves (chol.hip)
 
 size_t chol_workspace_bytes(int64_t m);
-// Factor the lower triangle in place; *dinfo (device int64) = 0 or first bad column (1-based).
-int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, void* work);
-// Solve L L^T x = b in place for one vector; `flags` is an int array of
-// chol_solve_flag_count(m) entries (zero-initialised once), `epoch` a value
-// never used before with these flags; `dstatus` an int receiving timeout errors.
-int64_t chol_solve_flag_count(int64_t m);
+// Factor the lower triangle in place; *dinfo (device int64) = 0 or first bad
+// column (1-based); dinv (device, m doubles, may be null) receives 1 / L_ii.
+int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, double* dinv);
+// Solves with a stored factor L: chol_prepare_solve builds the inverted
+// diagonal blocks into `aux` (chol_solve_aux_bytes(m) bytes, device); then
+// chol_solve overwrites b with (L L^T)^{-1} b. aux also holds the solve's
+// temporary vector, so one aux serves one solve at a time.
+int64_t chol_solve_block(int64_t m);
+size_t chol_solve_aux_bytes(int64_t m);
+int chol_prepare_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, double* aux);
+int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, const double* aux,
+               double* b);
+// y = alpha A x + beta y (A: M x K row-major) and y = alpha A^T x + beta y
+int gemv_rows(hipStream_t s, int64_t M, int64_t K, const double* A, int64_t lda, const double* x,
+              double alpha, double beta, double* y);
+int gemv_cols(hipStream_t s, int64_t M, int64_t K, const double* A, int64_t lda, const double* x,
+              double alpha, double beta, double* y);
 // B <- L^{-1} B for lower-triangular L (ell x ell) and B (ell x N row-major, ldB)
 int trsm_lower_left(hipStream_t s, int64_t ell, const double* L, int64_t ldL, int64_t N, double* B,
                     int64_t ldB);
-int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, double* b, unsigned* flags,
-               unsigned* epoch, int* dstatus, double* tmp);
+int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, const double* dinv,
+               double* b, unsigned* flags, unsigned* epoch, int* dstatus);
 
 // ---------------------------------------------------------------------------
 // vector kernels (blas1.hip)

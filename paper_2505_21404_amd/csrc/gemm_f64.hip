@@ -21,6 +21,7 @@ namespace {
 
 constexpr int KS = 16;  // K step
 constexpr int kPartialFull = 3;  // split-K full GEMM: tile partials, then gemm_reduce_full
+constexpr int kBatched = 5;      // full GEMM over a batch of matrices (blockIdx.z)
 
 __device__ inline void tri_decode(int64_t t, int64_t& i, int64_t& j) {
   int64_t ii = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -85,11 +86,22 @@ struct SlabLoader {
   }
 };
 
+struct Batch {
+  int64_t inner = 1;                 // batch index z -> (z / inner, z % inner)
+  int64_t a_out = 0, a_in = 0, b_out = 0, b_in = 0, c_out = 0, c_in = 0;  // element strides
+};
+
 template <int BM, int BN, bool AK, bool BKC, int MODE>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
-    double* __restrict__ work, int64_t k_per_split, int64_t ntiles) {
+    double* __restrict__ work, int64_t k_per_split, int64_t ntiles, Batch bt) {
+  if (MODE == kBatched) {
+    const int64_t zo = blockIdx.z / bt.inner, zi = blockIdx.z % bt.inner;
+    A += zo * bt.a_out + zi * bt.a_in;
+    B += zo * bt.b_out + zi * bt.b_in;
+    C += zo * bt.c_out + zi * bt.c_in;
+  }
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   __shared__ double As[KS][BM];
@@ -97,7 +109,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
 
   constexpr bool PARTIAL = (MODE == GEMM_PARTIAL_LOWER || MODE == kPartialFull);
   int64_t tm, tn;
-  if (MODE == GEMM_FULL || MODE == kPartialFull) {
+  if (MODE == GEMM_FULL || MODE == kPartialFull || MODE == GEMM_FULL_LOWER || MODE == kBatched) {
     tm = blockIdx.x;
     tn = blockIdx.y;
   } else {
@@ -171,7 +183,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
           work[(tile * BM + rl) * BN + cl] = x;
         } else {
           const int64_t row = m0 + rl, col = n0 + cl;
-          if (row < M && col < N && (MODE == GEMM_FULL || row >= col)) {
+          if (row < M && col < N &&
+              (MODE == GEMM_FULL || MODE == kBatched || row >= col)) {  // *_LOWER: row >= col
             double* p = C + row * ldc + col;
             *p = (beta == 0.0) ? alpha * x : alpha * x + beta * *p;
           }
@@ -204,7 +217,7 @@ int launch_split_full(hipStream_t s, int64_t M, int64_t N, int64_t K, double alp
   const int64_t kps = round_up(cdiv(K, splits), KS);
   dim3 grid((unsigned)cdiv(M, BM), (unsigned)cdiv(N, BN), (unsigned)splits);
   hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, AK, BKC, kPartialFull>), grid, dim3(256), 0, s, M, N,
-                     K, alpha, A, lda, B, ldb, beta, C, ldc, work, kps, (int64_t)0);
+                     K, alpha, A, lda, B, ldb, beta, C, ldc, work, kps, (int64_t)0, Batch{});
   DNGD_LAUNCH_CHECK();
   dim3 g2(grid.x, grid.y, BM * BN / 256);
   hipLaunchKernelGGL((gemm_reduce_full_kernel<BM, BN>), g2, dim3(256), 0, s, M, N, splits, work,
@@ -219,7 +232,7 @@ int launch(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const d
            double* work, int splits) {
   dim3 grid;
   int64_t ntiles = 0, kps = K;
-  if (MODE == GEMM_FULL) {
+  if (MODE == GEMM_FULL || MODE == GEMM_FULL_LOWER) {
     grid = dim3((unsigned)cdiv(M, BM), (unsigned)cdiv(N, BN), 1);
   } else {
     ntiles = lower_tiles(M, BM);
@@ -228,12 +241,38 @@ int launch(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const d
   }
   if (grid.x == 0 || grid.y == 0) return 0;
   hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, AK, BKC, MODE>), grid, dim3(256), 0, s, M, N, K,
-                     alpha, A, lda, B, ldb, beta, C, ldc, work, kps, ntiles);
+                     alpha, A, lda, B, ldb, beta, C, ldc, work, kps, ntiles, Batch{});
   DNGD_LAUNCH_CHECK();
   return 0;
 }
 
 }  // namespace
+
+int gemm_f64_batched(hipStream_t s, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
+                     int64_t K, double alpha, const double* A, int64_t lda, int64_t a_out,
+                     int64_t a_in, const double* B, int64_t ldb, int64_t b_out, int64_t b_in,
+                     double beta, double* C, int64_t ldc, int64_t c_out, int64_t c_in,
+                     int64_t n_outer, int64_t n_inner) {
+  if (M <= 0 || N <= 0 || n_outer * n_inner <= 0) return 0;
+  Batch bt;
+  bt.inner = n_inner;
+  bt.a_out = a_out, bt.a_in = a_in, bt.b_out = b_out, bt.b_in = b_in, bt.c_out = c_out,
+  bt.c_in = c_in;
+  const dim3 grid((unsigned)cdiv(M, 64), (unsigned)cdiv(N, 64), (unsigned)(n_outer * n_inner));
+#define DNGD_BATCH_CASE(AKV, BKV)                                                              \
+  if (a_kcontig == AKV && b_kcontig == BKV) {                                                 \
+    hipLaunchKernelGGL((gemm_f64_kernel<64, 64, AKV, BKV, kBatched>), grid, dim3(256), 0, s, M, \
+                       N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, K, (int64_t)0, bt);  \
+    DNGD_LAUNCH_CHECK();                                                                      \
+    return 0;                                                                                 \
+  }
+  DNGD_BATCH_CASE(true, true)
+  DNGD_BATCH_CASE(true, false)
+  DNGD_BATCH_CASE(false, true)
+  DNGD_BATCH_CASE(false, false)
+#undef DNGD_BATCH_CASE
+  return -1;
+}
 
 int64_t lower_tiles(int64_t M, int tile) {
   const int64_t t = cdiv(M, tile);
@@ -247,6 +286,11 @@ int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64
   if (mode == GEMM_PARTIAL_LOWER) {
     return launch<128, 128, true, true, GEMM_PARTIAL_LOWER>(s, M, N, K, alpha, A, lda, B, ldb,
                                                              beta, C, ldc, work, splits);
+  }
+  if (mode == GEMM_FULL_LOWER) {
+    DNGD_REQUIRE(a_kcontig && b_kcontig, "gemm_f64: FULL_LOWER needs K-contiguous operands");
+    return launch<64, 64, true, true, GEMM_FULL_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                        ldc, work, 1);
   }
   if (mode == GEMM_SYRK_LOWER) {
     if (M >= 1024)

@@ -5,25 +5,23 @@
 // (the contraction runs along a row of J), so every lane loads contiguous
 // 16-byte chunks and no transpose is needed anywhere.
 //
-// Mixed path (FP32 J): v_mfma_f32_32x32x16_bf16 with FP32 accumulation.
-// J is rounded to bf16 while it is staged into LDS (no bf16 copy of J in
+// Mixed path (FP32 J): v_mfma_f32_32x32x16_bf16 with FP32 accumulation. J is
+// rounded to bf16 in registers right before the MFMAs (no bf16 copy of J in
 // HBM). PASSES == 3 keeps the rounding residual as a second bf16 term,
 // J = hi + lo, and accumulates hi hi^T + hi lo^T + lo hi^T (the lo lo^T term
 // is below FP32 resolution), so K carries ~16 bits of J instead of 8.
 // Plain path (FP64 J): the FP64 MFMA GEMM in split-K partial mode.
 //
-// Workgroup tile 128 x 128 of K (4 waves, 64 x 64 each = 2 x 2 MFMA 32x32),
-// K-step 64 elements. LDS rows are 64 bf16 = 8 chunks of 16 B; chunk c of row
-// r is stored at c ^ (r & 7) so the 32 lanes reading 32 rows of one chunk hit
-// distinct banks.
-//
 // Only lower-triangle tiles are launched. Tiles are numbered row-major over
 // the lower triangle and the launch index is remapped so that each XCD
 // (workgroups go round-robin over the 8 XCDs) receives a contiguous run of
-// tiles, which share row panels of J in that XCD's L2.
+// tiles of one split, which share row panels of J in that XCD's L2.
 //
 // Split-K partial tiles (FP32 or FP64) are summed in FP64 in split order by
-// gram_reduce, which also adds lambda on the diagonal: deterministic.
+// gram_reduce, which also adds lambda on the diagonal: deterministic. The
+// FP32 accumulation error of a partial grows with the number of terms it
+// holds while the FP64 sum of S partials does not, so the bf16 path uses
+// many short splits (~4096 terms each).
 #include "common.h"
 
 namespace dngd {
@@ -33,8 +31,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int GT = 128;   // tile edge
-constexpr int GK = 64;    // K step (elements)
+constexpr int GT = 128;   // tile edge of the FP64 path
 constexpr int NXCD = 8;
 
 __device__ inline void tri_decode_g(int64_t t, int64_t& i, int64_t& j) {
@@ -61,144 +58,162 @@ __device__ inline void split8(const float4& a, const float4& b, Chunk& hi, Chunk
   }
 }
 
+// 256 x 256 tile of K per workgroup: 8 waves in a 2 x 4 grid, each wave a
+// 128 x 64 block = 4 x 2 MFMA 32x32 accumulators. K advances 32 elements per
+// step. The FP32 slabs of both row panels go from HBM straight into LDS with
+// global_load_lds (no register staging), double-buffered in two separate LDS
+// stages so the loads of step it + 1 overlap the MFMAs of step it. Each wave
+// splits its fragments into bf16 hi (and lo) in registers right before the
+// MFMAs.
+// LDS rows are 32 floats = 8 chunks of 16 B; chunk c of row r is stored at
+// c ^ g(r), g(r) = (r & 7) ^ ((r >> 3) & 1).
+constexpr int BT = 256;   // tile edge
+constexpr int BKE = 32;   // K elements per step
+constexpr int ROWCH = BKE / 4;  // 16-byte chunks per LDS row
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ inline int gsw(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+__device__ inline int slot(int r, int c) { return r * ROWCH + (c ^ gsw(r)); }
+
 template <int PASSES>
-__global__ __launch_bounds__(256) void gram_bf16_kernel(int64_t m, int64_t n,
+__global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
                                                         const float* __restrict__ J, int64_t ldJ,
                                                         float* __restrict__ work,
                                                         int64_t k_per_split, int64_t ntiles,
-                                                        int64_t per_xcd) {
+                                                        int64_t per_xcd, int splits) {
   constexpr bool LO = (PASSES == 3);
-  __shared__ uint4 Ahi[GT * 8];
-  __shared__ uint4 Bhi[GT * 8];
-  __shared__ uint4 Alo[LO ? GT * 8 : 1];
-  __shared__ uint4 Blo[LO ? GT * 8 : 1];
+  __shared__ float4 sA0[BT * ROWCH];
+  __shared__ float4 sB0[BT * ROWCH];
+  __shared__ float4 sA1[BT * ROWCH];
+  __shared__ float4 sB1[BT * ROWCH];
 
-  const int64_t logical = (int64_t)(blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
-  if (logical >= ntiles) return;
+  // launch index -> (split, tile): each XCD gets a contiguous run of tiles of one split
+  const int64_t lin = blockIdx.x;
+  const int64_t slt = (lin % NXCD) * per_xcd + lin / NXCD;
+  if (slt >= ntiles * (int64_t)splits) return;  // padding slots
+  const int64_t split = slt / ntiles;
+  const int64_t logical = slt % ntiles;
   int64_t ti, tj;
   tri_decode_g(logical, ti, tj);
   const bool diag = (ti == tj);
-  const int split = blockIdx.y;
-  const int64_t kbeg = (int64_t)split * k_per_split;
+  const int64_t kbeg = split * k_per_split;
   const int64_t kend = min(n, kbeg + k_per_split);
 
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave >> 2, wn = wave & 3;   // 2 x 4 waves
 
-  // loader geometry: thread -> row (t >> 1), 32 consecutive k (t & 1)
-  const int lrow = t >> 1;
-  const int lhalf = t & 1;
-  const int64_t arow = ti * GT + lrow, brow = tj * GT + lrow;
-  const bool aok = arow < m, bok = brow < m;
-  const float* pa = J + (aok ? arow : 0) * ldJ;
-  const float* pb = J + (bok ? brow : 0) * ldJ;
-
-  f32x16 acc[2][2];
+  // DMA geometry: wave w, instruction j fills LDS slots [(4w + j) * 64, +64):
+  // rows 8 (4w + j) + lane / 8, physical chunk lane % 8. Rows beyond m read
+  // row m - 1 (their K entries are discarded).
+  const float* pa[4];
+  const float* pb[4];
+  int ca[4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 4; ++j) {
+    const int r = (wave * 4 + j) * 8 + (lane >> 3);
+    ca[j] = 4 * ((lane & 7) ^ gsw(r));
+    const int64_t ra = min(ti * BT + r, m - 1), rb = min(tj * BT + r, m - 1);
+    pa[j] = J + ra * ldJ;
+    pb[j] = J + rb * ldJ;
+  }
+  auto dma = [&](int64_t k0, float4* dA, float4* dB) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t k = k0 + ca[j];
+      const int64_t kk = (k < n) ? k : 0;  // in bounds; k >= kend is masked after the read
+      __builtin_amdgcn_global_load_lds(pa[j] + kk, (lds_void*)(dA + (wave * 4 + j) * 64), 16, 0, 0);
+      if (!diag)
+        __builtin_amdgcn_global_load_lds(pb[j] + kk, (lds_void*)(dB + (wave * 4 + j) * 64), 16, 0,
+                                         0);
+    }
+  };
+
+  f32x16 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-  float4 ra[8], rb[8];
-  auto gload = [&](int64_t k0) {
-    const int64_t kb = k0 + lhalf * 32;
-    const bool full = (kb + 32 <= kend);
+  // fragment of row r for k-slice sl: 8 floats (two chunks), split to bf16
+  auto frag = [&](const float4* S, int r, int sl, int64_t k0, bool tail, Chunk& hi, Chunk& lo) {
+    const int c0 = sl * 4 + 2 * (lane >> 5);
+    float4 x0 = S[slot(r, c0)];
+    float4 x1 = S[slot(r, c0 + 1)];
+    if (tail) {
+      const int64_t kb = k0 + sl * 16 + 8 * (lane >> 5);
+      float f[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t k = kb + 4 * q;
-      if (full) {
-        ra[q] = aok ? *reinterpret_cast<const float4*>(pa + k) : float4{0, 0, 0, 0};
-        if (!diag) rb[q] = bok ? *reinterpret_cast<const float4*>(pb + k) : float4{0, 0, 0, 0};
-      } else {
-        float xa[4], xb[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool kin = (k + e) < kend;
-          xa[e] = (aok && kin) ? pa[k + e] : 0.0f;
-          xb[e] = (!diag && bok && kin) ? pb[k + e] : 0.0f;
-        }
-        ra[q] = float4{xa[0], xa[1], xa[2], xa[3]};
-        if (!diag) rb[q] = float4{xb[0], xb[1], xb[2], xb[3]};
-      }
+      for (int e = 0; e < 8; ++e)
+        if (kb + e >= kend) f[e] = 0.0f;
+      x0 = float4{f[0], f[1], f[2], f[3]};
+      x1 = float4{f[4], f[5], f[6], f[7]};
     }
+    split8(x0, x1, hi, lo, LO);
   };
-  auto sstore = [&]() {
+
+  auto compute = [&](const float4* SA, const float4* SB, int64_t k0) {
+    const bool tail = (k0 + BKE > kend);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int chunk = lhalf * 4 + c;
-      const int slot = lrow * 8 + (chunk ^ (lrow & 7));
-      Chunk h, l;
-      split8(ra[2 * c], ra[2 * c + 1], h, l, LO);
-      Ahi[slot] = h.u;
-      if (LO) Alo[slot] = l.u;
-      if (!diag) {
-        split8(rb[2 * c], rb[2 * c + 1], h, l, LO);
-        Bhi[slot] = h.u;
-        if (LO) Blo[slot] = l.u;
+    for (int sl = 0; sl < BKE / 16; ++sl) {
+      Chunk bh[2], bl[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) frag(SB, wn * 64 + j * 32 + (lane & 31), sl, k0, tail, bh[j], bl[j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        Chunk ah, al;
+        frag(SA, wm * 128 + i * 32 + (lane & 31), sl, k0, tail, ah, al);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.h, bh[j].h, acc[i][j], 0, 0, 0);
+        if (LO) {
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.h, bl[j].h, acc[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.h, bh[j].h, acc[i][j], 0, 0, 0);
+        }
       }
     }
   };
 
-  const uint4* BH = diag ? Ahi : Bhi;
-  const uint4* BL = diag ? Alo : Blo;
-
-  const int64_t nk = (kend > kbeg) ? (kend - kbeg + GK - 1) / GK : 0;
-  if (nk > 0) gload(kbeg);
-  for (int64_t it = 0; it < nk; ++it) {
-    sstore();
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg + BKE - 1) / BKE : 0;
+  if (nk > 0) dma(kbeg, sA0, sB0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int64_t it = 0; it < nk; it += 2) {
+    if (it + 1 < nk) dma(kbeg + (it + 1) * BKE, sA1, sB1);
+    compute(sA0, diag ? sA0 : sB0, kbeg + it * BKE);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (it + 1 < nk) gload(kbeg + (it + 1) * GK);
-#pragma unroll
-    for (int s = 0; s < GK / 16; ++s) {
-      const int chunk = s * 2 + (lane >> 5);
-      Chunk ah[2], bh[2], al[2], bl[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int r = wm * 64 + i * 32 + (lane & 31);
-        ah[i].u = Ahi[r * 8 + (chunk ^ (r & 7))];
-        if (LO) al[i].u = Alo[r * 8 + (chunk ^ (r & 7))];
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int r = wn * 64 + j * 32 + (lane & 31);
-        bh[j].u = BH[r * 8 + (chunk ^ (r & 7))];
-        if (LO) bl[j].u = BL[r * 8 + (chunk ^ (r & 7))];
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].h, bh[j].h, acc[i][j], 0, 0, 0);
-          if (LO) {
-            acc[i][j] =
-                __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].h, bl[j].h, acc[i][j], 0, 0, 0);
-            acc[i][j] =
-                __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i].h, bh[j].h, acc[i][j], 0, 0, 0);
-          }
-        }
+    if (it + 1 < nk) {
+      if (it + 2 < nk) dma(kbeg + (it + 2) * BKE, sA0, sB0);
+      compute(sA1, diag ? sA1 : sB1, kbeg + (it + 1) * BKE);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // accumulator v of tile (i, j): row 8 (v/4) + 4 (lane/32) + v%4, col lane%32
-  float* out = work + ((int64_t)split * ntiles + logical) * (GT * GT);
+  float* out = work + ((int64_t)split * ntiles + logical) * (BT * BT);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int rl = wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int rl = wm * 128 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int cl = wn * 64 + j * 32 + (lane & 31);
-        out[rl * GT + cl] = acc[i][j][v];
+        out[rl * BT + cl] = acc[i][j][v];
       }
 }
 
-template <typename P>
+template <typename P, int T>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t m, const P* __restrict__ work,
                                                           int splits, int64_t ntiles,
                                                           double lambda, double* __restrict__ K,
@@ -206,75 +221,93 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t m, const P* __
   int64_t ti, tj;
   tri_decode_g(blockIdx.x, ti, tj);
   const int base = (blockIdx.y * 256 + threadIdx.x) * 4;  // 4 consecutive elements
-  const int rl = base / GT, cl0 = base % GT;
-  const int64_t row = ti * GT + rl;
+  const int rl = base / T, cl0 = base % T;
+  const int64_t row = ti * T + rl;
   if (row >= m) return;
   double s[4] = {0, 0, 0, 0};
   for (int sp = 0; sp < splits; ++sp) {
-    const P* p = work + ((int64_t)sp * ntiles + blockIdx.x) * (GT * GT) + rl * GT + cl0;
+    const P* p = work + ((int64_t)sp * ntiles + blockIdx.x) * (T * T) + rl * T + cl0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) s[e] += (double)p[e];
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int64_t col = tj * GT + cl0 + e;
+    const int64_t col = tj * T + cl0 + e;
     if (col < m && col <= row) K[row * ldK + col] = s[e] + (row == col ? lambda : 0.0);
   }
 }
 
-int choose_splits(int64_t ntiles, int64_t n) {
+// FP64 path: enough splits to fill the chip.
+int choose_splits_f64(int64_t ntiles, int64_t n) {
   int64_t s = cdiv(1536, ntiles);
-  const int64_t smax = std::max<int64_t>(1, n / 2048);
-  if (s > smax) s = smax;
-  if (s < 1) s = 1;
-  if (s > 64) s = 64;
-  return (int)s;
+  s = std::min<int64_t>(s, std::max<int64_t>(1, n / 2048));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+}
+
+// bf16 path: <= ~4096 terms per split (accuracy) and enough workgroups to
+// fill the chip, at most 64 splits.
+int choose_splits_bf16(int64_t ntiles, int64_t n) {
+  int64_t s = std::max<int64_t>(cdiv(n, 4096), cdiv(3072, ntiles));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, cdiv(n, BKE)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
 }
 
 }  // namespace
 
 size_t gram_workspace_bytes(int64_t m, int64_t n, int j_dtype, int passes, int* splits_out) {
   (void)passes;
-  const int64_t nt = lower_tiles(m, GT);
-  const int s = choose_splits(nt, n);
+  if (j_dtype == 0) {
+    const int64_t nt = lower_tiles(m, GT);
+    const int s = choose_splits_f64(nt, n);
+    if (splits_out) *splits_out = s;
+    return (size_t)s * (size_t)nt * GT * GT * sizeof(double);
+  }
+  const int64_t nt = lower_tiles(m, BT);
+  const int s = choose_splits_bf16(nt, n);
   if (splits_out) *splits_out = s;
-  const size_t esz = (j_dtype == 0) ? sizeof(double) : sizeof(float);
-  return (size_t)s * (size_t)nt * GT * GT * esz;
+  return (size_t)s * (size_t)nt * BT * BT * sizeof(float);
 }
 
 int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
-                int passes, double lambda, double* K, int64_t ldK, void* work,
-                size_t work_bytes) {
+                int passes, double lambda, double* K, int64_t ldK, void* work, size_t work_bytes,
+                hipEvent_t ev_begin, hipEvent_t ev_end) {
   int splits = 1;
   const size_t need = gram_workspace_bytes(m, n, j_dtype, passes, &splits);
   DNGD_REQUIRE(work_bytes >= need, "gram: workspace too small (%zu < %zu)", work_bytes, need);
-  const int64_t nt = lower_tiles(m, GT);
-  const int64_t kps = round_up(cdiv(n, splits), GK);
+  if (ev_begin) DNGD_HIP(hipEventRecord(ev_begin, st));
   if (j_dtype == 0) {
+    const int64_t nt = lower_tiles(m, GT);
     int rc = gemm_f64(st, GEMM_PARTIAL_LOWER, true, true, m, m, n, 1.0,
                       static_cast<const double*>(J), ldJ, static_cast<const double*>(J), ldJ, 0.0,
                       nullptr, 0, static_cast<double*>(work), splits);
     if (rc) return rc;
-    hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3((unsigned)nt, GT * GT / 1024), dim3(256),
-                       0, st, m, static_cast<const double*>(work), splits, nt, lambda, K, ldK);
+    if (ev_end) DNGD_HIP(hipEventRecord(ev_end, st));
+    hipLaunchKernelGGL((gram_reduce_kernel<double, GT>), dim3((unsigned)nt, GT * GT / 1024),
+                       dim3(256), 0, st, m, static_cast<const double*>(work), splits, nt, lambda,
+                       K, ldK);
     DNGD_LAUNCH_CHECK();
     return 0;
   }
   DNGD_REQUIRE(ldJ % 4 == 0, "gram: FP32 J needs ldJ %% 4 == 0");
   DNGD_REQUIRE(passes == 1 || passes == 3, "gram: passes must be 1 or 3");
-  const int64_t per_xcd = cdiv(nt, NXCD);
-  dim3 grid((unsigned)(per_xcd * NXCD), (unsigned)splits);
+  const int64_t nt = lower_tiles(m, BT);
+  const int64_t kps = round_up(cdiv(n, splits), BKE);
+  const int64_t per_xcd = cdiv(nt * splits, NXCD);
+  // one workgroup per (split, tile); the kernel derives both from blockIdx.x
+  const dim3 grid((unsigned)(per_xcd * NXCD));
   if (passes == 3)
-    hipLaunchKernelGGL(gram_bf16_kernel<3>, grid, dim3(256), 0, st, m, n,
+    hipLaunchKernelGGL(gram_bf16_kernel<3>, grid, dim3(512), 0, st, m, n,
                        static_cast<const float*>(J), ldJ, static_cast<float*>(work), kps, nt,
-                       per_xcd);
+                       per_xcd, splits);
   else
-    hipLaunchKernelGGL(gram_bf16_kernel<1>, grid, dim3(256), 0, st, m, n,
+    hipLaunchKernelGGL(gram_bf16_kernel<1>, grid, dim3(512), 0, st, m, n,
                        static_cast<const float*>(J), ldJ, static_cast<float*>(work), kps, nt,
-                       per_xcd);
+                       per_xcd, splits);
   DNGD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3((unsigned)nt, GT * GT / 1024), dim3(256), 0,
-                     st, m, static_cast<const float*>(work), splits, nt, lambda, K, ldK);
+  if (ev_end) DNGD_HIP(hipEventRecord(ev_end, st));
+  hipLaunchKernelGGL((gram_reduce_kernel<float, BT>), dim3((unsigned)nt, BT * BT / 1024),
+                     dim3(256), 0, st, m, static_cast<const float*>(work), splits, nt, lambda, K,
+                     ldK);
   DNGD_LAUNCH_CHECK();
   return 0;
 }

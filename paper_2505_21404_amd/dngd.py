@@ -54,7 +54,8 @@ class StepStats(C.Structure):
                 ("anorm", C.c_double), ("ga_accepted", C.c_int32),
                 ("gram_passes_used", C.c_int32), ("pcg_iterations", C.c_int32),
                 ("pcg_converged", C.c_int32), ("ir_residual", C.c_double * 8),
-                ("max_row_norm2", C.c_double), ("pcg_rel_residual", C.c_double)]
+                ("max_row_norm2", C.c_double), ("pcg_rel_residual", C.c_double),
+                ("ms_gram_kernel", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ir_residual"}
