@@ -86,8 +86,11 @@ typedef struct {
   int32_t solver;       /* DNGD_DENSE (Cholesky) or DNGD_PCG (Nystrom-PCG) */
   int32_t ga;           /* 1: geodesic acceleration (Section 3.2), 0: off */
   int32_t ir_sweeps;    /* mixed dense: iterative-refinement sweeps per solve (default 2) */
-  int32_t gram_passes;  /* mixed: 1 (bf16 x bf16), 3 (split hi/lo bf16), 0 = pick from
-                           max_i ||J_i||^2 / lambda (default 0) */
+  int32_t gram_passes;  /* mixed: 1 (bf16 x bf16), 3 (split J ~ hi + lo, hi hi^T + hi lo^T
+                           + lo hi^T), 4 (also lo lo^T: positive semidefinite), 0 = pick
+                           from D = max_i ||J_i||^2 and lambda (default 0): 1 if
+                           2^-8 sqrt(D / lambda) <= 0.02, else 3 if 2^-16 D <= lambda / 10,
+                           else 4. A failed mixed factorisation is retried once with 4. */
   int32_t reserved0;
   double eps_norm;      /* GA guard: GA only if ||v|| > eps_norm (default 0) */
   /* PCG (solver == DNGD_PCG) */
@@ -129,6 +132,12 @@ int64_t dngd_jacobian_ld(const dngd_problem* h);    /* recommended ldJ: n rounde
  * Host-only, does not allocate. */
 int dngd_footprint(const dngd_problem* h, const dngd_step_opts* opts, size_t* bytes);
 
+/* The same figure from a problem description, before any device memory is
+ * allocated, plus the handle's copies of the point arrays (admission control
+ * of a serving loop). The description's array pointers may be NULL here.
+ * Host-only. */
+int dngd_footprint_desc(const dngd_problem_desc* desc, const dngd_step_opts* opts, size_t* bytes);
+
 /* Residual map and Jacobian (Section 2.2: r(theta) and J = dr/dtheta).
  * theta: device, n FP64.  r: device, m FP64 (may be NULL).
  * J: device, m rows of ldJ elements, row-major, row i = dr_i/dtheta in the
@@ -140,7 +149,8 @@ int dngd_residual_jacobian(dngd_problem* h, const double* theta, double* r, void
 /* Residual Gramian (Definition 3.3) plus damping: K = J J^T + lambda I.
  * J: device, m x ldJ row-major, j_dtype DNGD_F64 (FP64 MFMA) or DNGD_F32
  * (BF16 MFMA with FP32 accumulation; passes = 1 rounds J to bf16, passes = 3
- * uses the split J = hi + lo and adds hi hi^T + hi lo^T + lo hi^T).
+ * uses the split J ~ hi + lo and adds hi hi^T + hi lo^T + lo hi^T, passes = 4
+ * adds lo lo^T as well).
  * Split-K partial sums are added in FP64 in a fixed order, so the result is
  * deterministic. K: device, m x ldK FP64, lower triangle (i >= j) written,
  * strict upper triangle untouched. ldK >= m. */
@@ -191,6 +201,34 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda,
  * Synchronises `stream` before returning. */
 int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_step_opts* opts,
               double* dtheta, dngd_step_stats* stats, void* stream);
+
+/* Statistics of one optimiser iteration (dngd_iterate). */
+typedef struct {
+  double loss;            /* L(theta_k) = 0.5 ||r(theta_k)||^2 */
+  double lambda;          /* damping used for the step */
+  double eta;             /* chosen step length */
+  double loss_new;        /* L(theta_k + eta dtheta) */
+  double ms_line_search;  /* host wall time of the line search and update */
+  int32_t eta_index;      /* index of eta in the grid */
+  int32_t step_status;    /* dngd_step's status: DNGD_OK or DNGD_ENOCONV (PCG) */
+  dngd_step_stats step;
+} dngd_iter_stats;
+
+/* One iteration of the D-NGD training workflow (the workflow algorithm of
+ * Section 4 with the damping rule of the experiments' hyper-parameter
+ * tables): lambda_k = min(L(theta_k), lambda_cap) (or lambda_fixed when it is
+ * > 0; then lambda_cap is ignored), dtheta = dngd_step(theta, lambda_k, opts),
+ * eta = the first minimiser of L(theta + eta dtheta) over the grid etas
+ * (host, n_eta <= 48, descending order makes ties go to the longer step),
+ * and theta <- theta + eta dtheta in place.
+ * theta: device n FP64, updated. dtheta: device n FP64 or NULL (receives the
+ * step direction). stats: host or NULL. Synchronises `stream`. Returns the
+ * status of dngd_step (DNGD_OK, or DNGD_ENOCONV from a PCG step that did not
+ * reach its tolerance; theta is still updated) or an error (theta unchanged
+ * unless the error comes from the final update). */
+int dngd_iterate(dngd_problem* h, double* theta, double lambda_cap, double lambda_fixed,
+                 const dngd_step_opts* opts, int32_t n_eta, const double* etas, double* dtheta,
+                 dngd_iter_stats* stats, void* stream);
 
 #ifdef __cplusplus
 }

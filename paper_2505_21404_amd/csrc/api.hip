@@ -1,6 +1,7 @@
 // C ABI of libdngd (declared in include/dngd.h): problem handles, workspace
 // management and the D-NGD step pipelines built from the kernels in this
 // directory.
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -55,7 +56,7 @@ struct dngd_problem {
   // tangent streams (lazy)
   double *Z1 = nullptr, *Z2 = nullptr, *A1[2] = {nullptr, nullptr}, *A2[2] = {nullptr, nullptr};
   // step / solver workspace (lazy, grown on demand)
-  DevBuf J, K, vecs, work, gram_work, solve_aux, small;
+  DevBuf J, K, vecs, work, gram_work, solve_aux, small, iter;
   int J_dtype = -1;
   int64_t ldJ = 0, ldK = 0;
   hipEvent_t ev[10] = {nullptr};
@@ -231,6 +232,8 @@ int tangent(dngd_problem* h, const double* theta, const double* dir, int order, 
   return net_linear_residual(s, h->rm, h->U, nullptr, out);
 }
 
+size_t vjp_work_bytes(const Geometry& g);
+
 // theta-bar = J^T p, matrix-free (requires forward() at theta).
 int vjp(dngd_problem* h, const double* theta, const double* p, double* gout, hipStream_t s) {
   const Geometry& g = h->g;
@@ -240,9 +243,7 @@ int vjp(dngd_problem* h, const double* theta, const double* p, double* gout, hip
   const int64_t tiles = cdiv(g.max_width, 64) * cdiv(g.max_width, 64);
   int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, cdiv(512, tiles)));
   splits = (int)std::min<int64_t>(splits, std::max<int64_t>(1, g.R / 256));
-  const size_t wbytes = std::max<size_t>((size_t)splits * tiles * 64 * 64 * sizeof(double),
-                                         (size_t)64 * kMaxWidth * sizeof(double));
-  rc = ensure(h, h->work, wbytes);
+  rc = ensure(h, h->work, vjp_work_bytes(g));
   if (rc) return rc;
   double* work = static_cast<double*>(h->work.p);
   for (int l = 0; l < g.L; ++l) {
@@ -360,32 +361,9 @@ struct Precond {
   double lambda = 0;
 };
 
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// C ABI
-
-extern "C" {
-
-const char* dngd_last_error(void) { return g_err; }
-const char* dngd_version(void) { return "libdngd 0.1 (gfx950)"; }
-
-void dngd_step_opts_default(dngd_step_opts* o) {
-  if (!o) return;
-  std::memset(o, 0, sizeof(*o));
-  o->precision = DNGD_MIXED;
-  o->solver = DNGD_DENSE;
-  o->ga = 1;
-  o->ir_sweeps = 2;
-  o->gram_passes = 0;
-  o->eps_norm = 0.0;
-  o->pcg_tol = 1e-6;
-  o->pcg_maxit = 500;
-}
-
-int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
-  DNGD_REQUIRE(d && out, "dngd_problem_create: null argument");
-  *out = nullptr;
+// Checks a problem description; need_data == false skips the array pointers
+// (footprint queries before any data is on the device).
+int validate_desc(const dngd_problem_desc* d, bool need_data) {
   DNGD_REQUIRE(d->pde == DNGD_POISSON || d->pde == DNGD_HEAT, "unknown pde %d", d->pde);
   DNGD_REQUIRE(d->n_layers >= 1 && d->n_layers <= kMaxLayers, "n_layers out of range");
   DNGD_REQUIRE(d->widths != nullptr, "widths is null");
@@ -397,13 +375,15 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   DNGD_REQUIRE(d->n_int + d->n_bdy + d->n_init > 0, "no points");
   DNGD_REQUIRE(d->pde == DNGD_HEAT || d->n_init == 0, "initial points need the heat equation");
   DNGD_REQUIRE(d->pde == DNGD_POISSON || d->widths[0] >= 2, "heat needs d_in >= 2");
-  DNGD_REQUIRE((d->n_int == 0 || (d->x_int && d->f_int)) && (d->n_bdy == 0 || (d->x_bdy && d->g_bdy)) &&
-                   (d->n_init == 0 || (d->x_init && d->g_init)),
+  DNGD_REQUIRE(!need_data || ((d->n_int == 0 || (d->x_int && d->f_int)) &&
+                                (d->n_bdy == 0 || (d->x_bdy && d->g_bdy)) &&
+                                (d->n_init == 0 || (d->x_init && d->g_init))),
                "null point or target array");
   DNGD_REQUIRE(std::isfinite(d->kappa), "kappa not finite");
+  return 0;
+}
 
-  dngd_problem* h = new dngd_problem();
-  Geometry& g = h->g;
+void make_geometry(const dngd_problem_desc* d, Geometry& g) {
   g.pde = d->pde;
   g.L = d->n_layers;
   int64_t off = 0;
@@ -430,6 +410,88 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   g.c_int = g.n_int ? 1.0 / std::sqrt((double)g.n_int) : 0.0;
   g.c_bdy = g.n_bdy ? 1.0 / std::sqrt((double)g.n_bdy) : 0.0;
   g.c_init = g.n_init ? 1.0 / std::sqrt((double)g.n_init) : 0.0;
+}
+
+size_t vjp_work_bytes(const Geometry& g) {
+  const int64_t tiles = cdiv(g.max_width, 64) * cdiv(g.max_width, 64);
+  int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, cdiv(512, tiles)));
+  splits = (int)std::min<int64_t>(splits, std::max<int64_t>(1, g.R / 256));
+  return std::max<size_t>((size_t)splits * tiles * 64 * 64 * sizeof(double),
+                          (size_t)64 * kMaxWidth * sizeof(double));
+}
+
+// Rows of recomputed Jacobian per chunk of the Nystrom column build (~4 GB).
+int64_t nystrom_chunk_rows(const Geometry& g) {
+  const int64_t ldJ = round_up(g.n, 256);
+  return std::max<int64_t>(1, std::min<int64_t>(g.m, (int64_t)(4e9 / (ldJ * 8.0))));
+}
+
+// Device bytes a handle holds after a step with options o (activations,
+// tangent streams, vectors, J, K, Gram and solve workspaces), excluding the
+// copies of the point arrays.
+size_t footprint_bytes(const Geometry& g, const dngd_step_opts* o) {
+  dngd_step_opts def;
+  dngd_step_opts_default(&def);
+  if (!o) o = &def;
+  size_t b = 0;
+  b += (size_t)g.R * g.d_in * 8 + 2 * (size_t)act_bytes(g) + 2 * (size_t)g.R * 8;
+  for (int l = 0; l < g.L - 1; ++l) b += 3 * (size_t)g.R * g.widths[l + 1] * 8;
+  if (o->ga || o->solver == DNGD_PCG) b += 6 * (size_t)act_bytes(g);
+  b += step_vec_bytes(g) + vjp_work_bytes(g) + (size_t)g.n * 8 + 256;
+  if (o->solver == DNGD_DENSE) {
+    const int jd = (o->precision == DNGD_PLAIN) ? DNGD_F64 : DNGD_F32;
+    const int64_t ldJ = round_up(g.n, 256);
+    b += (size_t)g.m * ldJ * (jd == DNGD_F64 ? 8 : 4);
+    b += (size_t)g.m * g.m * 8 + chol_solve_aux_bytes(g.m);
+    b += gram_workspace_bytes(g.m, g.n, jd, 3, nullptr);
+  } else {
+    const int64_t ell = std::max<int64_t>(1, o->n_landmarks);
+    const int64_t ldJ = round_up(g.n, 256), ldM = round_up(g.m, 4);
+    const int64_t chunk = nystrom_chunk_rows(g);
+    b += (size_t)(ell + chunk) * ldJ * 8;
+    b += (size_t)ell * ldM * 8 + (size_t)ell * ell * 8 + (size_t)std::max(chunk, ell) * 8 +
+         (size_t)ell * 8 + chol_solve_aux_bytes(ell);
+    b += gram_workspace_bytes(ell, g.m, DNGD_F64, 1, nullptr);
+  }
+  return b;
+}
+
+// losses[k] = 0.5 ||r(theta + etas[k] dtheta)||^2 (host array); synchronises s
+int losses_impl(dngd_problem* h, const double* theta, const double* dtheta, int n_eta,
+                const double* etas, double* losses, hipStream_t s);
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char* dngd_last_error(void) { return g_err; }
+const char* dngd_version(void) { return "libdngd 0.1 (gfx950)"; }
+
+void dngd_step_opts_default(dngd_step_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = DNGD_MIXED;
+  o->solver = DNGD_DENSE;
+  o->ga = 1;
+  o->ir_sweeps = 2;
+  o->gram_passes = 0;
+  o->eps_norm = 0.0;
+  o->pcg_tol = 1e-6;
+  o->pcg_maxit = 500;
+}
+
+int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
+  DNGD_REQUIRE(d && out, "dngd_problem_create: null argument");
+  *out = nullptr;
+  int vrc = validate_desc(d, true);
+  if (vrc) return vrc;
+
+  dngd_problem* h = new dngd_problem();
+  Geometry& g = h->g;
+  make_geometry(d, g);
   h->rm = row_map(g);
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
 
@@ -486,29 +548,18 @@ int64_t dngd_jacobian_ld(const dngd_problem* h) { return h ? round_up(h->g.n, 25
 
 int dngd_footprint(const dngd_problem* h, const dngd_step_opts* o, size_t* bytes) {
   DNGD_REQUIRE(h && bytes, "dngd_footprint: null argument");
-  dngd_step_opts def;
-  dngd_step_opts_default(&def);
-  if (!o) o = &def;
-  const Geometry& g = h->g;
-  size_t b = 0;
-  b += (size_t)g.R * g.d_in * 8 + 2 * (size_t)act_bytes(g) + 2 * (size_t)g.R * 8;
-  for (int l = 0; l < g.L - 1; ++l) b += 3 * (size_t)g.R * g.widths[l + 1] * 8;
-  if (o->ga || o->solver == DNGD_PCG) b += 6 * (size_t)act_bytes(g);
-  b += step_vec_bytes(g);
-  if (o->solver == DNGD_DENSE) {
-    const int jd = (o->precision == DNGD_PLAIN) ? DNGD_F64 : DNGD_F32;
-    const int64_t ldJ = round_up(g.n, 256);
-    b += (size_t)g.m * ldJ * (jd == DNGD_F64 ? 8 : 4);
-    b += (size_t)g.m * g.m * 8 + chol_solve_aux_bytes(g.m) + 64;
-    b += gram_workspace_bytes(g.m, g.n, jd, 3, nullptr);
-  } else {
-    const int64_t ell = o->n_landmarks;
-    const int64_t ldJ = round_up(g.n, 256);
-    b += (size_t)ell * ldJ * 8 + (size_t)ell * g.m * 8 + (size_t)ell * ell * 8 +
-         chol_solve_aux_bytes(ell);
-    b += (size_t)std::min<int64_t>(g.m, 256) * ldJ * 8;
-  }
-  *bytes = b;
+  *bytes = footprint_bytes(h->g, o);
+  return DNGD_OK;
+}
+
+int dngd_footprint_desc(const dngd_problem_desc* d, const dngd_step_opts* o, size_t* bytes) {
+  DNGD_REQUIRE(d && bytes, "dngd_footprint_desc: null argument");
+  int rc = validate_desc(d, false);
+  if (rc) return rc;
+  Geometry g;
+  make_geometry(d, g);
+  *bytes = footprint_bytes(g, o) + (size_t)(g.n_int * (g.d_in + 1) + g.n_bdy * (g.d_in + 1) +
+                                            g.n_init * (g.d_in + 1)) * sizeof(double);
   return DNGD_OK;
 }
 
@@ -533,7 +584,8 @@ int dngd_gram(int64_t m, int64_t n, const void* J, int64_t ldJ, int32_t j_dtype,
   DNGD_REQUIRE(J && K, "dngd_gram: null pointer");
   DNGD_REQUIRE(m > 0 && n > 0 && ldJ >= n && ldK >= m, "dngd_gram: bad sizes");
   DNGD_REQUIRE(j_dtype == DNGD_F64 || j_dtype == DNGD_F32, "dngd_gram: bad j_dtype");
-  DNGD_REQUIRE(j_dtype == DNGD_F64 || passes == 1 || passes == 3, "dngd_gram: passes 1 or 3");
+  DNGD_REQUIRE(j_dtype == DNGD_F64 || passes == 1 || passes == 3 || passes == 4,
+               "dngd_gram: passes 1, 3 or 4");
   DNGD_REQUIRE(std::isfinite(lambda), "dngd_gram: lambda not finite");
   DNGD_REQUIRE(j_dtype == DNGD_F64 || ldJ % 4 == 0, "dngd_gram: FP32 J needs ldJ %% 4 == 0");
   hipStream_t s = S(stream);
@@ -609,7 +661,15 @@ int dngd_losses(dngd_problem* h, const double* theta, const double* dtheta, int3
                 const double* etas, double* losses, void* stream) {
   DNGD_REQUIRE(h && theta && dtheta && etas && losses && n_eta > 0 && n_eta <= 48,
                "dngd_losses: bad argument");
-  hipStream_t s = S(stream);
+  return losses_impl(h, theta, dtheta, n_eta, etas, losses, S(stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+int losses_impl(dngd_problem* h, const double* theta, const double* dtheta, int n_eta,
+                const double* etas, double* losses, hipStream_t s) {
   StepVecs v;
   int rc = carve_vecs(h, v);
   if (rc) return rc;
@@ -626,7 +686,7 @@ int dngd_losses(dngd_problem* h, const double* theta, const double* dtheta, int3
   return DNGD_OK;
 }
 
-}  // extern "C"
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // Nystrom-PCG (Sections 3.3, 4.2)
@@ -654,7 +714,7 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
   }
   const int64_t ldJ = round_up(g.n, 256);
   const int64_t ldM = round_up(g.m, 4);
-  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(g.m, (int64_t)(4e9 / (ldJ * 8.0))));
+  const int64_t chunk = nystrom_chunk_rows(g);
   // J_I (ell x ldJ) and a chunk of J rows; Mt (ell x ldM), G (ell x ell), index list, ell scratch
   const size_t bJI = (size_t)ell * ldJ * 8, bMt = (size_t)ell * ldM * 8, bG = (size_t)ell * ell * 8;
   const size_t bCh = (size_t)chunk * ldJ * 8, bIdx = (size_t)std::max<int64_t>(chunk, ell) * 8;
@@ -871,7 +931,9 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   DNGD_REQUIRE(o.precision == DNGD_PLAIN || o.precision == DNGD_MIXED, "bad precision");
   DNGD_REQUIRE(o.solver == DNGD_DENSE || o.solver == DNGD_PCG, "bad solver");
   DNGD_REQUIRE(o.ir_sweeps >= 0 && o.ir_sweeps <= 8, "ir_sweeps must be in [0, 8]");
-  DNGD_REQUIRE(o.gram_passes == 0 || o.gram_passes == 1 || o.gram_passes == 3, "bad gram_passes");
+  DNGD_REQUIRE(o.gram_passes == 0 || o.gram_passes == 1 || o.gram_passes == 3 ||
+                   o.gram_passes == 4,
+               "bad gram_passes");
   const Geometry& g = h->g;
   hipStream_t s = S(stream);
   StepVecs v;
@@ -907,9 +969,9 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     if (!rc) rc = sumsq(s, g.n, dtheta, v.scal + 8, v.red);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[7], s));
-    DNGD_HIP(hipEventSynchronize(h->ev[7]));
     double vn2 = 0;
-    DNGD_HIP(hipMemcpy(&vn2, v.scal + 8, 8, hipMemcpyDeviceToHost));
+    DNGD_HIP(hipMemcpyAsync(&vn2, v.scal + 8, 8, hipMemcpyDeviceToHost, s));
+    DNGD_HIP(hipStreamSynchronize(s));
     float ms = 0;
     hipEventElapsedTime(&ms, h->ev[0], h->ev[7]);
     st.ms_total = ms;
@@ -957,23 +1019,38 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     st.max_row_norm2 = dmax;
     if (passes == 0) {
       // bf16 unit roundoff 2^-8 times sqrt(D / lam) estimates the refinement
-      // contraction of a 1-pass Gram; split when it would exceed 1/50.
-      passes = (std::ldexp(1.0, -8) * std::sqrt(dmax / lambda) > 0.02) ? 3 : 1;
+      // contraction of a 1-pass Gram; split when it would exceed 1/50. The
+      // split without lo lo^T is indefinite by ~2^-16 D: keep it only while
+      // that is below lam / 10, else add the fourth product.
+      if (std::ldexp(1.0, -8) * std::sqrt(dmax / lambda) <= 0.02) passes = 1;
+      else if (std::ldexp(1.0, -16) * dmax <= 0.1 * lambda) passes = 3;
+      else passes = 4;
     }
   }
-  st.gram_passes_used = passes;
-  const size_t gw = gram_workspace_bytes(g.m, g.n, jd, passes, nullptr);
-  rc = ensure(h, h->gram_work, gw);
-  if (!rc)
-    rc = gram_launch(s, g.m, g.n, J, ldJ, jd, passes, lambda, K, g.m, h->gram_work.p, gw, h->ev[8],
-                     h->ev[9]);
-  if (rc) return rc;
-  DNGD_HIP(hipEventRecord(h->ev[2], s));
-
-  // Cholesky of K + lam I
   rc = ensure(h, h->solve_aux, chol_solve_aux_bytes(g.m));
-  if (!rc) rc = chol_factor(s, g.m, K, g.m, sm.info, nullptr);
-  if (!rc) rc = chol_prepare_solve(s, g.m, K, g.m, static_cast<double*>(h->solve_aux.p));
+  if (rc) return rc;
+  int64_t info = 0;
+  for (int attempt = 0;; ++attempt) {
+    const size_t gw = gram_workspace_bytes(g.m, g.n, jd, passes, nullptr);
+    rc = ensure(h, h->gram_work, gw);
+    if (!rc)
+      rc = gram_launch(s, g.m, g.n, J, ldJ, jd, passes, lambda, K, g.m, h->gram_work.p, gw,
+                       h->ev[8], h->ev[9]);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[2], s));
+    // Cholesky of K + lam I
+    rc = chol_factor(s, g.m, K, g.m, sm.info, nullptr);
+    if (rc) return rc;
+    if (jd == DNGD_F64 || passes == 4 || attempt > 0) break;
+    // mixed path: a failed factorisation is retried once with the
+    // positive semidefinite 4-product Gram
+    DNGD_HIP(hipMemcpyAsync(&info, sm.info, 8, hipMemcpyDeviceToHost, s));
+    DNGD_HIP(hipStreamSynchronize(s));
+    if (info == 0) break;
+    passes = 4;
+  }
+  st.gram_passes_used = passes;
+  rc = chol_prepare_solve(s, g.m, K, g.m, static_cast<double*>(h->solve_aux.p));
   if (rc) return rc;
   DNGD_HIP(hipEventRecord(h->ev[3], s));
 
@@ -1006,14 +1083,13 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     if (rc) return rc;
   }
   DNGD_HIP(hipEventRecord(h->ev[6], s));
-  DNGD_HIP(hipEventSynchronize(h->ev[6]));
 
   double sc[32];
-  DNGD_HIP(hipMemcpy(sc, v.scal, sizeof(sc), hipMemcpyDeviceToHost));
-  int64_t info = 0;
   int gaf = 0;
-  DNGD_HIP(hipMemcpy(&info, sm.info, 8, hipMemcpyDeviceToHost));
-  DNGD_HIP(hipMemcpy(&gaf, sm.ga_flag, sizeof(int), hipMemcpyDeviceToHost));
+  DNGD_HIP(hipMemcpyAsync(sc, v.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipMemcpyAsync(&info, sm.info, 8, hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipMemcpyAsync(&gaf, sm.ga_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
   float ms = 0;
   hipEventElapsedTime(&ms, h->ev[0], h->ev[6]);
   st.ms_total = ms;
@@ -1048,6 +1124,69 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     return DNGD_ENAN;
   }
   return DNGD_OK;
+}
+
+
+// One iteration of the D-NGD workflow (damping rule, step, grid line search,
+// update), see include/dngd.h.
+int dngd_iterate(dngd_problem* h, double* theta, double lambda_cap, double lambda_fixed,
+                 const dngd_step_opts* opts, int32_t n_eta, const double* etas, double* dtheta,
+                 dngd_iter_stats* stats, void* stream) {
+  DNGD_REQUIRE(h && theta && etas && n_eta > 0 && n_eta <= 48, "dngd_iterate: bad argument");
+  DNGD_REQUIRE((lambda_fixed > 0.0 && std::isfinite(lambda_fixed)) ||
+                   (lambda_fixed == 0.0 && lambda_cap > 0.0 && std::isfinite(lambda_cap)),
+               "dngd_iterate: need lambda_fixed > 0, or lambda_fixed == 0 and lambda_cap > 0");
+  for (int k = 0; k < n_eta; ++k)
+    DNGD_REQUIRE(std::isfinite(etas[k]), "dngd_iterate: non-finite step length");
+  const Geometry& g = h->g;
+  hipStream_t s = S(stream);
+  int rc = ensure(h, h->iter, (size_t)g.n * sizeof(double));
+  if (rc) return rc;
+  double* dth = static_cast<double*>(h->iter.p);
+  StepVecs v;
+  rc = carve_vecs(h, v);
+  if (rc) return rc;
+
+  // L(theta_k) and the damping lambda_k = min(L(theta_k), cap)
+  rc = forward(h, theta, v.tmpm, s);
+  if (!rc) rc = sumsq(s, g.m, v.tmpm, v.scal + 56, v.red);
+  if (rc) return rc;
+  double rr = 0.0;
+  DNGD_HIP(hipMemcpyAsync(&rr, v.scal + 56, 8, hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
+  const double L0 = 0.5 * rr;
+  DNGD_REQUIRE(std::isfinite(L0), "dngd_iterate: non-finite loss at theta");
+  double lam = (lambda_fixed > 0.0) ? lambda_fixed : std::min(L0, lambda_cap);
+  lam = std::max(lam, 1e-300);  // L = 0 exactly: any positive damping gives dtheta = 0
+
+  dngd_iter_stats st;
+  std::memset(&st, 0, sizeof(st));
+  const int sst = dngd_step(h, theta, lam, opts, dth, &st.step, stream);
+  if (sst < 0) return sst;
+
+  // grid line search: the first minimiser wins ties; NaN losses never win
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> L(n_eta);
+  rc = losses_impl(h, theta, dth, n_eta, etas, L.data(), s);
+  if (rc) return rc;
+  int best = -1;
+  for (int k = 0; k < n_eta; ++k)
+    if (std::isfinite(L[k]) && (best < 0 || L[k] < L[best])) best = k;
+  DNGD_REQUIRE(best >= 0, "dngd_iterate: every line-search loss is non-finite");
+  rc = axpy(s, g.n, etas[best], dth, theta);
+  if (!rc && dtheta) rc = copy(s, g.n, dth, dtheta);
+  if (rc) return rc;
+  DNGD_HIP(hipStreamSynchronize(s));
+  st.ms_line_search =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  st.loss = L0;
+  st.lambda = lam;
+  st.eta = etas[best];
+  st.eta_index = best;
+  st.loss_new = L[best];
+  st.step_status = sst;
+  if (stats) *stats = st;
+  return sst;
 }
 
 }  // extern "C"

@@ -8,8 +8,11 @@
 // Mixed path (FP32 J): v_mfma_f32_32x32x16_bf16 with FP32 accumulation. J is
 // rounded to bf16 in registers right before the MFMAs (no bf16 copy of J in
 // HBM). PASSES == 3 keeps the rounding residual as a second bf16 term,
-// J = hi + lo, and accumulates hi hi^T + hi lo^T + lo hi^T (the lo lo^T term
-// is below FP32 resolution), so K carries ~16 bits of J instead of 8.
+// J ~ hi + lo, and accumulates hi hi^T + hi lo^T + lo hi^T, so K carries ~16
+// bits of J instead of 8. Dropping lo lo^T makes that K indefinite by up to
+// ||lo lo^T|| (~2^-16 max_i ||J_i||^2), which matters only when the damping is
+// that small; PASSES == 4 adds lo lo^T, so K = (hi + lo)(hi + lo)^T is
+// positive semidefinite up to the FP32 accumulation error.
 // Plain path (FP64 J): the FP64 MFMA GEMM in split-K partial mode.
 //
 // Only lower-triangle tiles are launched. Tiles are numbered row-major over
@@ -82,7 +85,8 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
                                                         float* __restrict__ work,
                                                         int64_t k_per_split, int64_t ntiles,
                                                         int64_t per_xcd, int splits) {
-  constexpr bool LO = (PASSES == 3);
+  constexpr bool LO = (PASSES >= 3);
+  constexpr bool LOLO = (PASSES == 4);
   __shared__ float4 sA0[BT * ROWCH];
   __shared__ float4 sB0[BT * ROWCH];
   __shared__ float4 sA1[BT * ROWCH];
@@ -177,6 +181,11 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
 #pragma unroll
           for (int j = 0; j < 2; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.h, bh[j].h, acc[i][j], 0, 0, 0);
+        }
+        if (LOLO) {
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.h, bl[j].h, acc[i][j], 0, 0, 0);
         }
       }
     }
@@ -289,13 +298,17 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
     return 0;
   }
   DNGD_REQUIRE(ldJ % 4 == 0, "gram: FP32 J needs ldJ %% 4 == 0");
-  DNGD_REQUIRE(passes == 1 || passes == 3, "gram: passes must be 1 or 3");
+  DNGD_REQUIRE(passes == 1 || passes == 3 || passes == 4, "gram: passes must be 1, 3 or 4");
   const int64_t nt = lower_tiles(m, BT);
   const int64_t kps = round_up(cdiv(n, splits), BKE);
   const int64_t per_xcd = cdiv(nt * splits, NXCD);
   // one workgroup per (split, tile); the kernel derives both from blockIdx.x
   const dim3 grid((unsigned)(per_xcd * NXCD));
-  if (passes == 3)
+  if (passes == 4)
+    hipLaunchKernelGGL(gram_bf16_kernel<4>, grid, dim3(512), 0, st, m, n,
+                       static_cast<const float*>(J), ldJ, static_cast<float*>(work), kps, nt,
+                       per_xcd, splits);
+  else if (passes == 3)
     hipLaunchKernelGGL(gram_bf16_kernel<3>, grid, dim3(512), 0, st, m, n,
                        static_cast<const float*>(J), ldJ, static_cast<float*>(work), kps, nt,
                        per_xcd, splits);

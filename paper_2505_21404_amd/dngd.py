@@ -63,11 +63,23 @@ class StepStats(C.Structure):
         return d
 
 
+class IterStats(C.Structure):
+    _fields_ = [("loss", C.c_double), ("lam", C.c_double), ("eta", C.c_double),
+                ("loss_new", C.c_double), ("ms_line_search", C.c_double),
+                ("eta_index", C.c_int32), ("step_status", C.c_int32), ("step", StepStats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "step"}
+        d["step"] = self.step.as_dict()
+        return d
+
+
 EXPORTS = [
     "dngd_last_error", "dngd_version", "dngd_step_opts_default", "dngd_problem_create",
     "dngd_problem_destroy", "dngd_num_params", "dngd_num_residuals", "dngd_jacobian_ld",
     "dngd_footprint", "dngd_residual_jacobian", "dngd_gram", "dngd_cholesky_solve", "dngd_fvv",
-    "dngd_jvp", "dngd_vjp", "dngd_losses", "dngd_nystrom_pcg", "dngd_step",
+    "dngd_jvp", "dngd_vjp", "dngd_losses", "dngd_nystrom_pcg", "dngd_step", "dngd_iterate",
+    "dngd_footprint_desc",
 ]
 
 
@@ -86,6 +98,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "dngd_num_residuals": (i64, [vp]),
         "dngd_jacobian_ld": (i64, [vp]),
         "dngd_footprint": (C.c_int, [vp, C.POINTER(StepOpts), C.POINTER(C.c_size_t)]),
+        "dngd_footprint_desc": (C.c_int, [C.POINTER(ProblemDesc), C.POINTER(StepOpts),
+                                          C.POINTER(C.c_size_t)]),
         "dngd_residual_jacobian": (C.c_int, [vp, vp, vp, vp, i64, i32, vp]),
         "dngd_gram": (C.c_int, [i64, i64, vp, i64, i32, i32, dbl, vp, i64, vp]),
         "dngd_cholesky_solve": (C.c_int, [i64, vp, i64, i32, i64, vp, i64, C.POINTER(i64), vp]),
@@ -96,6 +110,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "dngd_nystrom_pcg": (C.c_int, [vp, vp, dbl, vp, i64, dbl, i64, vp, vp,
                                        C.POINTER(StepStats), vp]),
         "dngd_step": (C.c_int, [vp, vp, dbl, C.POINTER(StepOpts), vp, C.POINTER(StepStats), vp]),
+        "dngd_iterate": (C.c_int, [vp, vp, dbl, dbl, C.POINTER(StepOpts), i32, C.POINTER(dbl), vp,
+                                   C.POINTER(IterStats), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -139,6 +155,7 @@ def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0
     if landmarks is not None:
         o.n_landmarks = landmarks.numel()
         o.landmarks = landmarks.data_ptr()
+        o._landmarks_ref = landmarks   # the options hold a device pointer into it
     o.pcg_tol, o.pcg_maxit = pcg_tol, pcg_maxit
     return o
 
@@ -157,6 +174,9 @@ class Problem:
         d.n_int, d.n_bdy, d.n_init = arrs[0].shape[0], arrs[1].shape[0], arrs[2].shape[0]
         d.x_int, d.x_bdy, d.x_init = [a.data_ptr() if a.numel() else None for a in arrs[:3]]
         d.f_int, d.g_bdy, d.g_init = [a.data_ptr() if a.numel() else None for a in arrs[3:]]
+        # the device copies above were enqueued on the current stream; the
+        # handle copies them with a synchronous call on the legacy stream
+        torch.cuda.current_stream(self.device).synchronize()
         h = C.c_void_p()
         _check(_lib.dngd_problem_create(C.byref(d), C.byref(h)))
         self._h = h
@@ -244,6 +264,19 @@ class Problem:
                               _ptr(dth), C.byref(st), _stream(stream)), allow=(OK, ENOCONV))
         return dth, st
 
+    def iterate(self, theta: torch.Tensor, etas, lam_cap: float = 0.0, fixed_lambda: float = 0.0,
+                opts: Optional[StepOpts] = None, dtheta_out=None, stream=None) -> IterStats:
+        """One D-NGD workflow iteration; ``theta`` (device FP64, contiguous) is
+        updated in place."""
+        assert theta.dtype == torch.float64 and theta.is_contiguous() and theta.numel() == self.n
+        etas = [float(e) for e in etas]
+        ea = (C.c_double * len(etas))(*etas)
+        st = IterStats()
+        _check(_lib.dngd_iterate(self._h, _ptr(theta), float(lam_cap), float(fixed_lambda),
+                                 C.byref(opts) if opts else None, len(etas), ea, _ptr(dtheta_out),
+                                 C.byref(st), _stream(stream)), allow=(OK, ENOCONV))
+        return st
+
     def nystrom_pcg(self, theta, lam, landmarks: torch.Tensor, b, tol=1e-6, maxit=500,
                     stream=None):
         th = self._theta(theta)
@@ -255,6 +288,19 @@ class Problem:
                                           float(tol), int(maxit), _ptr(bb), _ptr(x), C.byref(st),
                                           _stream(stream)), allow=(OK, ENOCONV))
         return x, st, rc
+
+
+def footprint_of(pde: int, widths: Sequence[int], n_int: int, n_bdy: int, n_init: int = 0,
+                 opts: Optional[StepOpts] = None) -> int:
+    """Device bytes a problem of this shape holds after a step with ``opts``
+    (dngd_footprint_desc); host-only, allocates nothing."""
+    w = (C.c_int32 * len(widths))(*[int(x) for x in widths])
+    d = ProblemDesc()
+    d.pde, d.n_layers, d.widths, d.kappa = pde, len(widths) - 1, w, 0.0
+    d.n_int, d.n_bdy, d.n_init = int(n_int), int(n_bdy), int(n_init)
+    b = C.c_size_t()
+    _check(_lib.dngd_footprint_desc(C.byref(d), C.byref(opts) if opts else None, C.byref(b)))
+    return int(b.value)
 
 
 def gram(J: torch.Tensor, n: int, lam: float, passes: int = 1, stream=None) -> torch.Tensor:

@@ -104,7 +104,7 @@ def test_gram_f64(m, n):
     assert np.all(np.triu(K, 1) == 0.0)
 
 
-@pytest.mark.parametrize("passes", [1, 3])
+@pytest.mark.parametrize("passes", [1, 3, 4])
 @pytest.mark.parametrize("m,n", [(70, 333), (300, 5003), (700, 20000)])
 def test_gram_bf16(m, n, passes):
     say("case gram_bf16", m, n, passes)
@@ -119,8 +119,10 @@ def test_gram_bf16(m, n, passes):
     lo = (Jt - hi.to(torch.float32)).to(torch.bfloat16).to(torch.float64)
     if passes == 1:
         ref = (hi @ hi.T).numpy()
-    else:
+    elif passes == 3:
         ref = (hi @ hi.T + hi @ lo.T + lo @ hi.T).numpy()
+    else:
+        ref = ((hi + lo) @ (hi + lo).T).numpy()
     a = np.abs(J.astype(np.float64))
     bound = (a @ a.T) * (n ** 0.5 * 2.0 ** -22) + 1e-30   # FP32 accumulation
     low = np.tril_indices(m)
@@ -129,6 +131,21 @@ def test_gram_bf16(m, n, passes):
     exact = J.astype(np.float64) @ J.astype(np.float64).T
     err = np.abs(K[low] - exact[low]).max() / np.abs(exact).max()
     assert err <= (2e-2 if passes == 1 else 2e-4), err
+
+
+def test_gram_bf16_four_products_is_semidefinite():
+    """Rank-deficient J (m > n): the exact Gram is singular. The 4-product
+    split Gram is (hi + lo)(hi + lo)^T up to FP32 accumulation, so its
+    smallest eigenvalue stays within that error of zero."""
+    m, n = 600, 200
+    rng = np.random.default_rng(9)
+    J = (rng.standard_normal((m, n)) @ np.diag(np.linspace(0.1, 2.0, n))).astype(np.float32)
+    K = D().gram(torch.tensor(J, device="cuda"), n, 0.0, passes=4).cpu().numpy()
+    K = np.tril(K) + np.tril(K, -1).T
+    ev = np.linalg.eigvalsh(K)
+    dmax = np.diag(K).max()
+    say("4-pass min eig", ev[0], "D", dmax)
+    assert ev[0] >= -n ** 0.5 * 2.0 ** -22 * dmax
 
 
 @pytest.mark.parametrize("m", [1, 2, 63, 64, 65, 130, 700])

@@ -1,0 +1,189 @@
+"""GPU parity of the workflow layers above the step: the D-NGD training loop
+(dngd_iterate: damping rule, line search, update), the autograd.Function of
+the residual map, and the Nystrom-PCG solver, each against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import network as N
+from oracle import nystrom as NY
+from oracle import step as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def D():
+    from paper_2505_21404_amd import dngd
+    return dngd
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# --------------------------------------------------------------------------
+# training loop (a9)
+
+def test_config0_training_20_steps():
+    """Config 0 (2-D Poisson, m = 500, plain FP64, lambda = 1e-8, GA): 20
+    iterations. The step is checked against the oracle at the GPU's own
+    iterates (line-search ties may differ), the line search against the
+    oracle's losses, the loss must not increase, and the final relative L2
+    error against u* = sin(pi x) sin(pi y) must reach the 1e-2 gate."""
+    from paper_2505_21404_amd import driver
+    d = D()
+    p = W.config(0)
+    th0 = W.glorot_theta(p.widths, 0)
+    prob = d.Problem.from_workload(p)
+    thetas, dirs = [], []
+    dbuf = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    theta = torch.tensor(th0, device="cuda")
+    hist = []
+    for k in range(20):
+        thetas.append(theta.cpu().numpy().copy())
+        st = prob.iterate(theta, driver.ETA_GRID, fixed_lambda=1e-8,
+                          opts=d.step_opts(precision=d.PLAIN, ga=True), dtheta_out=dbuf)
+        dirs.append(dbuf.cpu().numpy().copy())
+        hist.append(st.as_dict())
+        say(f"iter {k} loss {st.loss:.6e} eta {st.eta:.3g} -> {st.loss_new:.6e}")
+    thT = theta.cpu().numpy()
+    losses = [h["loss"] for h in hist] + [hist[-1]["loss_new"]]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(losses, losses[1:]))
+    u64 = np.finfo(np.float64).eps / 2
+    for k in (0, 7, 19):
+        ref = S.dense_step(p, thetas[k], 1e-8, ga=True)
+        e = rel(dirs[k], ref.dtheta)
+        # lambda = 1e-8 is conditioning-limited: both sides are backward
+        # stable, so they may differ by ~ u64 cond(K + lambda I)
+        cond = np.linalg.cond(ref.K + 1e-8 * np.eye(p.m))
+        say("step", k, "rel err vs oracle", e, "u64 * cond", u64 * cond)
+        assert e <= max(1e-10, 10 * u64 * cond)
+        assert hist[k]["step"]["ga_accepted"] == int(ref.accepted)
+        # at moderate damping the same iterate is checked tightly
+        ref6 = S.dense_step(p, thetas[k], 1e-6, ga=True)
+        d6, _ = prob.step(thetas[k], 1e-6, d.step_opts(precision=d.PLAIN, ga=True))
+        e6 = rel(d6.cpu().numpy(), ref6.dtheta)
+        cond6 = np.linalg.cond(ref6.K + 1e-6 * np.eye(p.m))
+        say("step", k, "lambda 1e-6 rel err", e6, "u64 * cond", u64 * cond6)
+        assert e6 <= max(1e-10, 10 * u64 * cond6)
+        # the line search at this iterate against the oracle's losses
+        eta, ls = S.line_search(p, thetas[k], dirs[k])
+        assert abs(ls.min() - hist[k]["loss_new"]) <= 1e-10 * ls.min() + 1e-300
+        assert np.isclose(ls[hist[k]["eta_index"]], ls.min(), rtol=1e-9, atol=0)
+    # the update itself: theta_{k+1} = theta_k + eta dtheta
+    k = 19
+    assert rel(thT, thetas[k] + hist[k]["eta"] * dirs[k]) <= 1e-15
+    xe = W.eval_points(p, 10_000, 0)
+    l2 = N.relative_l2(p, thT, xe, W.exact_solution("sinsin", xe))
+    say("relative L2 after 20 iterations", l2)
+    assert l2 <= 1e-2
+    prob.close()
+
+
+def test_driver_train_damping_rule():
+    """driver.train with the damping rule lambda_k = min(L(theta_k), cap):
+    the lambda it reports is min(loss, cap) and theta moves as recorded."""
+    from paper_2505_21404_amd import driver
+    d = D()
+    p = W.config(1, scale=dict(widths=[5, 24, 24, 1], n_int=300, n_bdy=80))
+    th0 = W.glorot_theta(p.widths, 3)
+    prob = d.Problem.from_workload(p)
+    theta, hist = driver.train(prob, th0, 4, lam_cap=1e-5, opts=d.step_opts(precision=d.MIXED))
+    for h in hist:
+        assert h["lam"] == min(h["loss"], 1e-5)
+        assert h["loss_new"] <= h["loss"]
+    assert abs(hist[0]["loss"] - N.loss(p, th0)) <= 1e-12 * hist[0]["loss"]
+    assert abs(N.loss(p, theta.cpu().numpy()) - hist[-1]["loss_new"]) <= 1e-10 * hist[-1]["loss_new"]
+    prob.close()
+
+
+# --------------------------------------------------------------------------
+# autograd.Function (a13)
+
+def test_autograd_gradcheck_and_oracle_gradient():
+    from paper_2505_21404_amd import autograd as AG
+    d = D()
+    p = W.heat_problem([3, 6, 5, 1], 9, 4, 3, 0.2, 11)
+    prob = d.Problem.from_workload(p)
+    th0 = 0.8 * np.random.default_rng(2).standard_normal(p.n_params)
+    th = torch.tensor(th0, device="cuda", requires_grad=True)
+    say("case gradcheck heat", p.widths, p.m)
+    assert torch.autograd.gradcheck(lambda t: AG.residual(prob, t), (th,), eps=1e-6, atol=1e-7,
+                                    rtol=1e-5)
+    # backward against the oracle's J^T r_bar, and the loss gradient J^T r
+    rbar = np.random.default_rng(3).standard_normal(p.m)
+    r = AG.residual(prob, th)
+    (g,) = torch.autograd.grad(r, th, torch.tensor(rbar, device="cuda"))
+    J = N.jacobian(p, th0)
+    assert rel(g.cpu().numpy(), J.T @ rbar) <= 1e-12
+    th.grad = None
+    AG.loss(prob, th).backward()
+    assert rel(th.grad.cpu().numpy(), J.T @ N.residual(p, th0)) <= 1e-12
+    prob.close()
+
+
+# --------------------------------------------------------------------------
+# Nystrom-PCG (a10 - a12)
+
+def _pcg_case(ell, lam, tol, seed=0):
+    d = D()
+    p = W.config(1, scale=dict(widths=[5, 32, 32, 1], n_int=240, n_bdy=60))
+    th = W.glorot_theta(p.widths, seed)
+    prob = d.Problem.from_workload(p)
+    r = N.residual(p, th)
+    J = N.jacobian(p, th)
+    I = W.landmarks(p.m, ell, seed)
+    x, st, rc = prob.nystrom_pcg(th, lam, torch.tensor(I), r, tol=tol, maxit=500)
+    return d, p, th, prob, r, J, I, x.cpu().numpy(), st, rc
+
+
+@pytest.mark.parametrize("ell", [30, 120])
+def test_pcg_matches_dense_solution(ell):
+    lam, tol = 1e-4, 1e-10
+    d, p, th, prob, r, J, I, x, st, rc = _pcg_case(ell, lam, tol)
+    say("case pcg ell", ell, "iters", st.pcg_iterations, "rel res", st.pcg_rel_residual)
+    assert rc == d.OK and st.pcg_converged
+    K = J @ J.T
+    alpha = S.solve(S.cholesky(K, lam), r)
+    # the true residual in FP64 and the distance to the dense solution
+    true_res = np.linalg.norm((K + lam * np.eye(p.m)) @ x - r) / np.linalg.norm(r)
+    assert true_res <= 10 * tol
+    cond = np.linalg.cond(K + lam * np.eye(p.m))
+    assert rel(x, alpha) <= 10 * tol * cond
+    # iteration count against the oracle's PCG with the same landmarks
+    _, _, its_o, ok_o = NY.pcg_step(J, r, lam, I, tol, 500)
+    say("iterations gpu", st.pcg_iterations, "oracle", its_o)
+    assert ok_o and abs(st.pcg_iterations - its_o) <= max(2, its_o // 5)
+    prob.close()
+
+
+def test_pcg_all_landmarks_converges_at_once():
+    """ell = m: the preconditioner is (K + lam I)^{-1} up to the K_II shift,
+    so PCG stops after one or two iterations."""
+    d, p, th, prob, r, J, I, x, st, rc = _pcg_case(300, 1e-3, 1e-8)
+    say("case pcg ell = m, iters", st.pcg_iterations)
+    assert rc == d.OK and st.pcg_iterations <= 2
+    prob.close()
+
+
+def test_pcg_step_matches_oracle_step():
+    """dngd_step with the PCG solver (no GA) against the oracle's dense step."""
+    d = D()
+    p = W.config(1, scale=dict(widths=[5, 32, 32, 1], n_int=240, n_bdy=60))
+    th = W.glorot_theta(p.widths, 1)
+    lam = 1e-4
+    prob = d.Problem.from_workload(p)
+    I = torch.tensor(W.landmarks(p.m, 60, 1))
+    o = d.step_opts(solver=d.PCG, ga=False, landmarks=I.cuda(), pcg_tol=1e-10, pcg_maxit=500)
+    dth, st = prob.step(th, lam, o)
+    ref = S.dense_step(p, th, lam, ga=False)
+    e = rel(dth.cpu().numpy(), ref.dtheta)
+    say("pcg step rel err", e, "iters", st.pcg_iterations)
+    assert st.pcg_converged and e <= 1e-6
+    prob.close()

@@ -1,0 +1,114 @@
+"""Serving loop: the scheduler's admission rules on the CPU with a fake
+executor, and on the GPU that every job's result is the same alone and in
+the mix."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2505_21404_amd import serving as SV
+
+
+def _fake(durations):
+    live = {"n": 0, "max": 0}
+    lock = threading.Lock()
+
+    def run_job(spec, res):
+        with lock:
+            live["n"] += 1
+            live["max"] = max(live["max"], live["n"])
+        for _ in range(spec.steps):
+            t0 = time.perf_counter()
+            time.sleep(durations[spec.job_id])
+            res.step_ms.append((time.perf_counter() - t0) * 1e3)
+        res.theta = np.array([spec.job_id], dtype=float)
+        with lock:
+            live["n"] -= 1
+    return run_job, live
+
+
+def _specs(fps, arrivals, steps=2):
+    return [SV.JobSpec(j, a, problem=None, theta0=None, steps=steps)
+            for j, a in enumerate(arrivals)], {j: f for j, f in enumerate(fps)}
+
+
+def test_scheduler_respects_slots_and_budget():
+    specs, fps = _specs([4, 3, 5, 2, 6, 1], [0.0, 0.0, 0.01, 0.02, 0.02, 0.03])
+    run_job, live = _fake({j: 0.02 for j in fps})
+    srv = SV.Server(budget_bytes=9, max_slots=2, run_job=run_job,
+                    footprint=lambda s: fps[s.job_id])
+    rep = srv.run(specs)
+    assert rep["jobs"] == 6 and not rep["errors"]
+    assert srv.peak_bytes <= 9 and srv.peak_slots <= 2 and live["max"] <= 2
+    for t, kind, j, in_use, active in srv.events:
+        assert in_use <= 9 and active <= 2
+    # first come, first served: admission order = arrival order
+    admits = [j for _, kind, j, _, _ in srv.events if kind == "admit"]
+    assert admits == sorted(admits, key=lambda j: (specs[j].arrival, j))
+    for r in rep["results"].values():
+        assert r.admitted >= r.arrival - 1e-9 and r.finished >= r.admitted
+        assert len(r.step_ms) == 2
+    assert rep["steps"] == 12 and rep["p99_step_ms"] >= rep["p50_step_ms"] > 0
+
+
+def test_scheduler_queues_on_memory_and_overlaps_when_it_fits():
+    # two jobs that together exceed the budget run one after the other ...
+    specs, fps = _specs([6, 6], [0.0, 0.0])
+    run_job, live = _fake({0: 0.05, 1: 0.05})
+    srv = SV.Server(budget_bytes=10, max_slots=4, run_job=run_job,
+                    footprint=lambda s: fps[s.job_id])
+    rep = srv.run(specs)
+    assert live["max"] == 1 and rep["results"][1].admitted >= rep["results"][0].finished - 1e-6
+    # ... and overlap when both fit
+    specs, fps = _specs([5, 5], [0.0, 0.0])
+    run_job, live = _fake({0: 0.05, 1: 0.05})
+    srv = SV.Server(budget_bytes=10, max_slots=4, run_job=run_job,
+                    footprint=lambda s: fps[s.job_id])
+    srv.run(specs)
+    assert live["max"] == 2
+
+
+def test_scheduler_rejects_job_larger_than_budget():
+    specs, fps = _specs([11], [0.0])
+    run_job, _ = _fake({0: 0.0})
+    srv = SV.Server(budget_bytes=10, run_job=run_job, footprint=lambda s: fps[s.job_id])
+    with pytest.raises(ValueError):
+        srv.run(specs)
+
+
+def test_footprint_query_is_host_only():
+    from paper_2505_21404_amd import dngd as D
+    p = W.config(1)
+    b = D.footprint_of(p.pde, p.widths, p.n_int, p.n_bdy, p.n_init)
+    # at least J (FP32, m x ldJ) and K (FP64, m x m)
+    ldJ = -(-p.n_params // 256) * 256
+    assert b >= p.m * ldJ * 4 + p.m * p.m * 8
+    b64 = D.footprint_of(p.pde, p.widths, p.n_int, p.n_bdy, p.n_init,
+                         D.step_opts(precision=D.PLAIN))
+    assert b64 >= p.m * ldJ * 8 + p.m * p.m * 8
+
+
+def small_jobs(n=6, steps=3):
+    """A short job stream like the serving workload, scaled down (m 150-400,
+    width 16-32) so that it runs in seconds."""
+    jobs = W.serving_jobs(n_jobs=n, rate=40.0, steps=steps, m_range=(150, 400),
+                          widths_choice=(16, 32), depth=3)
+    return SV.specs_from_workloads(jobs)
+
+
+@pytest.mark.gpu
+def test_results_identical_alone_and_in_mix():
+    torch = pytest.importorskip("torch")
+    specs = small_jobs()
+    alone = {s.job_id: SV.run_alone(s) for s in specs}
+    free, _ = torch.cuda.mem_get_info()
+    srv = SV.Server(budget_bytes=int(0.5 * free), max_slots=4)
+    rep = srv.run(specs, realtime=True)
+    print("serving", {k: v for k, v in rep.items() if k != "results"}, flush=True)
+    assert not rep["errors"], rep["errors"]
+    assert srv.peak_slots >= 2   # the jobs did overlap
+    for s in specs:
+        a, b = alone[s.job_id].theta, rep["results"][s.job_id].theta
+        assert np.array_equal(a, b), (s.job_id, np.abs(a - b).max())
