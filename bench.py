@@ -45,8 +45,14 @@ def parse():
     ap.add_argument("--gram-passes", type=int, default=0)
     ap.add_argument("--ir-sweeps", type=int, default=2)
     ap.add_argument("--only-mixed", action="store_true", help="profiling: mixed steps only")
+    ap.add_argument("--only-plain", action="store_true", help="profiling: plain steps only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling: 3 device copies of 1 GiB (calibrates the HBM byte counters)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream run")
+    ap.add_argument("--serving-jobs", type=int, default=64)
+    ap.add_argument("--serving-steps", type=int, default=10,
+                    help="iterations per serving job (the stream's jobs ask for 200)")
+    ap.add_argument("--serving-slots", type=int, default=4)
     return ap.parse_args()
 
 
@@ -124,6 +130,32 @@ def cpu_baseline(seed_theta, lam, frac=5):
                       f"to m=5000: {est:.1f} s/step"}
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gram_bf16_kernel_poisson5d_m5000.traffic.txt")
+
+
+def serving_run(n_jobs, steps, slots, torch):
+    """The serving stream (Poisson arrivals at 4 jobs/s, uneven m and widths)
+    with ``steps`` iterations per job, admitted by footprint into 80% of the
+    free device memory."""
+    import workloads as W
+    from paper_2505_21404_amd import serving as SV
+    specs = SV.specs_from_workloads(W.serving_jobs(n_jobs=n_jobs, rate=4.0, steps=steps))
+    free, _ = torch.cuda.mem_get_info()
+    srv = SV.Server(budget_bytes=int(0.8 * free), max_slots=slots)
+    rep = srv.run(specs, realtime=True)
+    out = {k: v for k, v in rep.items() if k not in ("results", "errors")}
+    out["errors"] = len(rep["errors"])
+    out["jobs_requested"] = n_jobs
+    out["steps_per_job"] = steps
+    out["slots"] = slots
+    out["budget_bytes"] = srv.budget
+    return out
+
+
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -146,9 +178,15 @@ def main():
     L0 = 0.5 * float((r0 * r0).sum())
     lam = min(L0, W.LAMBDA_CAP[1])
 
+    if a.only_plain:
+        plain = D.step_opts(precision=D.PLAIN, ga=True)
+        tot, _, _, _ = timed_steps(prob, th, lam, plain, a.steps, a.warmup, torch)
+        print(json.dumps({"steps": a.steps, "ms_per_step": tot * 1e3 / a.steps}))
+        return 0
     mixed = D.step_opts(precision=D.MIXED, ga=True, ir_sweeps=a.ir_sweeps,
                         gram_passes=a.gram_passes)
     tot, walls, stats, dth_mixed = timed_steps(prob, th, lam, mixed, a.steps, a.warmup, torch)
+    progress(f"mixed steps done: {tot * 1e3 / a.steps:.2f} ms/step")
     if a.only_mixed:
         print(json.dumps({"steps": a.steps, "ms_per_step": tot * 1e3 / a.steps}))
         return 0
@@ -184,6 +222,11 @@ def main():
                      "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
                      "flops_per_launch": gram_flops, "avg_launch_ms": gk_avg},
     }
+    from paper_2505_21404_amd.profiling import read_traffic
+    tr = read_traffic(TRAFFIC_RECORD, ROOT)
+    if tr is not None and int(tr.get("gram_passes", "-1")) == stats[-1]["gram_passes_used"]:
+        out["roofline"]["traffic"] = float(tr["traffic_bytes_per_dispatch"])
+        out["roofline"]["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
     if not a.no_plain:
         plain = D.step_opts(precision=D.PLAIN, ga=True)
@@ -198,6 +241,7 @@ def main():
                             "ms_residual_jacobian", "ms_gram", "ms_factor", "ms_solve_v",
                             "ms_fvv", "ms_solve_a")}}
         out["speedup_mixed_vs_plain"] = out["value"] / out["plain"]["steps_per_s"]
+        progress("plain steps done")
         dm, dp = dth_mixed.cpu().numpy(), dth_plain.cpu().numpy()
         out["mixed_vs_plain_rel_err"] = float(np.linalg.norm(dm - dp) / np.linalg.norm(dp))
 
@@ -224,7 +268,13 @@ def main():
                 out["plain_vs_oracle_rel_err"] = float(np.linalg.norm(dp - ref)
                                                        / np.linalg.norm(ref))
 
+    if not a.no_serving:
+        progress("serving stream ...")
+        out["serving"] = serving_run(a.serving_jobs, a.serving_steps, a.serving_slots, torch)
+        progress("serving done")
+
     if not a.no_cpu:
+        progress("CPU oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(th0, lam)
     print(json.dumps(out), flush=True)
     prob.close()

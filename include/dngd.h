@@ -87,10 +87,13 @@ typedef struct {
   int32_t ga;           /* 1: geodesic acceleration (Section 3.2), 0: off */
   int32_t ir_sweeps;    /* mixed dense: iterative-refinement sweeps per solve (default 2) */
   int32_t gram_passes;  /* mixed: 1 (bf16 x bf16), 3 (split J ~ hi + lo, hi hi^T + hi lo^T
-                           + lo hi^T), 4 (also lo lo^T: positive semidefinite), 0 = pick
-                           from D = max_i ||J_i||^2 and lambda (default 0): 1 if
-                           2^-8 sqrt(D / lambda) <= 0.02, else 3 if 2^-16 D <= lambda / 10,
-                           else 4. A failed mixed factorisation is retried once with 4. */
+                           + lo hi^T), 4 (also lo lo^T: positive semidefinite),
+                           DNGD_GRAM_F64 (J widened to FP64, FP64 products and sums),
+                           0 = auto (default): start from D = max_i ||J_i||^2 and lambda
+                           with 1 if 2^-8 sqrt(D / lambda) <= 0.02, else 3 if
+                           2^-16 D <= lambda / 10, else 4; then escalate (3 -> 4 ->
+                           DNGD_GRAM_F64, 1 -> 4) when the factorisation fails or the
+                           refinement residual of the v solve stays above ir_tol. */
   int32_t reserved0;
   double eps_norm;      /* GA guard: GA only if ||v|| > eps_norm (default 0) */
   /* PCG (solver == DNGD_PCG) */
@@ -98,7 +101,12 @@ typedef struct {
   const int64_t* landmarks; /* device, l sorted distinct residual indices in [0, m) */
   double pcg_tol;           /* stop at ||b - A y|| <= tol ||b|| (recursive residual) */
   int64_t pcg_maxit;
+  double ir_tol;            /* mixed, auto Gram: escalate when ||s|| / ||r|| before the last
+                               refinement sweep of the v solve exceeds this (default 1e-5) */
 } dngd_step_opts;
+
+/* gram_passes / dngd_gram passes value: FP64-product Gram of an FP32 J */
+#define DNGD_GRAM_F64 64
 
 typedef struct {
   double ms_total, ms_residual_jacobian, ms_gram, ms_factor, ms_solve_v, ms_fvv, ms_solve_a;
@@ -111,6 +119,8 @@ typedef struct {
   double max_row_norm2;       /* max_i ||J_i||^2 (mixed path) */
   double pcg_rel_residual;    /* PCG: final recursive ||r|| / ||b|| */
   double ms_gram_kernel;      /* the Gram contraction kernel alone (HIP events on `stream`) */
+  int32_t gram_attempts;      /* Gram + factorisation attempts (> 1 after an escalation) */
+  int32_t reserved1;
 } dngd_step_stats;
 
 const char* dngd_last_error(void);
@@ -150,7 +160,8 @@ int dngd_residual_jacobian(dngd_problem* h, const double* theta, double* r, void
  * J: device, m x ldJ row-major, j_dtype DNGD_F64 (FP64 MFMA) or DNGD_F32
  * (BF16 MFMA with FP32 accumulation; passes = 1 rounds J to bf16, passes = 3
  * uses the split J ~ hi + lo and adds hi hi^T + hi lo^T + lo hi^T, passes = 4
- * adds lo lo^T as well).
+ * adds lo lo^T as well; passes = DNGD_GRAM_F64 widens J to FP64 and uses the
+ * FP64 MFMA path).
  * Split-K partial sums are added in FP64 in a fixed order, so the result is
  * deterministic. K: device, m x ldK FP64, lower triangle (i >= j) written,
  * strict upper triangle untouched. ldK >= m. */

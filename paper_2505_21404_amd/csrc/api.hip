@@ -481,6 +481,7 @@ void dngd_step_opts_default(dngd_step_opts* o) {
   o->eps_norm = 0.0;
   o->pcg_tol = 1e-6;
   o->pcg_maxit = 500;
+  o->ir_tol = 1e-5;
 }
 
 int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
@@ -584,8 +585,9 @@ int dngd_gram(int64_t m, int64_t n, const void* J, int64_t ldJ, int32_t j_dtype,
   DNGD_REQUIRE(J && K, "dngd_gram: null pointer");
   DNGD_REQUIRE(m > 0 && n > 0 && ldJ >= n && ldK >= m, "dngd_gram: bad sizes");
   DNGD_REQUIRE(j_dtype == DNGD_F64 || j_dtype == DNGD_F32, "dngd_gram: bad j_dtype");
-  DNGD_REQUIRE(j_dtype == DNGD_F64 || passes == 1 || passes == 3 || passes == 4,
-               "dngd_gram: passes 1, 3 or 4");
+  DNGD_REQUIRE(j_dtype == DNGD_F64 || passes == 1 || passes == 3 || passes == 4 ||
+                   passes == DNGD_GRAM_F64,
+               "dngd_gram: passes 1, 3, 4 or DNGD_GRAM_F64");
   DNGD_REQUIRE(std::isfinite(lambda), "dngd_gram: lambda not finite");
   DNGD_REQUIRE(j_dtype == DNGD_F64 || ldJ % 4 == 0, "dngd_gram: FP32 J needs ldJ %% 4 == 0");
   hipStream_t s = S(stream);
@@ -932,7 +934,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   DNGD_REQUIRE(o.solver == DNGD_DENSE || o.solver == DNGD_PCG, "bad solver");
   DNGD_REQUIRE(o.ir_sweeps >= 0 && o.ir_sweeps <= 8, "ir_sweeps must be in [0, 8]");
   DNGD_REQUIRE(o.gram_passes == 0 || o.gram_passes == 1 || o.gram_passes == 3 ||
-                   o.gram_passes == 4,
+                   o.gram_passes == 4 || o.gram_passes == DNGD_GRAM_F64,
                "bad gram_passes");
   const Geometry& g = h->g;
   hipStream_t s = S(stream);
@@ -1029,8 +1031,12 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   }
   rc = ensure(h, h->solve_aux, chol_solve_aux_bytes(g.m));
   if (rc) return rc;
+  const int ir = (jd == DNGD_F32) ? o.ir_sweeps : 0;
+  const bool adaptive = (jd == DNGD_F32 && o.gram_passes == 0);
   int64_t info = 0;
-  for (int attempt = 0;; ++attempt) {
+  int attempts = 0;
+  for (;;) {
+    ++attempts;
     const size_t gw = gram_workspace_bytes(g.m, g.n, jd, passes, nullptr);
     rc = ensure(h, h->gram_work, gw);
     if (!rc)
@@ -1041,23 +1047,42 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     // Cholesky of K + lam I
     rc = chol_factor(s, g.m, K, g.m, sm.info, nullptr);
     if (rc) return rc;
-    if (jd == DNGD_F64 || passes == 4 || attempt > 0) break;
-    // mixed path: a failed factorisation is retried once with the
-    // positive semidefinite 4-product Gram
-    DNGD_HIP(hipMemcpyAsync(&info, sm.info, 8, hipMemcpyDeviceToHost, s));
-    DNGD_HIP(hipStreamSynchronize(s));
-    if (info == 0) break;
-    passes = 4;
+    const bool can_escalate = adaptive && passes != DNGD_GRAM_F64;
+    if (can_escalate) {
+      DNGD_HIP(hipMemcpyAsync(&info, sm.info, 8, hipMemcpyDeviceToHost, s));
+      DNGD_HIP(hipStreamSynchronize(s));
+      if (info != 0) {  // K~ + lam I not positive definite in this precision
+        passes = (passes == 4) ? DNGD_GRAM_F64 : 4;
+        continue;
+      }
+    }
+    rc = chol_prepare_solve(s, g.m, K, g.m, static_cast<double*>(h->solve_aux.p));
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[3], s));
+
+    // alpha = (K + lam I)^{-1} r (+ refinement), v = -J^T alpha
+    rc = dense_solve(h, v, sm, v.r, v.alpha, lambda, ir, J, jd, v.scal + 16, s);
+    if (rc) return rc;
+    if (can_escalate && ir > 0) {
+      // refinement did not bring the residual below ir_tol: the Gram is too
+      // coarse for this damping
+      double sc2[9];
+      rc = sumsq(s, g.m, v.r, v.scal + 15, v.red);
+      if (rc) return rc;
+      DNGD_HIP(hipMemcpyAsync(sc2, v.scal + 15, sizeof(sc2), hipMemcpyDeviceToHost, s));
+      DNGD_HIP(hipStreamSynchronize(s));
+      const double nr = std::sqrt(sc2[0]);
+      const double last = nr > 0 ? std::sqrt(sc2[1 + std::min(ir, 8) - 1]) / nr : 0.0;
+      if (!(last <= o.ir_tol)) {
+        passes = DNGD_GRAM_F64;
+        continue;
+      }
+    }
+    break;
   }
   st.gram_passes_used = passes;
-  rc = chol_prepare_solve(s, g.m, K, g.m, static_cast<double*>(h->solve_aux.p));
-  if (rc) return rc;
-  DNGD_HIP(hipEventRecord(h->ev[3], s));
-
-  // alpha = (K + lam I)^{-1} r (+ refinement), v = -J^T alpha
-  const int ir = (jd == DNGD_F32) ? o.ir_sweeps : 0;
-  rc = dense_solve(h, v, sm, v.r, v.alpha, lambda, ir, J, jd, v.scal + 16, s);
-  if (!rc) rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.alpha, -1.0, v.v, v.gemv_work);
+  st.gram_attempts = attempts;
+  rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.alpha, -1.0, v.v, v.gemv_work);
   if (rc) return rc;
   DNGD_HIP(hipEventRecord(h->ev[4], s));
 

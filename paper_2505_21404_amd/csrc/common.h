@@ -103,6 +103,10 @@ int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64
 
 // Batched GEMM_FULL: matrix z = (z / n_inner, z % n_inner) starts at
 // A + zo * a_out + zi * a_in (likewise B, C); n_outer * n_inner matrices.
+// Lower-tile split-K partials of A A^T for FP32 A (M x K, K-contiguous),
+// widened to FP64 on load: 128 x 128 tiles, work as in GEMM_PARTIAL_LOWER.
+int gemm_f64_syrk_partial_f32(hipStream_t s, int64_t M, int64_t K, const float* A, int64_t lda,
+                              double* work, int splits);
 int gemm_f64_batched(hipStream_t s, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
                      int64_t K, double alpha, const double* A, int64_t lda, int64_t a_out,
                      int64_t a_in, const double* B, int64_t ldb, int64_t b_out, int64_t b_in,
@@ -114,6 +118,9 @@ int64_t lower_tiles(int64_t M, int tile);
 
 // ---------------------------------------------------------------------------
 // Gram (gram.hip)
+
+// passes value of the FP64-product Gram of an FP32 J (dngd.h: DNGD_GRAM_F64)
+constexpr int kGramF64 = 64;
 
 size_t gram_workspace_bytes(int64_t m, int64_t n, int j_dtype, int passes, int* splits_out);
 // ev_begin/ev_end (optional) are recorded on `s` around the contraction kernel alone

@@ -31,12 +31,13 @@ __device__ inline void tri_decode(int64_t t, int64_t& i, int64_t& j) {
   j = t - ii * (ii + 1) / 2;
 }
 
-// Load a (rows x KS) slab of op(X) (rows along M or N) into registers.
+// Load a (rows x KS) slab of op(X) (rows along M or N) into registers,
+// widened to FP64 (TI = float: FP32 inputs, exact products in FP64).
 // kcontig: X[row*ld + k]; else X[k*ld + row].
-template <int ROWS, bool KCONTIG>
+template <int ROWS, bool KCONTIG, typename TI = double>
 struct SlabLoader {
   static constexpr int PER = ROWS * KS / 256;  // doubles per thread
-  __device__ static inline void load(double (&r)[PER], const double* __restrict__ X, int64_t ld,
+  __device__ static inline void load(double (&r)[PER], const TI* __restrict__ X, int64_t ld,
                                      int64_t row0, int64_t nrows, int64_t k0, int64_t kend) {
     const int t = threadIdx.x;
     if (KCONTIG) {
@@ -47,11 +48,11 @@ struct SlabLoader {
       const int64_t gr = row0 + row;
       const int64_t kb = k0 + part * PER;
       const bool rok = gr < nrows;
-      const double* p = X + (rok ? gr : 0) * ld;
+      const TI* p = X + (rok ? gr : 0) * ld;
 #pragma unroll
       for (int e = 0; e < PER; ++e) {
         const int64_t k = kb + e;
-        r[e] = (rok && k < kend) ? p[k] : 0.0;
+        r[e] = (rok && k < kend) ? (double)p[k] : 0.0;
       }
       (void)PARTS;
     } else {
@@ -61,11 +62,11 @@ struct SlabLoader {
       const int rb = (t % TPK) * PER;
       const int64_t gk = k0 + k;
       const bool kok = gk < kend;
-      const double* p = X + (kok ? gk : 0) * ld;
+      const TI* p = X + (kok ? gk : 0) * ld;
 #pragma unroll
       for (int e = 0; e < PER; ++e) {
         const int64_t gr = row0 + rb + e;
-        r[e] = (kok && gr < nrows) ? p[gr] : 0.0;
+        r[e] = (kok && gr < nrows) ? (double)p[gr] : 0.0;
       }
     }
   }
@@ -91,10 +92,10 @@ struct Batch {
   int64_t a_out = 0, a_in = 0, b_out = 0, b_in = 0, c_out = 0, c_in = 0;  // element strides
 };
 
-template <int BM, int BN, bool AK, bool BKC, int MODE>
+template <int BM, int BN, bool AK, bool BKC, int MODE, typename TI = double>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
-    int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
-    const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
+    int64_t M, int64_t N, int64_t K, double alpha, const TI* __restrict__ A, int64_t lda,
+    const TI* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
     double* __restrict__ work, int64_t k_per_split, int64_t ntiles, Batch bt) {
   if (MODE == kBatched) {
     const int64_t zo = blockIdx.z / bt.inner, zi = blockIdx.z % bt.inner;
@@ -130,8 +131,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  using LA = SlabLoader<BM, AK>;
-  using LB = SlabLoader<BN, BKC>;
+  using LA = SlabLoader<BM, AK, TI>;
+  using LB = SlabLoader<BN, BKC, TI>;
   double ra[LA::PER], rb[LB::PER];
   const int64_t nk = (kend > kbeg) ? (kend - kbeg + KS - 1) / KS : 0;
   if (nk > 0) {
@@ -272,6 +273,18 @@ int gemm_f64_batched(hipStream_t s, bool a_kcontig, bool b_kcontig, int64_t M, i
   DNGD_BATCH_CASE(false, false)
 #undef DNGD_BATCH_CASE
   return -1;
+}
+
+int gemm_f64_syrk_partial_f32(hipStream_t s, int64_t M, int64_t K, const float* A, int64_t lda,
+                              double* work, int splits) {
+  if (M <= 0) return 0;
+  const int64_t ntiles = lower_tiles(M, 128);
+  const int64_t kps = round_up(cdiv(K, splits), KS);
+  hipLaunchKernelGGL((gemm_f64_kernel<128, 128, true, true, GEMM_PARTIAL_LOWER, float>),
+                     dim3((unsigned)ntiles, (unsigned)splits), dim3(256), 0, s, M, M, K, 1.0, A,
+                     lda, A, lda, 0.0, nullptr, 0, work, kps, ntiles, Batch{});
+  DNGD_LAUNCH_CHECK();
+  return 0;
 }
 
 int64_t lower_tiles(int64_t M, int tile) {

@@ -13,7 +13,11 @@
 // ||lo lo^T|| (~2^-16 max_i ||J_i||^2), which matters only when the damping is
 // that small; PASSES == 4 adds lo lo^T, so K = (hi + lo)(hi + lo)^T is
 // positive semidefinite up to the FP32 accumulation error.
-// Plain path (FP64 J): the FP64 MFMA GEMM in split-K partial mode.
+// Plain path (FP64 J): the FP64 MFMA GEMM in split-K partial mode. FP32 J
+// with passes == kGramF64 takes the same FP64 path, widening J on load (the
+// products of FP32 values are exact in FP64): the accurate fallback of the
+// mixed path when bf16 products or FP32 accumulation are too coarse for the
+// damping.
 //
 // Only lower-triangle tiles are launched. Tiles are numbered row-major over
 // the lower triangle and the launch index is remapped so that each XCD
@@ -264,8 +268,7 @@ int choose_splits_bf16(int64_t ntiles, int64_t n) {
 }  // namespace
 
 size_t gram_workspace_bytes(int64_t m, int64_t n, int j_dtype, int passes, int* splits_out) {
-  (void)passes;
-  if (j_dtype == 0) {
+  if (j_dtype == 0 || passes == kGramF64) {
     const int64_t nt = lower_tiles(m, GT);
     const int s = choose_splits_f64(nt, n);
     if (splits_out) *splits_out = s;
@@ -284,11 +287,14 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
   const size_t need = gram_workspace_bytes(m, n, j_dtype, passes, &splits);
   DNGD_REQUIRE(work_bytes >= need, "gram: workspace too small (%zu < %zu)", work_bytes, need);
   if (ev_begin) DNGD_HIP(hipEventRecord(ev_begin, st));
-  if (j_dtype == 0) {
+  if (j_dtype == 0 || passes == kGramF64) {
     const int64_t nt = lower_tiles(m, GT);
-    int rc = gemm_f64(st, GEMM_PARTIAL_LOWER, true, true, m, m, n, 1.0,
-                      static_cast<const double*>(J), ldJ, static_cast<const double*>(J), ldJ, 0.0,
-                      nullptr, 0, static_cast<double*>(work), splits);
+    int rc = (j_dtype == 0)
+                 ? gemm_f64(st, GEMM_PARTIAL_LOWER, true, true, m, m, n, 1.0,
+                            static_cast<const double*>(J), ldJ, static_cast<const double*>(J),
+                            ldJ, 0.0, nullptr, 0, static_cast<double*>(work), splits)
+                 : gemm_f64_syrk_partial_f32(st, m, n, static_cast<const float*>(J), ldJ,
+                                             static_cast<double*>(work), splits);
     if (rc) return rc;
     if (ev_end) DNGD_HIP(hipEventRecord(ev_end, st));
     hipLaunchKernelGGL((gram_reduce_kernel<double, GT>), dim3((unsigned)nt, GT * GT / 1024),
@@ -298,7 +304,8 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
     return 0;
   }
   DNGD_REQUIRE(ldJ % 4 == 0, "gram: FP32 J needs ldJ %% 4 == 0");
-  DNGD_REQUIRE(passes == 1 || passes == 3 || passes == 4, "gram: passes must be 1, 3 or 4");
+  DNGD_REQUIRE(passes == 1 || passes == 3 || passes == 4, "gram: passes must be 1, 3, 4 or %d",
+               kGramF64);
   const int64_t nt = lower_tiles(m, BT);
   const int64_t kps = round_up(cdiv(n, splits), BKE);
   const int64_t per_xcd = cdiv(nt * splits, NXCD);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdngd.so")
 
 OK, ENOCONV, EINVAL, ENOMEM, EHIP, ENOTPD, ENAN, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
+GRAM_F64 = 64   # gram_passes value: FP64-product Gram of an FP32 J
 POISSON, HEAT = 0, 1
 PLAIN, MIXED = 0, 1
 DENSE, PCG = 0, 1
@@ -44,7 +45,7 @@ class StepOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("solver", C.c_int32), ("ga", C.c_int32),
                 ("ir_sweeps", C.c_int32), ("gram_passes", C.c_int32), ("reserved0", C.c_int32),
                 ("eps_norm", C.c_double), ("n_landmarks", C.c_int64), ("landmarks", C.c_void_p),
-                ("pcg_tol", C.c_double), ("pcg_maxit", C.c_int64)]
+                ("pcg_tol", C.c_double), ("pcg_maxit", C.c_int64), ("ir_tol", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -55,7 +56,8 @@ class StepStats(C.Structure):
                 ("gram_passes_used", C.c_int32), ("pcg_iterations", C.c_int32),
                 ("pcg_converged", C.c_int32), ("ir_residual", C.c_double * 8),
                 ("max_row_norm2", C.c_double), ("pcg_rel_residual", C.c_double),
-                ("ms_gram_kernel", C.c_double)]
+                ("ms_gram_kernel", C.c_double), ("gram_attempts", C.c_int32),
+                ("reserved1", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ir_residual"}
@@ -147,7 +149,8 @@ def version() -> str:
 
 
 def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0, eps_norm=0.0,
-              landmarks: Optional[torch.Tensor] = None, pcg_tol=1e-6, pcg_maxit=500) -> StepOpts:
+              landmarks: Optional[torch.Tensor] = None, pcg_tol=1e-6, pcg_maxit=500,
+              ir_tol: Optional[float] = None) -> StepOpts:
     o = StepOpts()
     _lib.dngd_step_opts_default(C.byref(o))
     o.precision, o.solver, o.ga = precision, solver, int(bool(ga))
@@ -157,6 +160,8 @@ def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0
         o.landmarks = landmarks.data_ptr()
         o._landmarks_ref = landmarks   # the options hold a device pointer into it
     o.pcg_tol, o.pcg_maxit = pcg_tol, pcg_maxit
+    if ir_tol is not None:
+        o.ir_tol = ir_tol
     return o
 
 

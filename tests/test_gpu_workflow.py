@@ -187,3 +187,48 @@ def test_pcg_step_matches_oracle_step():
     say("pcg step rel err", e, "iters", st.pcg_iterations)
     assert st.pcg_converged and e <= 1e-6
     prob.close()
+
+
+# --------------------------------------------------------------------------
+# mixed precision on a stiff serving job: the adaptive Gram
+
+def test_mixed_step_escalates_on_stiff_job():
+    """A 2-D Poisson job of the serving stream (width 128, m = 1100,
+    lambda = 1e-5) whose bf16 Gram is too coarse after the first update: the
+    mixed step must escalate (4 products, then FP64 products) and still
+    match the oracle's step to the mixed tolerance at every iterate."""
+    from paper_2505_21404_amd import serving as SV
+    d = D()
+    spec = SV.specs_from_workloads(W.serving_jobs(n_jobs=37, rate=4.0, steps=3))[36]
+    p = spec.problem
+    assert p.pde == 0 and p.widths[1] == 128 and p.m == 1100
+    prob = d.Problem.from_workload(p)
+    theta = torch.tensor(spec.theta0, device="cuda")
+    dbuf = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    for k in range(3):
+        th_k = theta.cpu().numpy().copy()
+        st = prob.iterate(theta, SV.ETA_GRID, lam_cap=spec.lam_cap,
+                          opts=d.step_opts(precision=d.MIXED, ga=True), dtheta_out=dbuf)
+        ref = S.dense_step(p, th_k, st.lam, ga=True)
+        e = rel(dbuf.cpu().numpy(), ref.dtheta)
+        say(f"iter {k} lam {st.lam:.3g} passes {st.step.gram_passes_used} attempts "
+            f"{st.step.gram_attempts} ir {list(st.step.ir_residual)[:2]} rel err {e:.3e}")
+        assert e <= 1e-4
+    prob.close()
+
+
+def test_gram_f64_products_of_fp32_jacobian():
+    """dngd_gram with FP32 J and passes = DNGD_GRAM_F64: the exact Gram of the
+    FP32 values up to FP64 rounding."""
+    d = D()
+    rng = np.random.default_rng(4)
+    m, n = 300, 7001
+    J = (rng.standard_normal((m, n)) * rng.uniform(0.1, 3.0, size=(m, 1))).astype(np.float32)
+    ld = (n + 3) // 4 * 4
+    Jp = np.zeros((m, ld), dtype=np.float32)
+    Jp[:, :n] = J
+    K = d.gram(torch.tensor(Jp, device="cuda"), n, 0.5, passes=d.GRAM_F64).cpu().numpy()
+    J64 = J.astype(np.float64)
+    ref = J64 @ J64.T + 0.5 * np.eye(m)
+    low = np.tril_indices(m)
+    assert np.abs(K[low] - ref[low]).max() <= 1e-13 * np.abs(ref).max()
