@@ -277,6 +277,64 @@ def jacobian(problem, theta, chunk=512):
     return np.concatenate(rows, axis=0)
 
 
+def _class_of(problem, idx):
+    """(class, point) for residual indices idx (order interior, boundary, initial)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    b0, b1 = problem.n_int, problem.n_int + problem.n_bdy
+    cls = np.where(idx < b0, 0, np.where(idx < b1, 1, 2))
+    pt = np.where(cls == 0, idx, np.where(cls == 1, idx - b0, idx - b1))
+    return cls, pt
+
+
+def _class_points(problem, c):
+    return (problem.x_int, problem.x_bdy, problem.x_init)[c]
+
+
+def residual_rows(problem, theta, idx):
+    """Entries idx of r(theta), each computed from its own point only (a
+    residual depends on one collocation point)."""
+    ci, cb, c0 = class_scales(problem)
+    nl = nlap_of(problem)
+    cls, pt = _class_of(problem, idx)
+    out = np.empty(len(cls), dtype=np.result_type(theta, np.float64))
+    for c, scale in ((0, ci), (1, cb), (2, c0)):
+        sel = np.nonzero(cls == c)[0]
+        if not len(sel):
+            continue
+        u = forward(theta, problem.widths, _class_points(problem, c)[pt[sel]], nl)
+        if c == 0:
+            out[sel] = scale * (interior_operator(problem, u) - problem.f_int[pt[sel]])
+        else:
+            tgt = problem.g_bdy if c == 1 else problem.g_init
+            out[sel] = scale * (u.v[:, 0] - tgt[pt[sel]])
+    return out
+
+
+def jacobian_rows(problem, theta, idx):
+    """Rows idx of J, each from its own point (seeds as in ``jacobian``)."""
+    ci, cb, c0 = class_scales(problem)
+    nl = nlap_of(problem)
+    d = problem.d_in
+    cls, pt = _class_of(problem, idx)
+    out = np.empty((len(cls), n_params(problem.widths)))
+    for c, scale in ((0, ci), (1, cb), (2, c0)):
+        sel = np.nonzero(cls == c)[0]
+        if not len(sel):
+            continue
+        N = len(sel)
+        sv, sg, sl = np.zeros(N), np.zeros((N, d)), np.zeros(N)
+        if c == 0 and problem.pde == POISSON:
+            sl[:] = -scale
+        elif c == 0:
+            sg[:, d - 1] = scale
+            sl[:] = -scale * problem.kappa
+        else:
+            sv[:] = scale
+        out[sel] = _jacobian_class(theta, problem.widths, _class_points(problem, c)[pt[sel]], nl,
+                                   sv, sg, sl)
+    return out
+
+
 # ----------------------------------------------------------------------------
 # f_vv = d^2/dt^2 r(theta + t v) at t = 0 (Section 3.2, geodesic acceleration)
 
@@ -330,3 +388,18 @@ def fvv(problem, theta, v):
             u2 = fvv_output(theta, v, problem.widths, x, nl)
             parts.append(c * u2.v[:, 0])
     return np.concatenate(parts)
+
+
+def fvv_rows(problem, theta, v, idx):
+    """Entries idx of f_vv, each from its own point."""
+    ci, cb, c0 = class_scales(problem)
+    nl = nlap_of(problem)
+    cls, pt = _class_of(problem, idx)
+    out = np.empty(len(cls))
+    for c, scale in ((0, ci), (1, cb), (2, c0)):
+        sel = np.nonzero(cls == c)[0]
+        if not len(sel):
+            continue
+        u2 = fvv_output(theta, v, problem.widths, _class_points(problem, c)[pt[sel]], nl)
+        out[sel] = scale * (interior_operator(problem, u2) if c == 0 else u2.v[:, 0])
+    return out

@@ -1083,12 +1083,14 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   st.gram_passes_used = passes;
   st.gram_attempts = attempts;
   rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.alpha, -1.0, v.v, v.gemv_work);
+  if (!rc && o.alpha_out) rc = copy(s, g.m, v.alpha, o.alpha_out);
   if (rc) return rc;
   DNGD_HIP(hipEventRecord(h->ev[4], s));
 
   if (o.ga) {
     // f_vv along v (Section 3.2), beta = (K + lam I)^{-1} f_vv, a = -J^T beta
     rc = tangent(h, theta, v.v, 2, v.fvv, s);
+    if (!rc && o.fvv_out) rc = copy(s, g.m, v.fvv, o.fvv_out);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[5], s));
     rc = dense_solve(h, v, sm, v.fvv, v.beta, lambda, ir, J, jd, nullptr, s);

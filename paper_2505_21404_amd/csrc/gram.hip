@@ -28,7 +28,8 @@
 // gram_reduce, which also adds lambda on the diagonal: deterministic. The
 // FP32 accumulation error of a partial grows with the number of terms it
 // holds while the FP64 sum of S partials does not, so the bf16 path uses
-// many short splits (~4096 terms each).
+// many short splits (~4096 terms each), run in batches of at most 64 splits
+// whose sums are added into K in order.
 #include "common.h"
 
 namespace dngd {
@@ -88,7 +89,8 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
                                                         const float* __restrict__ J, int64_t ldJ,
                                                         float* __restrict__ work,
                                                         int64_t k_per_split, int64_t ntiles,
-                                                        int64_t per_xcd, int splits) {
+                                                        int64_t per_xcd, int splits,
+                                                        int64_t split0) {
   constexpr bool LO = (PASSES >= 3);
   constexpr bool LOLO = (PASSES == 4);
   __shared__ float4 sA0[BT * ROWCH];
@@ -100,7 +102,8 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
   const int64_t lin = blockIdx.x;
   const int64_t slt = (lin % NXCD) * per_xcd + lin / NXCD;
   if (slt >= ntiles * (int64_t)splits) return;  // padding slots
-  const int64_t split = slt / ntiles;
+  const int64_t lsplit = slt / ntiles;           // split within this launch
+  const int64_t split = split0 + lsplit;         // split of the whole K range
   const int64_t logical = slt % ntiles;
   int64_t ti, tj;
   tri_decode_g(logical, ti, tj);
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
   }
 
   // accumulator v of tile (i, j): row 8 (v/4) + 4 (lane/32) + v%4, col lane%32
-  float* out = work + ((int64_t)split * ntiles + logical) * (BT * BT);
+  float* out = work + (lsplit * ntiles + logical) * (BT * BT);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -226,11 +229,13 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
       }
 }
 
+// K (lower triangle) = [K +] sum of the partial tiles in split order [+ lambda I]:
+// the first batch of splits writes K and adds lambda, later batches accumulate.
 template <typename P, int T>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t m, const P* __restrict__ work,
                                                           int splits, int64_t ntiles,
                                                           double lambda, double* __restrict__ K,
-                                                          int64_t ldK) {
+                                                          int64_t ldK, int accumulate) {
   int64_t ti, tj;
   tri_decode_g(blockIdx.x, ti, tj);
   const int base = (blockIdx.y * 256 + threadIdx.x) * 4;  // 4 consecutive elements
@@ -246,7 +251,10 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t m, const P* __
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int64_t col = tj * T + cl0 + e;
-    if (col < m && col <= row) K[row * ldK + col] = s[e] + (row == col ? lambda : 0.0);
+    if (col < m && col <= row) {
+      double* k = K + row * ldK + col;
+      *k = accumulate ? *k + s[e] : s[e] + (row == col ? lambda : 0.0);
+    }
   }
 }
 
@@ -258,11 +266,13 @@ int choose_splits_f64(int64_t ntiles, int64_t n) {
 }
 
 // bf16 path: <= ~4096 terms per split (accuracy) and enough workgroups to
-// fill the chip, at most 64 splits.
-int choose_splits_bf16(int64_t ntiles, int64_t n) {
-  int64_t s = std::max<int64_t>(cdiv(n, 4096), cdiv(3072, ntiles));
+// fill the chip. At most kSplitBatch splits are in flight (the workspace);
+// more are run in batches whose partials are added into K in order.
+constexpr int kSplitBatch = 64;
+int64_t choose_splits_bf16(int64_t ntiles, int64_t n) {
+  int64_t s = std::max<int64_t>(cdiv(n, 4096), std::min<int64_t>(cdiv(3072, ntiles), kSplitBatch));
   s = std::min<int64_t>(s, std::max<int64_t>(1, cdiv(n, BKE)));
-  return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+  return std::max<int64_t>(1, s);
 }
 
 }  // namespace
@@ -275,9 +285,9 @@ size_t gram_workspace_bytes(int64_t m, int64_t n, int j_dtype, int passes, int* 
     return (size_t)s * (size_t)nt * GT * GT * sizeof(double);
   }
   const int64_t nt = lower_tiles(m, BT);
-  const int s = choose_splits_bf16(nt, n);
-  if (splits_out) *splits_out = s;
-  return (size_t)s * (size_t)nt * BT * BT * sizeof(float);
+  const int64_t s = choose_splits_bf16(nt, n);
+  if (splits_out) *splits_out = (int)s;
+  return (size_t)std::min<int64_t>(s, kSplitBatch) * (size_t)nt * BT * BT * sizeof(float);
 }
 
 int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
@@ -299,7 +309,7 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
     if (ev_end) DNGD_HIP(hipEventRecord(ev_end, st));
     hipLaunchKernelGGL((gram_reduce_kernel<double, GT>), dim3((unsigned)nt, GT * GT / 1024),
                        dim3(256), 0, st, m, static_cast<const double*>(work), splits, nt, lambda,
-                       K, ldK);
+                       K, ldK, 0);
     DNGD_LAUNCH_CHECK();
     return 0;
   }
@@ -308,27 +318,29 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
                kGramF64);
   const int64_t nt = lower_tiles(m, BT);
   const int64_t kps = round_up(cdiv(n, splits), BKE);
-  const int64_t per_xcd = cdiv(nt * splits, NXCD);
-  // one workgroup per (split, tile); the kernel derives both from blockIdx.x
-  const dim3 grid((unsigned)(per_xcd * NXCD));
-  if (passes == 4)
-    hipLaunchKernelGGL(gram_bf16_kernel<4>, grid, dim3(512), 0, st, m, n,
-                       static_cast<const float*>(J), ldJ, static_cast<float*>(work), kps, nt,
-                       per_xcd, splits);
-  else if (passes == 3)
-    hipLaunchKernelGGL(gram_bf16_kernel<3>, grid, dim3(512), 0, st, m, n,
-                       static_cast<const float*>(J), ldJ, static_cast<float*>(work), kps, nt,
-                       per_xcd, splits);
-  else
-    hipLaunchKernelGGL(gram_bf16_kernel<1>, grid, dim3(512), 0, st, m, n,
-                       static_cast<const float*>(J), ldJ, static_cast<float*>(work), kps, nt,
-                       per_xcd, splits);
-  DNGD_LAUNCH_CHECK();
-  if (ev_end) DNGD_HIP(hipEventRecord(ev_end, st));
-  hipLaunchKernelGGL((gram_reduce_kernel<float, BT>), dim3((unsigned)nt, BT * BT / 1024),
-                     dim3(256), 0, st, m, static_cast<const float*>(work), splits, nt, lambda, K,
-                     ldK);
-  DNGD_LAUNCH_CHECK();
+  for (int64_t s0 = 0; s0 < splits; s0 += kSplitBatch) {
+    const int sb = (int)std::min<int64_t>(kSplitBatch, splits - s0);
+    const int64_t per_xcd = cdiv(nt * sb, NXCD);
+    // one workgroup per (split, tile); the kernel derives both from blockIdx.x
+    const dim3 grid((unsigned)(per_xcd * NXCD));
+    float* w = static_cast<float*>(work);
+    const float* Jf = static_cast<const float*>(J);
+    if (passes == 4)
+      hipLaunchKernelGGL(gram_bf16_kernel<4>, grid, dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt,
+                         per_xcd, sb, s0);
+    else if (passes == 3)
+      hipLaunchKernelGGL(gram_bf16_kernel<3>, grid, dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt,
+                         per_xcd, sb, s0);
+    else
+      hipLaunchKernelGGL(gram_bf16_kernel<1>, grid, dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt,
+                         per_xcd, sb, s0);
+    DNGD_LAUNCH_CHECK();
+    if (ev_end && s0 + sb >= splits) DNGD_HIP(hipEventRecord(ev_end, st));
+    hipLaunchKernelGGL((gram_reduce_kernel<float, BT>), dim3((unsigned)nt, BT * BT / 1024),
+                       dim3(256), 0, st, m, static_cast<const float*>(work), sb, nt, lambda, K,
+                       ldK, s0 > 0 ? 1 : 0);
+    DNGD_LAUNCH_CHECK();
+  }
   return 0;
 }
 

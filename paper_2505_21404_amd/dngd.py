@@ -45,7 +45,8 @@ class StepOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("solver", C.c_int32), ("ga", C.c_int32),
                 ("ir_sweeps", C.c_int32), ("gram_passes", C.c_int32), ("reserved0", C.c_int32),
                 ("eps_norm", C.c_double), ("n_landmarks", C.c_int64), ("landmarks", C.c_void_p),
-                ("pcg_tol", C.c_double), ("pcg_maxit", C.c_int64), ("ir_tol", C.c_double)]
+                ("pcg_tol", C.c_double), ("pcg_maxit", C.c_int64), ("ir_tol", C.c_double),
+                ("alpha_out", C.c_void_p), ("fvv_out", C.c_void_p)]
 
 
 class StepStats(C.Structure):
@@ -150,7 +151,8 @@ def version() -> str:
 
 def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0, eps_norm=0.0,
               landmarks: Optional[torch.Tensor] = None, pcg_tol=1e-6, pcg_maxit=500,
-              ir_tol: Optional[float] = None) -> StepOpts:
+              ir_tol: Optional[float] = None, alpha_out: Optional[torch.Tensor] = None,
+              fvv_out: Optional[torch.Tensor] = None) -> StepOpts:
     o = StepOpts()
     _lib.dngd_step_opts_default(C.byref(o))
     o.precision, o.solver, o.ga = precision, solver, int(bool(ga))
@@ -162,6 +164,11 @@ def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0
     o.pcg_tol, o.pcg_maxit = pcg_tol, pcg_maxit
     if ir_tol is not None:
         o.ir_tol = ir_tol
+    for name, t in (("alpha_out", alpha_out), ("fvv_out", fvv_out)):
+        if t is not None:
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.is_cuda
+            setattr(o, name, t.data_ptr())
+            setattr(o, "_" + name + "_ref", t)
     return o
 
 

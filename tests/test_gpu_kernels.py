@@ -105,7 +105,7 @@ def test_gram_f64(m, n):
 
 
 @pytest.mark.parametrize("passes", [1, 3, 4])
-@pytest.mark.parametrize("m,n", [(70, 333), (300, 5003), (700, 20000)])
+@pytest.mark.parametrize("m,n", [(70, 333), (300, 5003), (700, 20000), (300, 300001)])
 def test_gram_bf16(m, n, passes):
     say("case gram_bf16", m, n, passes)
     rng = np.random.default_rng(m + n + passes)

@@ -282,3 +282,19 @@ def test_fvv_invariants():
     nlast = p.widths[-2] * 1 + 1
     vo[-nlast:] = v[-nlast:]
     assert np.abs(N.fvv(p, th, vo)).max() <= 1e-14
+
+
+@pytest.mark.parametrize("kind", ["poisson", "heat"])
+def test_row_subsets_match_full_oracle(kind):
+    """residual_rows / jacobian_rows / fvv_rows (point by point, used at sizes
+    where the full arrays do not fit) equal the rows of the full results."""
+    if kind == "poisson":
+        p = W.config(0, scale=dict(widths=[2, 9, 7, 1], n_int=30, n_bdy=12))
+    else:
+        p = W.heat_problem([3, 8, 6, 1], 25, 9, 7, 0.3, 4)
+    th = 0.6 * np.random.default_rng(1).standard_normal(N.n_params(p.widths))
+    v = np.random.default_rng(2).standard_normal(N.n_params(p.widths))
+    idx = np.array([p.m - 1, 0, 3, p.n_int, p.n_int + 1, p.m - 2, 5])
+    assert np.array_equal(N.residual_rows(p, th, idx), N.residual(p, th)[idx])
+    assert np.allclose(N.jacobian_rows(p, th, idx), N.jacobian(p, th)[idx], rtol=0, atol=1e-14)
+    assert np.allclose(N.fvv_rows(p, th, v, idx), N.fvv(p, th, v)[idx], rtol=1e-13, atol=1e-14)
