@@ -4,9 +4,10 @@
 // Factorisation: right-looking, block width 64.
 //   panel kernel  one 256-thread workgroup per 64 rows of the current block
 //                 column. Every workgroup factors the 64 x 64 diagonal block
-//                 in LDS (left-looking by columns, 4 lanes per row sharing each
-//                 dot product), workgroup 0 writes L11 and the reciprocal
-//                 pivots, the others solve their rows of L21 = A21 L11^-T.
+//                 in LDS (8-column groups: a parallel update, then an 8-step
+//                 substitution inside one wave), workgroup 0 writes L11 and
+//                 the reciprocal pivots, the others solve their rows of
+//                 L21 = A21 L11^-T the same way.
 //   update        A22 -= L21 L21^T on the FP64 matrix cores (lower tiles).
 // A non-positive or non-finite pivot records its 1-based column in *info
 // (first failure wins) and poisons the rest of the factor with NaN.
@@ -22,21 +23,42 @@ namespace {
 
 constexpr int NB = 64;
 
-// 256 threads: row i of the 64-row block is owned by the 4 lanes 4i..4i+3 of
-// one wave, each summing every 4th term of a dot product; two xor-shuffles
-// complete the sum in all 4 lanes.
-__device__ inline double dot4(const double* a, const double* b, int len, int sub) {
-  double s0 = 0.0, s1 = 0.0;
-  int k = sub;
-  for (; k + 4 < len; k += 8) {
-    s0 += a[k] * b[k];
-    s1 += a[k + 4] * b[k + 4];
+// Grouped right-to-left elimination of one 64-wide panel, 8 columns at a
+// time. For group g (columns c0 .. c0+7):
+//   update  the group's columns of every row with the finished columns
+//           k < c0 (one dot product per entry, all 256 threads), then
+//   finish  the 8 columns by substitution inside wave 0 (lane i = row i,
+//           8 dependent steps with no workgroup barrier; LDS accesses of one
+//           wave complete in order).
+// Two barriers per group instead of two per column.
+constexpr int GW = 8;  // columns per group
+
+// S[i][j] -= sum_{k < c0} S[i][k] * Lr[j][k] for rows i in [r_lo, 64), j in the
+// group (j <= i when lower). Entries are spread over the 256 threads.
+__device__ inline void group_update(double (*S)[NB + 1], const double (*Lr)[NB + 1], int c0,
+                                    int r_lo, bool lower) {
+  const int t = threadIdx.x;
+  const int cnt = (NB - r_lo) * GW;
+  for (int e = t; e < cnt; e += 256) {
+    const int i = r_lo + e / GW, j = c0 + e % GW;
+    if (lower && j > i) continue;
+    double s0 = 0.0, s1 = 0.0;
+    int k = 0;
+    for (; k + 1 < c0; k += 2) {
+      s0 += S[i][k] * Lr[j][k];
+      s1 += S[i][k + 1] * Lr[j][k + 1];
+    }
+    if (k < c0) s0 += S[i][k] * Lr[j][k];
+    S[i][j] -= s0 + s1;
   }
-  if (k < len) s0 += a[k] * b[k];
-  double s = s0 + s1;
-  s += __shfl_xor(s, 1);
-  s += __shfl_xor(s, 2);
-  return s;
+}
+
+// Value of v held by lane `lane` (uniform), broadcast to the wave.
+__device__ inline double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __restrict__ K,
@@ -48,10 +70,11 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
   __shared__ double Ld[NB][NB + 1];
   __shared__ double X[NB][NB + 1];
   __shared__ double rinv[NB];
-  __shared__ double sdiag;
+  __shared__ int sbad;
   const int t = threadIdx.x;
-  const int row = t >> 2, sub = t & 3;
+  const int lane = t & 63, wave = t >> 6;
   const int nb = (int)min<int64_t>(NB, m - j0);
+  if (t == 0) sbad = -1;
 
   // ---- load the diagonal block, coalesced (identity padding beyond m)
   {
@@ -68,29 +91,40 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
     }
   }
   __syncthreads();
-  // ---- left-looking factorisation by columns:
-  //      s_i = A_ij - sum_{k<j} L_ik L_jk ;  L_jj = sqrt(s_j) ;  L_ij = s_i / L_jj
-  int bad = -1;
-  for (int j = 0; j < NB; ++j) {
-    const double sij = Ld[row][j] - dot4(&Ld[row][0], &Ld[j][0], j, sub);
-    if (row == j && sub == 0) sdiag = sij;
+  // ---- factor the diagonal block:  L_jj = sqrt(a_jj - sum_k L_jk^2),
+  //      L_ij = (a_ij - sum_k L_ik L_jk) / L_jj
+  for (int c0 = 0; c0 < NB; c0 += GW) {
+    group_update(Ld, Ld, c0, c0, true);
     __syncthreads();
-    const double d = sdiag;
-    double ljj;
-    if (d > 0.0 && __builtin_isfinite(d)) {
-      ljj = sqrt(d);
-    } else {
-      if (bad < 0) bad = j;
-      ljj = __builtin_nan("");
-    }
-    const double inv = 1.0 / ljj;
-    if (sub == 0) {
-      if (row == j) {
-        Ld[j][j] = ljj;
-        rinv[j] = inv;
-      } else if (row > j) {
-        Ld[row][j] = sij * inv;
+    if (wave == 0) {
+      // lane i holds row i of the group in registers; row c0 + j of L (the
+      // multipliers of step j) is read from lane c0 + j
+      const int i = lane;
+      double x[GW];
+#pragma unroll
+      for (int j = 0; j < GW; ++j) x[j] = Ld[i][c0 + j];
+#pragma unroll
+      for (int j = 0; j < GW; ++j) {
+        const int pj = c0 + j;
+        double sij = x[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) sij -= x[k] * lane_value(x[k], pj);
+        const double d = lane_value(sij, pj);  // the pivot, uniform
+        double ljj;
+        if (d > 0.0 && __builtin_isfinite(d)) {
+          ljj = sqrt(d);
+        } else {
+          if (i == 0 && sbad < 0) sbad = pj;
+          ljj = __builtin_nan("");
+        }
+        const double inv = 1.0 / ljj;
+        if (i == pj) x[j] = ljj;
+        else if (i > pj) x[j] = sij * inv;
+        if (i == 0) rinv[pj] = inv;
       }
+#pragma unroll
+      for (int j = 0; j < GW; ++j)
+        if (i >= c0 + j) Ld[i][c0 + j] = x[j];
     }
     __syncthreads();
   }
@@ -102,14 +136,14 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
       if (i < nb && k <= i) K[(j0 + i) * ldK + j0 + k] = Ld[i][k];
     }
     if (t < nb && dinv) dinv[j0 + t] = rinv[t];
-    if (t == 0 && bad >= 0 && bad < nb) {
+    if (t == 0 && sbad >= 0 && sbad < nb) {
       unsigned long long* p = reinterpret_cast<unsigned long long*>(info);
-      atomicCAS(p, 0ull, (unsigned long long)(j0 + bad + 1));
+      atomicCAS(p, 0ull, (unsigned long long)(j0 + sbad + 1));
     }
     return;
   }
 
-  // ---- L21 rows: x L11^T = a  (forward substitution; 4 lanes per row)
+  // ---- L21 rows: X L11^T = A21, by the same 8-column groups
   const int64_t r0 = j0 + (int64_t)blockIdx.x * NB;
   {
     double v[16];
@@ -125,9 +159,24 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
     }
   }
   __syncthreads();
-  for (int j = 0; j < NB; ++j) {
-    const double x = (X[row][j] - dot4(&X[row][0], &Ld[j][0], j, sub)) * rinv[j];
-    if (sub == 0) X[row][j] = x;
+  for (int c0 = 0; c0 < NB; c0 += GW) {
+    group_update(X, Ld, c0, 0, false);
+    __syncthreads();
+    if (wave == 0) {
+      const int i = lane;
+      double x[GW];
+#pragma unroll
+      for (int j = 0; j < GW; ++j) x[j] = X[i][c0 + j];
+#pragma unroll
+      for (int j = 0; j < GW; ++j) {
+        double v = x[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= x[k] * Ld[c0 + j][c0 + k];
+        x[j] = v * rinv[c0 + j];
+      }
+#pragma unroll
+      for (int j = 0; j < GW; ++j) X[i][c0 + j] = x[j];
+    }
     __syncthreads();
   }
 #pragma unroll
@@ -164,6 +213,32 @@ __global__ void blkdiag_copy_kernel(int64_t m, const double* __restrict__ L, int
   D[q * nbi * nbi + e] = v;
 }
 
+// dst[j][i] = src[i][j] for a batch of rows x cols matrices (64 x 64 tiles
+// through LDS, both sides coalesced). lower_only: only src entries with
+// j < i (strict lower) are moved.
+__global__ __launch_bounds__(256) void transpose_kernel(int64_t rows, int64_t cols,
+                                                        const double* __restrict__ src,
+                                                        int64_t lds, int64_t sstride,
+                                                        double* __restrict__ dst, int64_t ldd,
+                                                        int64_t dstride, int lower_only) {
+  __shared__ double tile[64][65];
+  const int64_t b = blockIdx.z;
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  if (lower_only && j0 > i0 + 63) return;  // tile entirely above the diagonal
+  src += b * sstride;
+  dst += b * dstride;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    tile[r][tx] = (i < rows && j < cols) ? src[i * lds + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t j = j0 + r, i = i0 + tx;  // dst row j, column i
+    if (j < cols && i < rows && (!lower_only || j < i)) dst[j * ldd + i] = tile[tx][r];
+  }
+}
+
 // In-place inverse of every 64 x 64 diagonal block of the D_q: lane c
 // computes column c by forward substitution.
 __global__ __launch_bounds__(64) void tri_inv64_kernel(int64_t nbi, double* __restrict__ D) {
@@ -195,59 +270,46 @@ __global__ __launch_bounds__(64) void tri_inv64_kernel(int64_t nbi, double* __re
   for (int i = 0; i < NB; ++i) base[i * nbi + c] = Xb[i][c];
 }
 
-// y[r] = alpha * sum_k A[r][k] x[k] + beta * y[r]   (r < M; 8 rows per workgroup)
+// y[r] = alpha * sum_k A[r][k] x[k] + beta * y[r]   (r < M; 4 rows per workgroup)
+// Each thread loads 4 consecutive doubles of every row per 1024-column chunk,
+// so a 1024-wide row segment is one round of loads for the whole workgroup.
+constexpr int GR_ROWS = 4;
 __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t M, int64_t K,
                                                         const double* __restrict__ A, int64_t lda,
                                                         const double* __restrict__ x, double alpha,
                                                         double beta, double* __restrict__ y) {
-  __shared__ double red[4][8];
-  const int64_t r0 = (int64_t)blockIdx.x * 8;
-  double acc[8];
+  __shared__ double red[4][GR_ROWS];
+  const int64_t r0 = (int64_t)blockIdx.x * GR_ROWS;
+  double acc[GR_ROWS];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  for (int64_t k = threadIdx.x; k < K; k += 256) {
-    const double xv = x[k];
+  for (int q = 0; q < GR_ROWS; ++q) acc[q] = 0.0;
+  for (int64_t k0 = 0; k0 < K; k0 += 1024) {
+    const int64_t k = k0 + (int64_t)threadIdx.x * 4;
+    double xv[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (r0 + q < M) acc[q] += A[(r0 + q) * lda + k] * xv;
+    for (int e = 0; e < 4; ++e) xv[e] = (k + e < K) ? x[k + e] : 0.0;
+#pragma unroll
+    for (int q = 0; q < GR_ROWS; ++q) {
+      if (r0 + q < M) {
+        const double* a = A + (r0 + q) * lda + k;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (k + e < K) acc[q] += a[e] * xv[e];
+      }
+    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < GR_ROWS; ++q) {
     double v = acc[q];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (lane == 0) red[wave][q] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 8 && r0 + threadIdx.x < M) {
+  if (threadIdx.x < GR_ROWS && r0 + threadIdx.x < M) {
     const int q = threadIdx.x;
     const double v = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
     y[r0 + q] = (beta == 0.0) ? alpha * v : alpha * v + beta * y[r0 + q];
-  }
-}
-
-// y[c] = alpha * sum_r A[r][c] x[r] + beta * y[c]   (r < M, c < K; 64 columns per workgroup)
-__global__ __launch_bounds__(256) void gemv_cols_kernel(int64_t M, int64_t K,
-                                                        const double* __restrict__ A, int64_t lda,
-                                                        const double* __restrict__ x, double alpha,
-                                                        double beta, double* __restrict__ y) {
-  __shared__ double red[4][64];
-  const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int64_t c = (int64_t)blockIdx.x * 64 + cl;
-  double s0 = 0.0, s1 = 0.0;
-  if (c < K) {
-    int64_t r = rg;
-    for (; r + 4 < M; r += 8) {
-      s0 += A[r * lda + c] * x[r];
-      s1 += A[(r + 4) * lda + c] * x[r + 4];
-    }
-    if (r < M) s0 += A[r * lda + c] * x[r];
-  }
-  red[rg][cl] = s0 + s1;
-  __syncthreads();
-  if (rg == 0 && c < K) {
-    const double v = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
-    y[c] = (beta == 0.0) ? alpha * v : alpha * v + beta * y[c];
   }
 }
 
@@ -283,16 +345,7 @@ __global__ __launch_bounds__(64) void trsm_diag_kernel(int64_t ell, const double
 int gemv_rows(hipStream_t s, int64_t M, int64_t K, const double* A, int64_t lda, const double* x,
               double alpha, double beta, double* y) {
   if (M <= 0) return 0;
-  hipLaunchKernelGGL(gemv_rows_kernel, dim3((unsigned)cdiv(M, 8)), dim3(256), 0, s, M, K, A, lda,
-                     x, alpha, beta, y);
-  DNGD_LAUNCH_CHECK();
-  return 0;
-}
-
-int gemv_cols(hipStream_t s, int64_t M, int64_t K, const double* A, int64_t lda, const double* x,
-              double alpha, double beta, double* y) {
-  if (K <= 0) return 0;
-  hipLaunchKernelGGL(gemv_cols_kernel, dim3((unsigned)cdiv(K, 64)), dim3(256), 0, s, M, K, A, lda,
+  hipLaunchKernelGGL(gemv_rows_kernel, dim3((unsigned)cdiv(M, GR_ROWS)), dim3(256), 0, s, M, K, A, lda,
                      x, alpha, beta, y);
   DNGD_LAUNCH_CHECK();
   return 0;
@@ -361,15 +414,19 @@ int64_t chol_solve_block(int64_t m) {
   return nbi;
 }
 
+// Solve workspace: D (nb inverted diagonal blocks), their transposes, a
+// vector of m, and U = L^T (m x m, strict upper part used), so that both
+// substitutions are row-wise matrix-vector products.
 size_t chol_solve_aux_bytes(int64_t m) {
   const int64_t nbi = chol_solve_block(m), nb = cdiv(m, nbi);
-  return (size_t)(2 * nb * nbi * nbi + m) * sizeof(double);
+  return (size_t)(2 * nb * nbi * nbi + m + m * m) * sizeof(double);
 }
 
 int chol_prepare_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, double* aux) {
   const int64_t nbi = chol_solve_block(m), nb = cdiv(m, nbi);
   double* D = aux;
   double* T = aux + nb * nbi * nbi;
+  double* U = T + nb * nbi * nbi + m;
   hipLaunchKernelGGL(blkdiag_copy_kernel, dim3((unsigned)cdiv(nbi * nbi, 256), (unsigned)nb),
                      dim3(256), 0, s, m, L, ldL, nbi, D);
   DNGD_LAUNCH_CHECK();
@@ -388,14 +445,25 @@ int chol_prepare_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, d
                           T + sz * nbi, nbi, out, in, 0.0, D + sz * nbi, nbi, out, in, nb, pairs);
     if (rc) return rc;
   }
+  // T_q = D_q^T and U = L^T (strict upper)
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)(nbi / 64), (unsigned)(nbi / 64), (unsigned)nb),
+                     dim3(256), 0, s, nbi, nbi, D, nbi, nbi * nbi, T, nbi, nbi * nbi, 0);
+  DNGD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)cdiv(m, 64), (unsigned)cdiv(m, 64), 1u),
+                     dim3(256), 0, s, m, m, L, ldL, (int64_t)0, U, m, (int64_t)0, 1);
+  DNGD_LAUNCH_CHECK();
   return 0;
 }
 
+// forward  y_q = D_q b_q ;        b_{>q} -= L_{>q,q} y_q
+// backward x_q = D_q^T y_q ;      y_{<q} -= U_{<q,q} x_q   (U = L^T)
 int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, const double* aux,
                double* b) {
   const int64_t nbi = chol_solve_block(m), nb = cdiv(m, nbi);
   const double* D = aux;
+  const double* T = aux + nb * nbi * nbi;
   double* y = const_cast<double*>(aux) + 2 * nb * nbi * nbi;
+  const double* U = y + m;
   int rc = 0;
   for (int64_t q = 0; q < nb && !rc; ++q) {
     const int64_t r0 = q * nbi, mq = std::min(nbi, m - r0), rest = m - r0 - mq;
@@ -405,8 +473,8 @@ int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, const dou
   }
   for (int64_t q = nb - 1; q >= 0 && !rc; --q) {
     const int64_t r0 = q * nbi, mq = std::min(nbi, m - r0);
-    rc = gemv_cols(s, mq, mq, D + q * nbi * nbi, nbi, y + r0, 1.0, 0.0, b + r0);
-    if (!rc && r0 > 0) rc = gemv_cols(s, mq, r0, L + r0 * ldL, ldL, b + r0, -1.0, 1.0, y);
+    rc = gemv_rows(s, mq, mq, T + q * nbi * nbi, nbi, y + r0, 1.0, 0.0, b + r0);
+    if (!rc && r0 > 0) rc = gemv_rows(s, r0, mq, U + r0, m, b + r0, -1.0, 1.0, y);
   }
   return rc;
 }

@@ -136,24 +136,21 @@ size_t chol_workspace_bytes(int64_t m);
 // column (1-based); dinv (device, m doubles, may be null) receives 1 / L_ii.
 int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, double* dinv);
 // Solves with a stored factor L: chol_prepare_solve builds the inverted
-// diagonal blocks into `aux` (chol_solve_aux_bytes(m) bytes, device); then
-// chol_solve overwrites b with (L L^T)^{-1} b. aux also holds the solve's
-// temporary vector, so one aux serves one solve at a time.
+// diagonal blocks, their transposes and U = L^T into `aux`
+// (chol_solve_aux_bytes(m) bytes, device); then chol_solve overwrites b with
+// (L L^T)^{-1} b. aux also holds the solve's temporary vector, so one aux
+// serves one solve at a time.
 int64_t chol_solve_block(int64_t m);
 size_t chol_solve_aux_bytes(int64_t m);
 int chol_prepare_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, double* aux);
 int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, const double* aux,
                double* b);
-// y = alpha A x + beta y (A: M x K row-major) and y = alpha A^T x + beta y
+// y = alpha A x + beta y (A: M x K row-major)
 int gemv_rows(hipStream_t s, int64_t M, int64_t K, const double* A, int64_t lda, const double* x,
-              double alpha, double beta, double* y);
-int gemv_cols(hipStream_t s, int64_t M, int64_t K, const double* A, int64_t lda, const double* x,
               double alpha, double beta, double* y);
 // B <- L^{-1} B for lower-triangular L (ell x ell) and B (ell x N row-major, ldB)
 int trsm_lower_left(hipStream_t s, int64_t ell, const double* L, int64_t ldL, int64_t N, double* B,
                     int64_t ldB);
-int chol_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, const double* dinv,
-               double* b, unsigned* flags, unsigned* epoch, int* dstatus);
 
 // ---------------------------------------------------------------------------
 // vector kernels (blas1.hip)

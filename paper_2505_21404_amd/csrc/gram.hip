@@ -6,8 +6,7 @@
 // 16-byte chunks and no transpose is needed anywhere.
 //
 // Mixed path (FP32 J): v_mfma_f32_32x32x16_bf16 with FP32 accumulation. J is
-// rounded to bf16 in registers right before the MFMAs (no bf16 copy of J in
-// HBM). PASSES == 3 keeps the rounding residual as a second bf16 term,
+// rounded to bf16 (RNE) as it is staged into LDS (no bf16 copy of J in HBM). PASSES == 3 keeps the rounding residual as a second bf16 term,
 // J ~ hi + lo, and accumulates hi hi^T + hi lo^T + lo hi^T, so K carries ~16
 // bits of J instead of 8. Dropping lo lo^T makes that K indefinite by up to
 // ||lo lo^T|| (~2^-16 max_i ||J_i||^2), which matters only when the damping is
@@ -55,34 +54,29 @@ union Chunk {
   bf16x8 h;
 };
 
-// Round 8 floats to bf16 (RNE); optionally produce the bf16 residual.
-__device__ inline void split8(const float4& a, const float4& b, Chunk& hi, Chunk& lo, bool want_lo) {
-  float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 h = (__bf16)f[e];
-    hi.h[e] = h;
-    if (want_lo) lo.h[e] = (__bf16)(f[e] - (float)h);
-  }
-}
-
 // 256 x 256 tile of K per workgroup: 8 waves in a 2 x 4 grid, each wave a
 // 128 x 64 block = 4 x 2 MFMA 32x32 accumulators. K advances 32 elements per
-// step. The FP32 slabs of both row panels go from HBM straight into LDS with
-// global_load_lds (no register staging), double-buffered in two separate LDS
-// stages so the loads of step it + 1 overlap the MFMAs of step it. Each wave
-// splits its fragments into bf16 hi (and lo) in registers right before the
-// MFMAs.
-// LDS rows are 32 floats = 8 chunks of 16 B; chunk c of row r is stored at
-// c ^ g(r), g(r) = (r & 7) ^ ((r >> 3) & 1).
+// step. The FP32 slabs of both row panels are loaded into registers one step
+// ahead (each lane 16 B of a row per load, 8 lanes per 128-byte row segment),
+// split once into bf16 hi (and lo) planes and stored in LDS, double-buffered,
+// so every element is converted once per workgroup and the MFMA fragments
+// are read as ready bf16 (one ds_read_b128 per operand).
+// LDS plane rows are 32 bf16 = 4 chunks of 16 B; chunk c of row r sits at
+// c ^ ((r >> 2) & 3), which makes the 16 rows a fragment read touches per
+// cycle land in 16 distinct 16-byte bank groups.
 constexpr int BT = 256;   // tile edge
 constexpr int BKE = 32;   // K elements per step
-constexpr int ROWCH = BKE / 4;  // 16-byte chunks per LDS row
+constexpr int PCH = BKE / 8;  // 16-byte bf16 chunks per plane row
 
-typedef __attribute__((address_space(3))) void lds_void;
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-__device__ inline int gsw(int r) { return (r & 7) ^ ((r >> 3) & 1); }
-__device__ inline int slot(int r, int c) { return r * ROWCH + (c ^ gsw(r)); }
+__device__ inline unsigned int pk_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned int, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+__device__ inline int psw(int r) { return (r >> 2) & 3; }
+// byte offset of (row r, chunk c) in a plane
+__device__ inline int poff(int r, int c) { return r * (PCH * 16) + ((c ^ psw(r)) << 4); }
 
 template <int PASSES>
 __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
@@ -93,10 +87,9 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
                                                         int64_t split0) {
   constexpr bool LO = (PASSES >= 3);
   constexpr bool LOLO = (PASSES == 4);
-  __shared__ float4 sA0[BT * ROWCH];
-  __shared__ float4 sB0[BT * ROWCH];
-  __shared__ float4 sA1[BT * ROWCH];
-  __shared__ float4 sB1[BT * ROWCH];
+  constexpr int PLANE = BT * PCH * 16;  // bytes per plane per stage
+  // stage s: A hi, B hi, A lo, B lo
+  __shared__ __attribute__((aligned(16))) char lds[2][LO ? 4 : 2][PLANE];
 
   // launch index -> (split, tile): each XCD gets a contiguous run of tiles of one split
   const int64_t lin = blockIdx.x;
@@ -116,29 +109,59 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
   const int wave = t >> 6;
   const int wm = wave >> 2, wn = wave & 3;   // 2 x 4 waves
 
-  // DMA geometry: wave w, instruction j fills LDS slots [(4w + j) * 64, +64):
-  // rows 8 (4w + j) + lane / 8, physical chunk lane % 8. Rows beyond m read
-  // row m - 1 (their K entries are discarded).
+  // load geometry: load q of a panel covers rows 64 q + 8 wave + lane / 8,
+  // floats 4 (lane % 8) .. +3 of the step. Rows beyond m read row m - 1
+  // (their K entries are discarded).
+  const int fch = lane & 7;                 // float4 chunk within the step
+  int lrow[4];
   const float* pa[4];
   const float* pb[4];
-  int ca[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int r = (wave * 4 + j) * 8 + (lane >> 3);
-    ca[j] = 4 * ((lane & 7) ^ gsw(r));
-    const int64_t ra = min(ti * BT + r, m - 1), rb = min(tj * BT + r, m - 1);
-    pa[j] = J + ra * ldJ;
-    pb[j] = J + rb * ldJ;
+  for (int q = 0; q < 4; ++q) {
+    lrow[q] = 64 * q + 8 * wave + (lane >> 3);
+    pa[q] = J + min(ti * BT + lrow[q], m - 1) * ldJ + 4 * fch;
+    pb[q] = J + min(tj * BT + lrow[q], m - 1) * ldJ + 4 * fch;
   }
-  auto dma = [&](int64_t k0, float4* dA, float4* dB) {
+  float4 ra[4], rb[4];
+  auto gload = [&](int64_t k0) {
+    const bool full = (k0 + BKE <= kend);
+    const int64_t kk = k0 + 4 * fch;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t k = k0 + ca[j];
-      const int64_t kk = (k < n) ? k : 0;  // in bounds; k >= kend is masked after the read
-      __builtin_amdgcn_global_load_lds(pa[j] + kk, (lds_void*)(dA + (wave * 4 + j) * 64), 16, 0, 0);
-      if (!diag)
-        __builtin_amdgcn_global_load_lds(pb[j] + kk, (lds_void*)(dB + (wave * 4 + j) * 64), 16, 0,
-                                         0);
+    for (int q = 0; q < 4; ++q) {
+      if (full) {
+        ra[q] = *reinterpret_cast<const float4*>(pa[q] + k0);
+        if (!diag) rb[q] = *reinterpret_cast<const float4*>(pb[q] + k0);
+      } else {
+        float a[4], b[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = kk + e < kend;
+          a[e] = ok ? pa[q][k0 + e] : 0.0f;
+          b[e] = (ok && !diag) ? pb[q][k0 + e] : 0.0f;
+        }
+        ra[q] = float4{a[0], a[1], a[2], a[3]};
+        rb[q] = float4{b[0], b[1], b[2], b[3]};
+      }
+    }
+  };
+  // split one float4 into bf16 hi (and lo) and store both halves-of-chunk
+  auto put = [&](char* hp, char* lp, int r, const float4& x) {
+    const unsigned int h0 = pk_bf16(x.x, x.y), h1 = pk_bf16(x.z, x.w);
+    const int off = poff(r, fch >> 1) + 8 * (fch & 1);
+    *reinterpret_cast<uint2*>(hp + off) = uint2{h0, h1};
+    if (LO) {
+      const float e0 = x.x - __uint_as_float(h0 << 16);
+      const float e1 = x.y - __uint_as_float(h0 & 0xffff0000u);
+      const float e2 = x.z - __uint_as_float(h1 << 16);
+      const float e3 = x.w - __uint_as_float(h1 & 0xffff0000u);
+      *reinterpret_cast<uint2*>(lp + off) = uint2{pk_bf16(e0, e1), pk_bf16(e2, e3)};
+    }
+  };
+  auto stage_store = [&](int st) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      put(lds[st][0], LO ? lds[st][2] : nullptr, lrow[q], ra[q]);
+      if (!diag) put(lds[st][1], LO ? lds[st][3] : nullptr, lrow[q], rb[q]);
     }
   };
 
@@ -150,69 +173,63 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-  // fragment of row r for k-slice sl: 8 floats (two chunks), split to bf16
-  auto frag = [&](const float4* S, int r, int sl, int64_t k0, bool tail, Chunk& hi, Chunk& lo) {
-    const int c0 = sl * 4 + 2 * (lane >> 5);
-    float4 x0 = S[slot(r, c0)];
-    float4 x1 = S[slot(r, c0 + 1)];
-    if (tail) {
-      const int64_t kb = k0 + sl * 16 + 8 * (lane >> 5);
-      float f[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        if (kb + e >= kend) f[e] = 0.0f;
-      x0 = float4{f[0], f[1], f[2], f[3]};
-      x1 = float4{f[4], f[5], f[6], f[7]};
-    }
-    split8(x0, x1, hi, lo, LO);
+  auto frag = [&](const char* plane, int r, int sl) -> bf16x8 {
+    Chunk c;
+    c.u = *reinterpret_cast<const uint4*>(plane + poff(r, 2 * sl + (lane >> 5)));
+    return c.h;
   };
-
-  auto compute = [&](const float4* SA, const float4* SB, int64_t k0) {
-    const bool tail = (k0 + BKE > kend);
+  auto compute = [&](int st) {
+    const char* Ah = lds[st][0];
+    const char* Bh = diag ? lds[st][0] : lds[st][1];
+    const char* Al = LO ? lds[st][2] : nullptr;
+    const char* Bl = LO ? (diag ? lds[st][2] : lds[st][3]) : nullptr;
 #pragma unroll
     for (int sl = 0; sl < BKE / 16; ++sl) {
-      Chunk bh[2], bl[2];
+      bf16x8 bh[2], bl[2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) frag(SB, wn * 64 + j * 32 + (lane & 31), sl, k0, tail, bh[j], bl[j]);
+      for (int j = 0; j < 2; ++j) {
+        const int r = wn * 64 + j * 32 + (lane & 31);
+        bh[j] = frag(Bh, r, sl);
+        if (LO) bl[j] = frag(Bl, r, sl);
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        Chunk ah, al;
-        frag(SA, wm * 128 + i * 32 + (lane & 31), sl, k0, tail, ah, al);
+        const int r = wm * 128 + i * 32 + (lane & 31);
+        const bf16x8 ah = frag(Ah, r, sl);
+        bf16x8 al;
+        if (LO) al = frag(Al, r, sl);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.h, bh[j].h, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
         if (LO) {
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.h, bl[j].h, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.h, bh[j].h, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
         }
         if (LOLO) {
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.h, bl[j].h, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl[j], acc[i][j], 0, 0, 0);
         }
       }
     }
   };
 
   const int64_t nk = (kend > kbeg) ? (kend - kbeg + BKE - 1) / BKE : 0;
-  if (nk > 0) dma(kbeg, sA0, sB0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  if (nk > 0) {
+    gload(kbeg);
+    stage_store(0);
+  }
   __syncthreads();
-  for (int64_t it = 0; it < nk; it += 2) {
-    if (it + 1 < nk) dma(kbeg + (it + 1) * BKE, sA1, sB1);
-    compute(sA0, diag ? sA0 : sB0, kbeg + it * BKE);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  for (int64_t it = 0; it < nk; ++it) {
+    const int st = (int)(it & 1);
+    if (it + 1 < nk) gload(kbeg + (it + 1) * BKE);
+    compute(st);
+    if (it + 1 < nk) stage_store(st ^ 1);
     __syncthreads();
-    if (it + 1 < nk) {
-      if (it + 2 < nk) dma(kbeg + (it + 2) * BKE, sA0, sB0);
-      compute(sA1, diag ? sA1 : sB1, kbeg + (it + 1) * BKE);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-    }
   }
 
   // accumulator v of tile (i, j): row 8 (v/4) + 4 (lane/32) + v%4, col lane%32
