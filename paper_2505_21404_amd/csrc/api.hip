@@ -60,6 +60,9 @@ struct dngd_problem {
   int J_dtype = -1;
   int64_t ldJ = 0, ldK = 0;
   hipEvent_t ev[10] = {nullptr};
+  // side stream and events of the factorisation's look-ahead
+  hipStream_t side = nullptr;
+  hipEvent_t cev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -524,6 +527,12 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   if (!rc) rc = dmalloc(h, (void**)&h->U, (size_t)g.R * sizeof(double));
   for (int e = 0; e < 10 && !rc; ++e)
     if (hipEventCreate(&h->ev[e]) != hipSuccess) rc = DNGD_EHIP;
+  for (int e = 0; e < 2 && !rc; ++e)
+    if (hipEventCreateWithFlags(&h->cev[e], hipEventDisableTiming) != hipSuccess) rc = DNGD_EHIP;
+  if (!rc && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+    h->side = nullptr;
+    rc = DNGD_EHIP;
+  }
   if (rc) {
     dngd_problem_destroy(h);
     return rc;
@@ -539,6 +548,9 @@ int dngd_problem_destroy(dngd_problem* h) {
     if (p) hipFree(p);
   for (auto& e : h->ev)
     if (e) hipEventDestroy(e);
+  for (auto& e : h->cev)
+    if (e) hipEventDestroy(e);
+  if (h->side) hipStreamDestroy(h->side);
   delete h;
   return DNGD_OK;
 }
@@ -1045,7 +1057,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[2], s));
     // Cholesky of K + lam I
-    rc = chol_factor(s, g.m, K, g.m, sm.info, nullptr);
+    rc = chol_factor(s, g.m, K, g.m, sm.info, nullptr, h->side, h->cev[0], h->cev[1]);
     if (rc) return rc;
     const bool can_escalate = adaptive && passes != DNGD_GRAM_F64;
     if (can_escalate) {

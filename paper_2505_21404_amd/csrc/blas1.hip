@@ -7,8 +7,8 @@
 // Each thread owns 4 adjacent columns (one 16-byte FP32 / 32-byte FP64 load
 // per row, coalesced across the wave) and a contiguous band of rows; the
 // per-band partial sums are added in FP64 in band order by a second kernel.
-// J t: 8 rows per workgroup so each slab of t (FP64, 2x the bytes of an FP32
-// row slab) is loaded once for 8 rows.
+// J t: 4 rows per workgroup so each slab of t (FP64, 2x the bytes of an FP32
+// row slab) is loaded once for 4 rows, with enough workgroups to fill the chip.
 #include "common.h"
 
 namespace dngd {
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void gemv_t_reduce_kernel(int64_t n, int split
   y[c] = alpha * s;
 }
 
-constexpr int GN_ROWS = 8;
+constexpr int GN_ROWS = 4;
 
 template <typename T>
 __global__ __launch_bounds__(256) void gemv_n_kernel(int64_t m, int64_t n, const T* __restrict__ J,

@@ -371,12 +371,19 @@ int trsm_lower_left(hipStream_t s, int64_t ell, const double* L, int64_t ldL, in
 
 size_t chol_workspace_bytes(int64_t) { return 0; }
 
-int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, double* dinv) {
+int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, double* dinv,
+                hipStream_t side, hipEvent_t ev_panel, hipEvent_t ev_trail) {
   // Block columns of width NB2 = 4 NB. Inside one, each 64-wide panel is
   // factored (diagonal block + the rows below) and applied to the remaining
-  // columns of the same block column; the trailing matrix then receives one
-  // rank-NB2 update on the matrix cores.
+  // columns of the same block column. The block column's update of the
+  // trailing matrix is split in two: the next block column (on `s`, needed
+  // by the next panels) and the rest (on `side` when given, overlapping the
+  // next block column's panels: look-ahead of one block). The two updates
+  // touch disjoint columns; `s` waits for the side update of block b before
+  // it updates block b + 2's columns itself.
   constexpr int NB2 = 4 * NB;
+  const bool ahead = side != nullptr && ev_panel != nullptr && ev_trail != nullptr;
+  bool side_busy = false;
   hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, dinfo, (int64_t)0);
   DNGD_LAUNCH_CHECK();
   for (int64_t jb = 0; jb < m; jb += NB2) {
@@ -397,14 +404,39 @@ int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo
       }
     }
     const int64_t rest = m - jend;
-    if (rest > 0) {
-      const double* L21 = K + jend * ldK + jb;
-      double* A22 = K + jend * ldK + jend;
-      int rc = gemm_f64(s, GEMM_SYRK_LOWER, true, true, rest, rest, jend - jb, -1.0, L21, ldK,
-                        L21, ldK, 1.0, A22, ldK);
+    if (rest <= 0) break;
+    const double* L21 = K + jend * ldK + jb;
+    double* A22 = K + jend * ldK + jend;
+    const int64_t kb = jend - jb;
+    if (!ahead) {
+      int rc = gemm_f64(s, GEMM_SYRK_LOWER, true, true, rest, rest, kb, -1.0, L21, ldK, L21, ldK,
+                        1.0, A22, ldK);
       if (rc) return rc;
+      continue;
+    }
+    // (i) the next block column, rows jend..m (lower part), on s; it overlaps
+    //     the previous side update's region, so wait for that first
+    if (side_busy) DNGD_HIP(hipStreamWaitEvent(s, ev_trail, 0));
+    const int64_t nxt = std::min<int64_t>(NB2, rest);
+    int rc = gemm_f64(s, GEMM_FULL_LOWER, true, true, rest, nxt, kb, -1.0, L21, ldK, L21, ldK,
+                      1.0, A22, ldK);
+    if (rc) return rc;
+    // (ii) everything right of it, on the side stream once this block's
+    //      panels are final
+    const int64_t r2 = rest - nxt;
+    if (r2 > 0) {
+      DNGD_HIP(hipEventRecord(ev_panel, s));
+      DNGD_HIP(hipStreamWaitEvent(side, ev_panel, 0));
+      rc = gemm_f64(side, GEMM_SYRK_LOWER, true, true, r2, r2, kb, -1.0, L21 + nxt * ldK, ldK,
+                    L21 + nxt * ldK, ldK, 1.0, A22 + nxt * ldK + nxt, ldK);
+      if (rc) return rc;
+      DNGD_HIP(hipEventRecord(ev_trail, side));
+      side_busy = true;
+    } else {
+      side_busy = false;
     }
   }
+  if (ahead && side_busy) DNGD_HIP(hipStreamWaitEvent(s, ev_trail, 0));
   return 0;
 }
 

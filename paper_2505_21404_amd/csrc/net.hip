@@ -206,7 +206,9 @@ __global__ void outer_seed_kernel(int64_t R, int w, const double* __restrict__ s
 
 // ---------------------------------------------------------------------------
 // Jacobian rows: J[p][W_l[o][k]] = sum_c Zbar_l[p,c][o] A_{l-1}[p,c][k],
-// J[p][b_l[o]] = Zbar_l[p,value][o]. One workgroup per point.
+// J[p][b_l[o]] = Zbar_l[p,value][o]. One workgroup per point; a thread owns
+// 4 consecutive inputs k (its A values stay in registers) and walks the
+// outputs o, with the point's adjoints staged in LDS chunk by chunk.
 
 struct JacLayers {
   const double* A[kMaxLayers];     // A_{l-1}: R x w_{l-1}
@@ -215,6 +217,16 @@ struct JacLayers {
   int64_t woff[kMaxLayers], boff[kMaxLayers];
   int L;
 };
+
+constexpr int JOC = 256;  // outputs per staged adjoint chunk
+
+__device__ inline void store4(float* p, const float (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = float4{v[0], v[1], v[2], v[3]};
+}
+__device__ inline void store4(double* p, const double (&v)[4]) {
+  reinterpret_cast<double2*>(p)[0] = double2{v[0], v[1]};
+  reinterpret_cast<double2*>(p)[1] = double2{v[2], v[3]};
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void jacobian_rows_kernel(RowMap rm, JacLayers jl, T* __restrict__ J,
@@ -229,6 +241,9 @@ __global__ __launch_bounds__(256) void jacobian_rows_kernel(RowMap rm, JacLayers
   T* row = J + (int64_t)blockIdx.x * ldJ;
   const int t = threadIdx.x;
   double ss = 0.0;
+  // the point's adjoints of a chunk of JOC outputs, staged in LDS (every
+  // thread of a row group reads the same entries)
+  __shared__ double zs[kMaxChannels][JOC];
   for (int l = 0; l < jl.L; ++l) {
     const int win = jl.win[l], wout = jl.wout[l];
     const double* A = jl.A[l] + base * win;
@@ -238,6 +253,8 @@ __global__ __launch_bounds__(256) void jacobian_rows_kernel(RowMap rm, JacLayers
     while (tpr < nq && tpr < 256) tpr <<= 1;
     const int rpp = 256 / tpr;
     T* W = row + jl.woff[l];
+    // 4 consecutive outputs per thread can be stored as one vector
+    const bool vec = (win % 4 == 0) && (jl.woff[l] % 4 == 0);
     for (int q0 = 0; q0 < nq; q0 += tpr) {
       const int q = q0 + (t % tpr);
       const bool qok = q < nq;
@@ -249,25 +266,41 @@ __global__ __launch_bounds__(256) void jacobian_rows_kernel(RowMap rm, JacLayers
           const int k = 4 * q + e;
           a[c][e] = (qok && c < C && k < win) ? A[(int64_t)c * win + k] : 0.0;
         }
-      if (qok) {
-        for (int o = t / tpr; o < wout; o += rpp) {
+      for (int o0 = 0; o0 < wout; o0 += JOC) {
+        const int oc = min(JOC, wout - o0);
+        __syncthreads();
+        for (int e = t; e < C * JOC; e += 256) {
+          const int c = e / JOC, o = e % JOC;
+          if (o < oc) zs[c][o] = Zb[(int64_t)c * wout + o0 + o];
+        }
+        __syncthreads();
+        if (!qok) continue;
+        for (int o = t / tpr; o < oc; o += rpp) {
           double v[4] = {0, 0, 0, 0};
 #pragma unroll
           for (int c = 0; c < kMaxChannels; ++c) {
             if (c < C) {
-              const double zc = Zb[(int64_t)c * wout + o];
+              const double zc = zs[c][o];
 #pragma unroll
               for (int e = 0; e < 4; ++e) v[e] += zc * a[c][e];
             }
           }
+          T* w = W + (int64_t)(o0 + o) * win + 4 * q;
+          T tv[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int k = 4 * q + e;
-            if (k < win) {
-              W[(int64_t)o * win + k] = (T)v[e];
-              const double vr = (double)(T)v[e];
+            tv[e] = (T)v[e];
+            if (4 * q + e < win) {
+              const double vr = (double)tv[e];
               ss += vr * vr;
             }
+          }
+          if (vec) {
+            store4(w, tv);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (4 * q + e < win) w[e] = tv[e];
           }
         }
       }
