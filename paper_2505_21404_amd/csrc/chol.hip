@@ -26,31 +26,49 @@ constexpr int NB = 64;
 // Grouped right-to-left elimination of one 64-wide panel, 8 columns at a
 // time. For group g (columns c0 .. c0+7):
 //   update  the group's columns of every row with the finished columns
-//           k < c0 (one dot product per entry, all 256 threads), then
+//           k < c0 (a 64 x 8 x c0 product on the FP64 matrix cores), then
 //   finish  the 8 columns by substitution inside wave 0 (lane i = row i,
 //           8 dependent steps with no workgroup barrier; LDS accesses of one
 //           wave complete in order).
 // Two barriers per group instead of two per column.
 constexpr int GW = 8;  // columns per group
 
-// S[i][j] -= sum_{k < c0} S[i][k] * Lr[j][k] for rows i in [r_lo, 64), j in the
-// group (j <= i when lower). Entries are spread over the 256 threads.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// S[i][c0 + j] -= sum_{k < c0} S[i][k] * Lr[c0 + j][k] for the group's 8
+// columns, rows i in [r_lo, 64), on the FP64 matrix cores: wave w owns rows
+// 16 w .. 16 w + 15 (a 16 x 16 tile whose columns 8..15 are padding) and
+// steps k by 4 (v_mfma_f64_16x16x4f64: A lane l = (row l % 16, k l / 16),
+// B lane l = (k l / 16, col l % 16), D element v of lane l = (row l / 16 + 4 v,
+// col l % 16)).
 __device__ inline void group_update(double (*S)[NB + 1], const double (*Lr)[NB + 1], int c0,
-                                    int r_lo, bool lower) {
-  const int t = threadIdx.x;
-  const int cnt = (NB - r_lo) * GW;
-  for (int e = t; e < cnt; e += 256) {
-    const int i = r_lo + e / GW, j = c0 + e % GW;
-    if (lower && j > i) continue;
-    double s0 = 0.0, s1 = 0.0;
-    int k = 0;
-    for (; k + 1 < c0; k += 2) {
-      s0 += S[i][k] * Lr[j][k];
-      s1 += S[i][k + 1] * Lr[j][k + 1];
-    }
-    if (k < c0) s0 += S[i][k] * Lr[j][k];
-    S[i][j] -= s0 + s1;
+                                    int r_lo) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ar = 16 * wave + (lane & 15), kq = lane >> 4, bc = lane & 15;
+  f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < c0; k0 += 4) {
+    const double a = S[ar][k0 + kq];
+    const double b = (bc < GW) ? Lr[c0 + bc][k0 + kq] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
+  if (bc < GW) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * wave + kq + 4 * v;
+      if (r >= r_lo) S[r][c0 + bc] -= acc[v];
+    }
+  }
+}
+
+// 1 / sqrt(d) for a positive finite d: the hardware estimate refined by two
+// Newton steps r <- r (3/2 - d r^2 / 2) (quadratic convergence from the
+// estimate's ~2^-22 relative error to FP64 rounding).
+__device__ inline double rsqrt_f64(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  r = r * __builtin_fma(-h * r, r, 1.5);
+  r = r * __builtin_fma(-h * r, r, 1.5);
+  return r;
 }
 
 // Value of v held by lane `lane` (uniform), broadcast to the wave.
@@ -94,7 +112,7 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
   // ---- factor the diagonal block:  L_jj = sqrt(a_jj - sum_k L_jk^2),
   //      L_ij = (a_ij - sum_k L_ik L_jk) / L_jj
   for (int c0 = 0; c0 < NB; c0 += GW) {
-    group_update(Ld, Ld, c0, c0, true);
+    if (c0 > 0) group_update(Ld, Ld, c0, c0);
     __syncthreads();
     if (wave == 0) {
       // lane i holds row i of the group in registers; row c0 + j of L (the
@@ -110,16 +128,15 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
 #pragma unroll
         for (int k = 0; k < j; ++k) sij -= x[k] * lane_value(x[k], pj);
         const double d = lane_value(sij, pj);  // the pivot, uniform
-        double ljj;
+        double inv, ljj;
         if (d > 0.0 && __builtin_isfinite(d)) {
-          ljj = sqrt(d);
+          inv = rsqrt_f64(d);
+          ljj = d * inv;
         } else {
           if (i == 0 && sbad < 0) sbad = pj;
-          ljj = __builtin_nan("");
+          inv = ljj = __builtin_nan("");
         }
-        const double inv = 1.0 / ljj;
-        if (i == pj) x[j] = ljj;
-        else if (i > pj) x[j] = sij * inv;
+        x[j] = (i == pj) ? ljj : ((i > pj) ? sij * inv : x[j]);
         if (i == 0) rinv[pj] = inv;
       }
 #pragma unroll
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
   }
   __syncthreads();
   for (int c0 = 0; c0 < NB; c0 += GW) {
-    group_update(X, Ld, c0, 0, false);
+    if (c0 > 0) group_update(X, Ld, c0, 0);
     __syncthreads();
     if (wave == 0) {
       const int i = lane;
