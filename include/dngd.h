@@ -94,7 +94,7 @@ typedef struct {
                            2^-16 D <= lambda / 10, else 4; then escalate (3 -> 4 ->
                            DNGD_GRAM_F64, 1 -> 4) when the factorisation fails or the
                            refinement residual of the v solve stays above ir_tol. */
-  int32_t reserved0;
+  int32_t no_lookahead;  /* dense: 1 = factor without the side-stream look-ahead (default 0) */
   double eps_norm;      /* GA guard: GA only if ||v|| > eps_norm (default 0) */
   /* PCG (solver == DNGD_PCG) */
   int64_t n_landmarks;      /* l: number of landmark residuals (<= m) */
@@ -133,7 +133,9 @@ const char* dngd_version(void);
 void dngd_step_opts_default(dngd_step_opts* opts);
 
 /* Create a problem handle: validates the description and copies the point
- * and target arrays to device memory owned by the handle. */
+ * and target arrays to device memory owned by the handle. The copies are
+ * complete when the call returns (the caller may free its arrays); work the
+ * caller enqueued to produce them must be finished before the call. */
 int dngd_problem_create(const dngd_problem_desc* desc, dngd_problem** out);
 int dngd_problem_destroy(dngd_problem* h);
 

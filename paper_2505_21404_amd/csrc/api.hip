@@ -500,12 +500,16 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
 
   int rc = 0;
+  // A device-to-device hipMemcpy does not wait for the copy before it
+  // returns, and the caller may free or reuse the source arrays as soon as
+  // this call returns: enqueue the copies, then wait for them.
   auto dup = [&](double** dst, const double* src, int64_t cnt) {
     if (rc) return;
     rc = dmalloc(h, (void**)dst, (size_t)std::max<int64_t>(cnt, 1) * sizeof(double));
     if (!rc && cnt > 0) {
-      hipError_t e = hipMemcpy(*dst, src, (size_t)cnt * sizeof(double), hipMemcpyDefault);
-      if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy", __FILE__, __LINE__);
+      hipError_t e = hipMemcpyAsync(*dst, src, (size_t)cnt * sizeof(double), hipMemcpyDefault,
+                                    nullptr);
+      if (e != hipSuccess) rc = hip_fail(e, "hipMemcpyAsync", __FILE__, __LINE__);
     }
   };
   dup(&h->x_int, d->x_int, g.n_int * g.d_in);
@@ -514,6 +518,10 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   dup(&h->f_int, d->f_int, g.n_int);
   dup(&h->g_bdy, d->g_bdy, g.n_bdy);
   dup(&h->g_init, d->g_init, g.n_init);
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
+  }
   if (!rc) rc = dmalloc(h, (void**)&h->A0, (size_t)g.R * g.d_in * sizeof(double));
   for (int l = 0; l < g.L - 1 && !rc; ++l) {
     const size_t b = (size_t)g.R * g.widths[l + 1] * sizeof(double);
@@ -627,7 +635,7 @@ int dngd_cholesky_solve(int64_t m, double* K, int64_t ldK, int32_t factored, int
   double* aux = reinterpret_cast<double*>(scratch + 64);
   int rc = 0;
   if (!factored) {
-    rc = chol_factor(s, m, K, ldK, dinfo, nullptr);
+    rc = chol_factor(s, m, K, ldK, dinfo, aux, nullptr);
     if (!rc) {
       hipError_t e = hipMemcpyAsync(info, dinfo, sizeof(int64_t), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -784,7 +792,7 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
     std::vector<double> A(Kii);
     for (int64_t i = 0; i < ell; ++i) A[(size_t)i * ell + i] += delta;
     DNGD_HIP(hipMemcpyAsync(LI, A.data(), A.size() * 8, hipMemcpyHostToDevice, s));
-    rc = chol_factor(s, ell, LI, ell, reinterpret_cast<int64_t*>(v.scal), nullptr);
+    rc = chol_factor(s, ell, LI, ell, reinterpret_cast<int64_t*>(v.scal), P.Gaux, nullptr);
     if (rc) return rc;
     DNGD_HIP(hipMemcpyAsync(&hinfo, v.scal, 8, hipMemcpyDeviceToHost, s));
     DNGD_HIP(hipStreamSynchronize(s));
@@ -801,7 +809,7 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
   if (rc) return rc;
   rc = gram_launch(s, ell, g.m, P.Mt, ldM, DNGD_F64, 1, lambda, P.G, ell, h->gram_work.p, gw);
   if (rc) return rc;
-  rc = chol_factor(s, ell, P.G, ell, reinterpret_cast<int64_t*>(v.scal), nullptr);
+  rc = chol_factor(s, ell, P.G, ell, reinterpret_cast<int64_t*>(v.scal), P.Gaux, nullptr);
   if (rc) return rc;
   DNGD_HIP(hipMemcpyAsync(&hinfo, v.scal, 8, hipMemcpyDeviceToHost, s));
   DNGD_HIP(hipStreamSynchronize(s));
@@ -1057,7 +1065,10 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[2], s));
     // Cholesky of K + lam I
-    rc = chol_factor(s, g.m, K, g.m, sm.info, nullptr, h->side, h->cev[0], h->cev[1]);
+    double* cwork = static_cast<double*>(h->solve_aux.p);  // reused by the solves after
+    rc = o.no_lookahead ? chol_factor(s, g.m, K, g.m, sm.info, cwork, nullptr)
+                        : chol_factor(s, g.m, K, g.m, sm.info, cwork, nullptr, h->side,
+                                      h->cev[0], h->cev[1]);
     if (rc) return rc;
     const bool can_escalate = adaptive && passes != DNGD_GRAM_F64;
     if (can_escalate) {

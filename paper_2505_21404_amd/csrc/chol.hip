@@ -79,10 +79,16 @@ __device__ inline double lane_value(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Every workgroup reads the diagonal block from K, so workgroup 0 must not
+// overwrite it while others may still be loading it (workgroups of a launch
+// can start at any time): L11 goes to `lbuf` (64 x 64, row-major) and is
+// copied into K by diag_writeback_kernel after the last panel (nothing reads
+// the factored diagonal blocks before that).
 __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __restrict__ K,
                                                           int64_t ldK, int64_t j0,
                                                           int64_t* __restrict__ info,
-                                                          double* __restrict__ dinv) {
+                                                          double* __restrict__ dinv,
+                                                          double* __restrict__ lbuf) {
   // Ld: the diagonal block, factored in place (lower part). X: this
   // workgroup's 64 panel rows below it (workgroups >= 1).
   __shared__ double Ld[NB][NB + 1];
@@ -149,8 +155,8 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
   if (blockIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int e = q * 256 + t, i = e / NB, k = e % NB;
-      if (i < nb && k <= i) K[(j0 + i) * ldK + j0 + k] = Ld[i][k];
+      const int e = q * 256 + t;
+      lbuf[e] = Ld[e / NB][e % NB];
     }
     if (t < nb && dinv) dinv[j0 + t] = rinv[t];
     if (t == 0 && sbad >= 0 && sbad < nb) {
@@ -204,6 +210,18 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
 }
 
 __global__ void set_i64_kernel(int64_t* p, int64_t v) { *p = v; }
+
+// K's diagonal 64 x 64 blocks (lower part) <- the factored blocks in lbuf
+__global__ __launch_bounds__(256) void diag_writeback_kernel(int64_t m, double* __restrict__ K,
+                                                             int64_t ldK,
+                                                             const double* __restrict__ lbuf) {
+  const int64_t j0 = (int64_t)blockIdx.x * NB;
+  const double* src = lbuf + (int64_t)blockIdx.x * NB * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int i = e / NB, k = e % NB;
+    if (j0 + i < m && k <= i) K[(j0 + i) * ldK + j0 + k] = src[e];
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Solves with the factor: L and L^T are applied block by block with explicit
@@ -386,10 +404,11 @@ int trsm_lower_left(hipStream_t s, int64_t ell, const double* L, int64_t ldL, in
   return 0;
 }
 
-size_t chol_workspace_bytes(int64_t) { return 0; }
+size_t chol_workspace_bytes(int64_t m) { return (size_t)cdiv(m, NB) * NB * NB * sizeof(double); }
 
-int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, double* dinv,
-                hipStream_t side, hipEvent_t ev_panel, hipEvent_t ev_trail) {
+int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, double* work,
+                double* dinv, hipStream_t side, hipEvent_t ev_panel, hipEvent_t ev_trail) {
+  DNGD_REQUIRE(work != nullptr, "chol_factor: needs chol_workspace_bytes(m) of scratch");
   // Block columns of width NB2 = 4 NB. Inside one, each 64-wide panel is
   // factored (diagonal block + the rows below) and applied to the remaining
   // columns of the same block column. The block column's update of the
@@ -409,7 +428,7 @@ int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo
       const int64_t rows = m - j0;
       const unsigned nblk = (unsigned)cdiv(rows, NB);
       hipLaunchKernelGGL(potrf_panel_kernel, dim3(nblk), dim3(256), 0, s, m, K, ldK, j0, dinfo,
-                         dinv);
+                         dinv, work + (j0 / NB) * NB * NB);
       DNGD_LAUNCH_CHECK();
       const int64_t c0 = j0 + NB;            // first column still to update in this block
       if (c0 < jend) {
@@ -454,6 +473,9 @@ int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo
     }
   }
   if (ahead && side_busy) DNGD_HIP(hipStreamWaitEvent(s, ev_trail, 0));
+  hipLaunchKernelGGL(diag_writeback_kernel, dim3((unsigned)cdiv(m, NB)), dim3(256), 0, s, m, K,
+                     ldK, work);
+  DNGD_LAUNCH_CHECK();
   return 0;
 }
 
@@ -468,7 +490,8 @@ int64_t chol_solve_block(int64_t m) {
 // substitutions are row-wise matrix-vector products.
 size_t chol_solve_aux_bytes(int64_t m) {
   const int64_t nbi = chol_solve_block(m), nb = cdiv(m, nbi);
-  return (size_t)(2 * nb * nbi * nbi + m + m * m) * sizeof(double);
+  return std::max((size_t)(2 * nb * nbi * nbi + m + m * m) * sizeof(double),
+                  chol_workspace_bytes(m));
 }
 
 int chol_prepare_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, double* aux) {

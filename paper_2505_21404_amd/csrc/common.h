@@ -133,17 +133,21 @@ int gram_launch(hipStream_t s, int64_t m, int64_t n, const void* J, int64_t ldJ,
 
 size_t chol_workspace_bytes(int64_t m);
 // Factor the lower triangle in place; *dinfo (device int64) = 0 or first bad
-// column (1-based); dinv (device, m doubles, may be null) receives 1 / L_ii.
+// column (1-based); work: chol_workspace_bytes(m) of device scratch (the
+// factored diagonal blocks until the final write-back); dinv (device, m
+// doubles, may be null) receives 1 / L_ii.
 // With `side` and two events the trailing update runs one block ahead on the
 // side stream; `s` has joined it when the call's work on `s` completes.
-int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, double* dinv,
-                hipStream_t side = nullptr, hipEvent_t ev_panel = nullptr,
+int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo, double* work,
+                double* dinv, hipStream_t side = nullptr, hipEvent_t ev_panel = nullptr,
                 hipEvent_t ev_trail = nullptr);
 // Solves with a stored factor L: chol_prepare_solve builds the inverted
 // diagonal blocks, their transposes and U = L^T into `aux`
 // (chol_solve_aux_bytes(m) bytes, device); then chol_solve overwrites b with
 // (L L^T)^{-1} b. aux also holds the solve's temporary vector, so one aux
-// serves one solve at a time.
+// serves one solve at a time. chol_solve_aux_bytes(m) >=
+// chol_workspace_bytes(m), so the same buffer can serve as chol_factor's work
+// before chol_prepare_solve overwrites it.
 int64_t chol_solve_block(int64_t m);
 size_t chol_solve_aux_bytes(int64_t m);
 int chol_prepare_solve(hipStream_t s, int64_t m, const double* L, int64_t ldL, double* aux);

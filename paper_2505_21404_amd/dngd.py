@@ -43,7 +43,7 @@ class ProblemDesc(C.Structure):
 
 class StepOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("solver", C.c_int32), ("ga", C.c_int32),
-                ("ir_sweeps", C.c_int32), ("gram_passes", C.c_int32), ("reserved0", C.c_int32),
+                ("ir_sweeps", C.c_int32), ("gram_passes", C.c_int32), ("no_lookahead", C.c_int32),
                 ("eps_norm", C.c_double), ("n_landmarks", C.c_int64), ("landmarks", C.c_void_p),
                 ("pcg_tol", C.c_double), ("pcg_maxit", C.c_int64), ("ir_tol", C.c_double),
                 ("alpha_out", C.c_void_p), ("fvv_out", C.c_void_p)]

@@ -90,16 +90,21 @@ def test_footprint_query_is_host_only():
     assert b64 >= p.m * ldJ * 8 + p.m * p.m * 8
 
 
-def small_jobs(n=6, steps=3):
-    """A short job stream like the serving workload, scaled down (m 150-400,
-    width 16-32) so that it runs in seconds."""
-    jobs = W.serving_jobs(n_jobs=n, rate=40.0, steps=steps, m_range=(150, 400),
-                          widths_choice=(16, 32), depth=3)
+def small_jobs(n=8, steps=3):
+    """A short job stream like the serving workload, scaled down (m 900-2600,
+    width 32-64: several Cholesky block columns per job) so that it runs in
+    seconds while jobs overlap on the device."""
+    jobs = W.serving_jobs(n_jobs=n, rate=40.0, steps=steps, m_range=(900, 2600),
+                          widths_choice=(32, 64), depth=3)
     return SV.specs_from_workloads(jobs)
 
 
 @pytest.mark.gpu
 def test_results_identical_alone_and_in_mix():
+    """Every job's parameters after its iterations are bitwise the same alone
+    and in the mix (deterministic kernels, no state shared between jobs, and
+    no dependence on when a workgroup is scheduled: a mixed stream delays
+    workgroups of one job behind another job's kernels)."""
     torch = pytest.importorskip("torch")
     specs = small_jobs()
     alone = {s.job_id: SV.run_alone(s) for s in specs}
