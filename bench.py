@@ -53,6 +53,11 @@ def parse():
     ap.add_argument("--serving-steps", type=int, default=10,
                     help="iterations per serving job (the stream's jobs ask for 200)")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--pcg", action="store_true",
+                    help="instead: one Nystrom-PCG step on the 5-D Poisson MLP 5-2048x4-1, m=50000")
+    ap.add_argument("--pcg-landmarks", type=int, default=2000)
+    ap.add_argument("--pcg-maxit", type=int, default=500)
+    ap.add_argument("--pcg-tol", type=float, default=1e-6)
     return ap.parse_args()
 
 
@@ -156,6 +161,51 @@ def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def pcg_run(a, torch):
+    """One matrix-free Nystrom-PCG step (no GA) on the large 5-D Poisson
+    workload: n = 12.6M parameters, m = 50,000 residuals (45,000 interior,
+    5,000 boundary), FP64 kernel-vector products."""
+    import numpy as np
+    import workloads as W
+    from paper_2505_21404_amd import dngd as D
+    p = W.config(3)
+    th = torch.tensor(W.glorot_theta(p.widths, 0), device="cuda")
+    prob = D.Problem.from_workload(p)
+    r = prob.residual(th)
+    L0 = 0.5 * float((r * r).sum())
+    lam = min(L0, W.LAMBDA_CAP[3])
+    I = torch.tensor(W.landmarks(p.m, a.pcg_landmarks, 0), device="cuda")
+    alpha = torch.empty(prob.m, dtype=torch.float64, device="cuda")
+    opts = D.step_opts(solver=D.PCG, ga=False, landmarks=I, pcg_tol=a.pcg_tol,
+                       pcg_maxit=a.pcg_maxit, alpha_out=alpha)
+    progress(f"PCG step: n={prob.n} m={prob.m} landmarks={a.pcg_landmarks}")
+    t0 = time.perf_counter()
+    dth, st = prob.step(th, lam, opts)
+    wall = time.perf_counter() - t0
+    # true dual residual with one more FP64 matrix-free product, timed alone
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ka = prob.jvp(th, prob.vjp(th, alpha))
+    torch.cuda.synchronize()
+    kvp_ms = (time.perf_counter() - t1) * 1e3
+    true_res = float(((ka + lam * alpha - r).norm() / r.norm()).item())
+    its = max(st.pcg_iterations, 1)
+    out = {
+        "metric": "D-NGD PCG step (matrix-free, Nystrom preconditioner)", "unit": "s",
+        "value": wall, "higher_is_better": False, "n_gpus": 1,
+        "config": {"workload": "poisson5d_mlp5-2048x4-1_m50000_pcg", "n": prob.n, "m": prob.m,
+                   "landmarks": a.pcg_landmarks, "tol": a.pcg_tol, "maxit": a.pcg_maxit,
+                   "lambda": lam},
+        "pcg_iterations": st.pcg_iterations, "pcg_converged": bool(st.pcg_converged),
+        "pcg_rel_residual": st.pcg_rel_residual, "true_rel_residual": true_res,
+        "ms_forward": st.ms_residual_jacobian, "ms_nystrom_build": st.ms_factor,
+        "ms_pcg_and_recovery": st.ms_solve_v, "ms_per_pcg_iteration": st.ms_solve_v / its,
+        "ms_kvp_alone_incl_forward": kvp_ms, "dtheta_norm": float(dth.norm()),
+    }
+    prob.close()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -166,6 +216,9 @@ def main():
     import torch
     if a.copy_calibration:
         copy_calibration(torch)
+        return 0
+    if a.pcg:
+        print(json.dumps(pcg_run(a, torch)), flush=True)
         return 0
     import workloads as W
     from paper_2505_21404_amd import dngd as D

@@ -103,8 +103,9 @@ typedef struct {
   int64_t pcg_maxit;
   double ir_tol;            /* mixed, auto Gram: escalate when ||s|| / ||r|| before the last
                                refinement sweep of the v solve exceeds this (default 1e-5) */
-  /* optional device outputs of the dense step (NULL = not written): the dual
-     solution alpha = (K + lambda I)^{-1} r (m FP64) and f_vv (m FP64, GA only) */
+  /* optional device outputs (NULL = not written): the dual solution
+     alpha = (K + lambda I)^{-1} r (m FP64; dense and PCG) and f_vv (m FP64,
+     dense step with GA only) */
   double* alpha_out;
   double* fvv_out;
 } dngd_step_opts;

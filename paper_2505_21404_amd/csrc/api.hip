@@ -423,10 +423,16 @@ size_t vjp_work_bytes(const Geometry& g) {
                           (size_t)64 * kMaxWidth * sizeof(double));
 }
 
-// Rows of recomputed Jacobian per chunk of the Nystrom column build (~4 GB).
-int64_t nystrom_chunk_rows(const Geometry& g) {
-  const int64_t ldJ = round_up(g.n, 256);
-  return std::max<int64_t>(1, std::min<int64_t>(g.m, (int64_t)(4e9 / (ldJ * 8.0))));
+// Jet rows per chunk of the Nystrom column build: the two FP64 products of a
+// chunk against the RI landmark rows take at most ~8 GB.
+int64_t nystrom_chunk_rows(const Geometry& g, int64_t RI) {
+  const int64_t rows = (int64_t)(8e9 / (16.0 * (double)std::max<int64_t>(RI, 1)));
+  return std::max<int64_t>(g.C_int, std::min<int64_t>(g.R, rows));
+}
+
+// Jet rows of ell landmark points, at most (all interior points)
+int64_t nystrom_rows_bound(const Geometry& g, int64_t ell) {
+  return std::min<int64_t>(ell, g.n_int) * g.C_int + std::max<int64_t>(0, ell - g.n_int);
 }
 
 // Device bytes a handle holds after a step with options o (activations,
@@ -449,11 +455,12 @@ size_t footprint_bytes(const Geometry& g, const dngd_step_opts* o) {
     b += gram_workspace_bytes(g.m, g.n, jd, 3, nullptr);
   } else {
     const int64_t ell = std::max<int64_t>(1, o->n_landmarks);
-    const int64_t ldJ = round_up(g.n, 256), ldM = round_up(g.m, 4);
-    const int64_t chunk = nystrom_chunk_rows(g);
-    b += (size_t)(ell + chunk) * ldJ * 8;
-    b += (size_t)ell * ldM * 8 + (size_t)ell * ell * 8 + (size_t)std::max(chunk, ell) * 8 +
-         (size_t)ell * 8 + chol_solve_aux_bytes(ell);
+    const int64_t ldM = round_up(g.m, 4);
+    const int64_t RI = nystrom_rows_bound(g, ell);
+    const int64_t RC = nystrom_chunk_rows(g, RI);
+    b += (size_t)(RI + ell + 1) * 8 + 2 * (size_t)RI * g.max_width * 8 + 2 * (size_t)RC * RI * 8;
+    b += (size_t)ell * ldM * 8 + (size_t)ell * ell * 8 + 2 * (size_t)ell * 8 +
+         chol_solve_aux_bytes(ell);
     b += gram_workspace_bytes(ell, g.m, DNGD_F64, 1, nullptr);
   }
   return b;
@@ -734,46 +741,78 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
     DNGD_REQUIRE(hI[q] >= 0 && hI[q] < g.m, "landmark index %lld out of range", (long long)hI[q]);
     DNGD_REQUIRE(q == 0 || hI[q] > hI[q - 1], "landmarks must be sorted and distinct");
   }
-  const int64_t ldJ = round_up(g.n, 256);
+  // jet rows of the landmark points (a residual is one point)
+  std::vector<int64_t> rowsI, qoff(ell + 1, 0);
+  for (int64_t q = 0; q < ell; ++q) {
+    const int64_t p = hI[q];
+    const int64_t base = p < g.n_int ? p * g.C_int : g.R_int + (p - g.n_int);
+    const int C = p < g.n_int ? g.C_int : 1;
+    for (int c = 0; c < C; ++c) rowsI.push_back(base + c);
+    qoff[q + 1] = qoff[q] + C;
+  }
+  const int64_t RI = qoff[ell];
   const int64_t ldM = round_up(g.m, 4);
-  const int64_t chunk = nystrom_chunk_rows(g);
-  // J_I (ell x ldJ) and a chunk of J rows; Mt (ell x ldM), G (ell x ell), index list, ell scratch
-  const size_t bJI = (size_t)ell * ldJ * 8, bMt = (size_t)ell * ldM * 8, bG = (size_t)ell * ell * 8;
-  const size_t bCh = (size_t)chunk * ldJ * 8, bIdx = (size_t)std::max<int64_t>(chunk, ell) * 8;
-  int rc = ensure(h, h->J, bJI + bCh);
+  const int64_t RC = nystrom_chunk_rows(g, RI);
+  // work (h->J): landmark row lists, gathered G_I and H_I, chunk products Gp, Hp
+  const size_t bRows = (size_t)(RI + ell + 1) * 8, bGath = 2 * (size_t)RI * g.max_width * 8;
+  const size_t bProd = 2 * (size_t)RC * RI * 8;
+  int rc = ensure(h, h->J, bRows + bGath + bProd);
   if (rc) return rc;
-  rc = ensure(h, h->K, bMt + bG + bIdx + (size_t)ell * 8 + chol_solve_aux_bytes(ell));
+  int64_t* dRows = static_cast<int64_t*>(h->J.p);
+  int64_t* dQoff = dRows + RI;
+  double* GI = reinterpret_cast<double*>(dQoff + ell + 1);
+  double* HI = GI + (size_t)RI * g.max_width;
+  double* Gp = HI + (size_t)RI * g.max_width;
+  double* Hp = Gp + (size_t)RC * RI;
+  // Mt (ell x ldM), G (ell x ell), index scratch, ell vector, solve workspace
+  const size_t bMt = (size_t)ell * ldM * 8, bG = (size_t)ell * ell * 8;
+  rc = ensure(h, h->K, bMt + bG + (size_t)ell * 8 + (size_t)ell * 8 + chol_solve_aux_bytes(ell));
   if (rc) return rc;
-  double* JI = static_cast<double*>(h->J.p);
-  double* Jc = JI + (size_t)ell * ldJ;
   P.Mt = static_cast<double*>(h->K.p);
   P.ldM = ldM;
   P.G = P.Mt + (size_t)ell * ldM;
   int64_t* idx = reinterpret_cast<int64_t*>(P.G + (size_t)ell * ell);
-  P.tl = reinterpret_cast<double*>(idx + std::max<int64_t>(chunk, ell));
+  P.tl = reinterpret_cast<double*>(idx + ell);
   P.Gaux = P.tl + ell;
   P.ell = ell;
   P.lambda = lambda;
   StepVecs v;
   rc = carve_vecs(h, v);
   if (rc) return rc;
+  DNGD_HIP(hipMemcpyAsync(dRows, rowsI.data(), RI * 8, hipMemcpyHostToDevice, s));
+  DNGD_HIP(hipMemcpyAsync(dQoff, qoff.data(), (ell + 1) * 8, hipMemcpyHostToDevice, s));
+  DNGD_HIP(hipMemcpyAsync(idx, hI.data(), ell * 8, hipMemcpyHostToDevice, s));
 
+  // K_{I,:} = J_I J^T layer by layer from the Jacobian-seeded adjoints
   rc = backward(h, theta, nullptr, s);
   if (rc) return rc;
-  rc = write_jacobian(h, JI, ldJ, DNGD_F64, nullptr, s, I, ell);
-  if (rc) return rc;
-  // K_{I,:} = J_I J^T, by chunks of recomputed Jacobian rows
-  std::vector<int64_t> hidx(chunk);
-  for (int64_t c0 = 0; c0 < g.m; c0 += chunk) {
-    const int64_t cn = std::min(chunk, g.m - c0);
-    for (int64_t q = 0; q < cn; ++q) hidx[q] = c0 + q;
-    DNGD_HIP(hipMemcpyAsync(idx, hidx.data(), cn * 8, hipMemcpyHostToDevice, s));
-    rc = write_jacobian(h, Jc, ldJ, DNGD_F64, nullptr, s, idx, cn);
+  const int64_t npts = g.m;
+  for (int l = 0; l < g.L; ++l) {
+    const int win = g.widths[l], wout = g.widths[l + 1];
+    const double* Gl = (l < g.L - 1) ? h->Zb[l] : h->seed;
+    const double* Hl = act_in(h, l);
+    rc = net_gather_rows(s, RI, wout, dRows, Gl, GI);
+    if (!rc) rc = net_gather_rows(s, RI, win, dRows, Hl, HI);
     if (rc) return rc;
-    rc = gemm_f64(s, GEMM_FULL, true, true, ell, cn, g.n, 1.0, JI, ldJ, Jc, ldJ, 0.0, P.Mt + c0,
-                  ldM);
-    if (rc) return rc;
-    DNGD_HIP(hipStreamSynchronize(s));  // hidx is reused
+    for (int64_t p0 = 0; p0 < npts;) {
+      // points [p0, p1) whose jet rows fit in one chunk
+      const int64_t row0 = p0 < g.n_int ? p0 * g.C_int : g.R_int + (p0 - g.n_int);
+      int64_t p1 = p0;
+      if (p0 < g.n_int) p1 = std::min<int64_t>(g.n_int, p0 + std::max<int64_t>(1, RC / g.C_int));
+      else p1 = std::min<int64_t>(npts, p0 + RC);
+      const int64_t row1 = p1 < g.n_int ? p1 * g.C_int : g.R_int + (p1 - g.n_int);
+      const int64_t nr = row1 - row0;
+      rc = gemm_f64(s, GEMM_FULL, true, true, nr, RI, wout, 1.0, Gl + row0 * wout, wout, GI, wout,
+                    0.0, Gp, RI);
+      if (!rc)
+        rc = gemm_f64(s, GEMM_FULL, true, true, nr, RI, win, 1.0, Hl + row0 * win, win, HI, win,
+                      0.0, Hp, RI);
+      if (!rc)
+        rc = net_nystrom_combine(s, h->rm, p0, p1 - p0, row0, Gp, Hp, RI, ell, dQoff, P.Mt, ldM,
+                                 l > 0 ? 1 : 0);
+      if (rc) return rc;
+      p0 = p1;
+    }
   }
   // K_II (landmark columns of K_{I,:}), shifted by delta and factorised; the
   // shift grows until the factorisation succeeds
@@ -982,6 +1021,10 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     const int pst =
         pcg_solve(h, theta, P, v, sm, v.r, v.fvv, o.pcg_tol, o.pcg_maxit, &its, &rel, s);
     if (pst < 0) return pst;
+    if (o.alpha_out) {
+      rc = copy(s, g.m, v.fvv, o.alpha_out);
+      if (rc) return rc;
+    }
     // dtheta = -J^T alpha (matrix-free reverse pass)
     rc = vjp(h, theta, v.fvv, v.v, s);
     if (rc) return rc;
@@ -997,6 +1040,8 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     float ms = 0;
     hipEventElapsedTime(&ms, h->ev[0], h->ev[7]);
     st.ms_total = ms;
+    hipEventElapsedTime(&ms, h->ev[0], h->ev[1]);
+    st.ms_residual_jacobian = ms;
     hipEventElapsedTime(&ms, h->ev[1], h->ev[2]);
     st.ms_factor = ms;
     hipEventElapsedTime(&ms, h->ev[2], h->ev[3]);

@@ -213,6 +213,12 @@ int net_jacobian_rows(hipStream_t s, const Geometry& g, const RowMap& rm, const 
                       int64_t nrows = 0);
 int net_tangent_act(hipStream_t s, const RowMap& rm, int w, const double* b1, const double* Z0,
                     double* Z1, double* Z2, double* A1, double* A2, int order);
+// Nystrom landmark columns without J (net.hip)
+int net_gather_rows(hipStream_t s, int64_t nrows, int w, const int64_t* rows, const double* src,
+                    double* dst);
+int net_nystrom_combine(hipStream_t s, const RowMap& rm, int64_t p0, int64_t np, int64_t row0,
+                        const double* Gp, const double* Hp, int64_t ld, int64_t ell,
+                        const int64_t* qoff, double* Mt, int64_t ldM, int accumulate);
 int net_colsum_value_rows(hipStream_t s, const RowMap& rm, int w, const double* Zbar, double* out,
                           double* work);
 

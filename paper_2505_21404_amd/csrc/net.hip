@@ -449,6 +449,48 @@ __global__ void colsum_reduce_kernel(int w, int S, const double* __restrict__ pa
   out[o] = s;
 }
 
+// ---------------------------------------------------------------------------
+// Landmark columns of K without forming J (Nystrom construction): for an
+// affine layer with input activations H (jet rows x w_in) and output
+// adjoints G (jet rows x w_out), the layer's part of J_i . J_j is
+//   sum_{c in rows(i), c' in rows(j)} (G_c . G_c') (H_c . H_c') + G_i0 . G_j0,
+// the second term from the bias (value rows only). G G_I^T and H H_I^T are
+// FP64 GEMMs; this kernel gathers the landmark rows and combines.
+
+__global__ void gather_rows_kernel(int64_t nrows, int w, const int64_t* __restrict__ rows,
+                                   const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nrows * w) return;
+  const int64_t r = e / w, k = e % w;
+  dst[e] = src[rows[r] * w + k];
+}
+
+// Mt[q][p] (=, or += when accumulate) for points p in [p0, p0 + np) and all
+// landmarks q; Gp, Hp hold the rows of the chunk starting at jet row row0,
+// one column per landmark jet row (ld = total landmark rows).
+__global__ void nystrom_combine_kernel(RowMap rm, int64_t p0, int64_t np, int64_t row0,
+                                       const double* __restrict__ Gp,
+                                       const double* __restrict__ Hp, int64_t ld, int64_t ell,
+                                       const int64_t* __restrict__ qoff, double* __restrict__ Mt,
+                                       int64_t ldM, int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= np * ell) return;
+  const int64_t i = e / ell, q = e % ell;  // consecutive threads: consecutive landmarks
+  int64_t base;
+  int C;
+  point_rows(rm, p0 + i, base, C);
+  const int64_t rb = base - row0;
+  const int64_t o = qoff[q], Cq = qoff[q + 1] - o;
+  double sum = Gp[rb * ld + o];  // bias: value rows
+  for (int c = 0; c < C; ++c) {
+    const double* g = Gp + (rb + c) * ld + o;
+    const double* h = Hp + (rb + c) * ld + o;
+    for (int64_t c2 = 0; c2 < Cq; ++c2) sum += g[c2] * h[c2];
+  }
+  double* out = Mt + q * ldM + p0 + i;
+  *out = accumulate ? *out + sum : sum;
+}
+
 }  // namespace
 
 RowMap row_map(const Geometry& g) {
@@ -593,6 +635,29 @@ int net_colsum_value_rows(hipStream_t s, const RowMap& rm, int w, const double* 
                      per, work);
   DNGD_LAUNCH_CHECK();
   hipLaunchKernelGGL(colsum_reduce_kernel, dim3(blocks_for(w)), dim3(256), 0, s, w, S, work, out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+}  // namespace dngd
+
+namespace dngd {
+
+int net_gather_rows(hipStream_t s, int64_t nrows, int w, const int64_t* rows, const double* src,
+                    double* dst) {
+  if (nrows * w <= 0) return 0;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for(nrows * w)), dim3(256), 0, s, nrows, w,
+                     rows, src, dst);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_nystrom_combine(hipStream_t s, const RowMap& rm, int64_t p0, int64_t np, int64_t row0,
+                        const double* Gp, const double* Hp, int64_t ld, int64_t ell,
+                        const int64_t* qoff, double* Mt, int64_t ldM, int accumulate) {
+  if (np * ell <= 0) return 0;
+  hipLaunchKernelGGL(nystrom_combine_kernel, dim3(blocks_for(np * ell)), dim3(256), 0, s, rm, p0,
+                     np, row0, Gp, Hp, ld, ell, qoff, Mt, ldM, accumulate);
   DNGD_LAUNCH_CHECK();
   return 0;
 }

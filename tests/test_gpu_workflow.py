@@ -232,3 +232,24 @@ def test_gram_f64_products_of_fp32_jacobian():
     ref = J64 @ J64.T + 0.5 * np.eye(m)
     low = np.tril_indices(m)
     assert np.abs(K[low] - ref[low]).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_pcg_heat_all_landmarks_and_partial():
+    """Heat problem (three residual classes, 5 jet rows per interior point):
+    with every residual a landmark the preconditioner inverts K + lam I, and
+    with a subset PCG still reaches the dense solution."""
+    d = D()
+    p = W.heat_problem([3, 24, 24, 1], 180, 40, 40, 0.2, 12)
+    th = W.glorot_theta(p.widths, 2)
+    prob = d.Problem.from_workload(p)
+    r = N.residual(p, th)
+    J = N.jacobian(p, th)
+    lam = 1e-3
+    alpha = S.solve(S.cholesky(J @ J.T, lam), r)
+    for ell, max_it in ((p.m, 2), (60, 500)):
+        I = W.landmarks(p.m, ell, 4)
+        x, st, rc = prob.nystrom_pcg(th, lam, torch.tensor(I), r, tol=1e-10, maxit=500)
+        say("heat pcg ell", ell, "iters", st.pcg_iterations)
+        assert rc == d.OK and st.pcg_iterations <= max_it
+        assert rel(x.cpu().numpy(), alpha) <= 1e-6
+    prob.close()
