@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--pcg-landmarks", type=int, default=2000)
     ap.add_argument("--pcg-maxit", type=int, default=500)
     ap.add_argument("--pcg-tol", type=float, default=1e-6)
+    ap.add_argument("--pcg-iters", type=int, default=0,
+                    help="with --pcg: also run this many optimiser iterations (PCG steps + line search)")
     return ap.parse_args()
 
 
@@ -202,6 +204,23 @@ def pcg_run(a, torch):
         "ms_pcg_and_recovery": st.ms_solve_v, "ms_per_pcg_iteration": st.ms_solve_v / its,
         "ms_kvp_alone_incl_forward": kvp_ms, "dtheta_norm": float(dth.norm()),
     }
+    if a.pcg_iters > 0:
+        # optimiser iterations: fresh landmarks per step (seed + 3 + k), damping rule
+        etas = [2.0 ** -k for k in range(31)]
+        hist = []
+        for k in range(a.pcg_iters):
+            Ik = torch.tensor(W.landmarks(p.m, a.pcg_landmarks, 0, step=k), device="cuda")
+            ok = D.step_opts(solver=D.PCG, ga=False, landmarks=Ik, pcg_tol=a.pcg_tol,
+                             pcg_maxit=a.pcg_maxit)
+            t0 = time.perf_counter()
+            it = prob.iterate(th, etas, lam_cap=W.LAMBDA_CAP[3], opts=ok)
+            hist.append({"loss": it.loss, "lam": it.lam, "eta": it.eta,
+                         "pcg_iterations": it.step.pcg_iterations,
+                         "pcg_rel_residual": it.step.pcg_rel_residual,
+                         "s_step": it.step.ms_total / 1e3, "s_line_search": it.ms_line_search / 1e3,
+                         "s_iteration": time.perf_counter() - t0})
+            progress(f"PCG iteration {k}: loss {it.loss:.4g} pcg its {it.step.pcg_iterations}")
+        out["iterations"] = hist
     prob.close()
     return out
 
