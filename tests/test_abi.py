@@ -58,3 +58,31 @@ def test_argument_validation_without_gpu():
     info = ctypes.c_int64()
     assert lib.dngd_cholesky_solve(0, ctypes.c_void_p(8), 1, 0, 0, None, 1, ctypes.byref(info),
                                    None) == dngd.EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdngd.so not built")
+def test_description_validation_and_defaults_without_gpu():
+    """dngd_footprint_desc validates a description on the host; the step
+    options have the documented defaults."""
+    from paper_2505_21404_amd import dngd
+    import workloads as W
+    ok = W.config(0)
+    assert dngd.footprint_of(ok.pde, ok.widths, ok.n_int, ok.n_bdy, ok.n_init) > 0
+    bad = [
+        (dngd.POISSON, [2, 8, 2], 10, 5, 0),         # two outputs
+        (dngd.POISSON, [9, 8, 1], 10, 5, 0),         # d_in above 8
+        (dngd.POISSON, [2, 8, 1], 10, 5, 3),         # initial points without heat
+        (dngd.HEAT, [1, 8, 1], 10, 5, 3),            # heat needs time plus space
+        (dngd.POISSON, [2, 5000, 1], 10, 5, 0),      # hidden width above 4096
+        (dngd.POISSON, [2, 8, 1], 0, 0, 0),          # no points
+        (dngd.POISSON, [2, 8, 1], -1, 5, 0),         # negative count
+    ]
+    for pde, widths, ni, nb, n0 in bad:
+        with pytest.raises(dngd.DngdError) as e:
+            dngd.footprint_of(pde, widths, ni, nb, n0)
+        assert e.value.status == dngd.EINVAL
+    o = dngd.StepOpts()
+    dngd._lib.dngd_step_opts_default(ctypes.byref(o))
+    assert (o.precision, o.solver, o.ga, o.ir_sweeps, o.gram_passes) == (dngd.MIXED, dngd.DENSE, 1, 2, 0)
+    assert o.eps_norm == 0.0 and o.pcg_tol == 1e-6 and o.pcg_maxit == 500 and o.ir_tol == 1e-5
+    assert o.no_lookahead == 0 and not o.alpha_out and not o.fvv_out
