@@ -278,7 +278,8 @@ size_t step_vec_bytes(const Geometry& g) {
   // (at most 64 row bands of m columns)
   const size_t gw = std::max(gemv_t_workspace_bytes(std::max<int64_t>(g.m, 1), std::max<int64_t>(g.n, 1)),
                              (size_t)64 * (size_t)std::max<int64_t>(g.m, 1) * sizeof(double));
-  return (size_t)(7 * g.m + 4 * g.n + 64) * sizeof(double) + kReduceWorkBytes + gw;
+  // each of the 13 segments is padded to 32 doubles (256-byte aligned starts)
+  return (size_t)(7 * g.m + 4 * g.n + 64 + 13 * 32) * sizeof(double) + kReduceWorkBytes + gw;
 }
 
 int carve_vecs(dngd_problem* h, StepVecs& v) {
@@ -286,9 +287,9 @@ int carve_vecs(dngd_problem* h, StepVecs& v) {
   int rc = ensure(h, h->vecs, step_vec_bytes(g));
   if (rc) return rc;
   double* p = static_cast<double*>(h->vecs.p);
-  auto take = [&](int64_t k) {
+  auto take = [&](int64_t k) {  // segments start 256-byte aligned (vector loads, GEMM operands)
     double* q = p;
-    p += k;
+    p += round_up(k, 32);
     return q;
   };
   v.r = take(g.m);

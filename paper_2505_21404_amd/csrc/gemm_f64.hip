@@ -193,6 +193,159 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
       }
 }
 
+// ---------------------------------------------------------------------------
+// K-contiguous operands (C = alpha A B^T + beta C, A: M x K and B: N x K both
+// row-major), the common case of every product on this path: BM x BM tiles,
+// 4 waves in a 2 x 2 grid, K advancing 16 doubles per stage. Both row panels
+// go from HBM straight into LDS (global_load_lds, 16 B per lane), double
+// buffered, rows of 8 chunks of 16 B with chunk c of row r stored at
+// c ^ ((r >> 1) & 7). Each MFMA pair takes both values of one 16-byte read: lane
+// group g = lane / 16 feeds k = k0 + 2 g to the first v_mfma_f64_16x16x4f64 and
+// k0 + 2 g + 1 to the second (the order of the k terms is a permutation).
+// Needs lda, ldb even and 16-byte aligned A, B (the host checks).
+typedef __attribute__((address_space(3))) void lds_void_t;
+constexpr int NTK = 16;  // doubles of K per stage
+
+__device__ inline int ntsw(int r) { return (r >> 1) & 7; }
+__device__ inline int ntoff(int r, int c) { return r * 128 + ((c ^ ntsw(r)) << 4); }
+
+template <int BM, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_f64_nt_kernel(
+    int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
+    const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
+    double* __restrict__ work, int64_t k_per_split, int64_t ntiles) {
+  constexpr int BN = BM;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int JPT = BM / 32;  // DMA instructions per wave per operand per stage
+  constexpr int PLANE = BM * 128;
+  __shared__ __attribute__((aligned(16))) char sA0[PLANE];
+  __shared__ __attribute__((aligned(16))) char sB0[PLANE];
+  __shared__ __attribute__((aligned(16))) char sA1[PLANE];
+  __shared__ __attribute__((aligned(16))) char sB1[PLANE];
+
+  constexpr bool PARTIAL = (MODE == GEMM_PARTIAL_LOWER || MODE == kPartialFull);
+  int64_t tm, tn;
+  if (MODE == GEMM_FULL || MODE == kPartialFull || MODE == GEMM_FULL_LOWER) {
+    tm = blockIdx.x;
+    tn = blockIdx.y;
+  } else {
+    tri_decode(blockIdx.x, tm, tn);
+  }
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int split = (MODE == GEMM_PARTIAL_LOWER) ? blockIdx.y : ((MODE == kPartialFull) ? blockIdx.z : 0);
+  const int64_t kbeg = PARTIAL ? (int64_t)split * k_per_split : 0;
+  const int64_t kend = PARTIAL ? min(K, kbeg + k_per_split) : K;
+  // the B panel is the A panel (a diagonal tile of a symmetric product)
+  const bool same = (A == B) && (lda == ldb) && (m0 == n0);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // DMA geometry: wave w, instruction j fills slots ((w JPT + j) * 64 + lane):
+  // row (w JPT + j) * 8 + lane / 8, physical chunk lane % 8 <- logical chunk
+  // (lane % 8) ^ sw(row). Rows beyond M (N) read the last row.
+  auto dma = [&](int64_t k0, char* dA, char* dB) {
+#pragma unroll
+    for (int j = 0; j < JPT; ++j) {
+      const int r = (wave * JPT + j) * 8 + (lane >> 3);
+      const int64_t k = k0 + 2 * ((lane & 7) ^ ntsw(r));
+      const int64_t kk = (k < K) ? k : 0;  // in bounds; k >= kend is masked at the read
+      __builtin_amdgcn_global_load_lds(A + min(m0 + r, M - 1) * lda + kk,
+                                       (lds_void_t*)(dA + (wave * JPT + j) * 1024), 16, 0, 0);
+      if (!same)
+        __builtin_amdgcn_global_load_lds(B + min(n0 + r, N - 1) * ldb + kk,
+                                         (lds_void_t*)(dB + (wave * JPT + j) * 1024), 16, 0, 0);
+    }
+  };
+
+  f64x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  const int g = lane >> 4;
+  auto compute = [&](const char* SA, const char* SB, int64_t k0) {
+    const bool tail = (k0 + NTK > kend);
+#pragma unroll
+    for (int kp = 0; kp < NTK / 8; ++kp) {
+      const int c = kp * 4 + g;  // logical chunk: k = k0 + 2 c, 2 c + 1
+      bool ok0 = true, ok1 = true;
+      if (tail) {
+        ok0 = k0 + 2 * c < kend;
+        ok1 = k0 + 2 * c + 1 < kend;
+      }
+      double2 a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        a[i] = *reinterpret_cast<const double2*>(SA + ntoff(wm * WM + i * 16 + (lane & 15), c));
+        if (!ok0) a[i].x = 0.0;
+        if (!ok1) a[i].y = 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        b[j] = *reinterpret_cast<const double2*>(SB + ntoff(wn * WN + j * 16 + (lane & 15), c));
+        if (!ok0) b[j].x = 0.0;
+        if (!ok1) b[j].y = 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc[i][j], 0, 0, 0);
+    }
+  };
+
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg + NTK - 1) / NTK : 0;
+  if (nk > 0) dma(kbeg, sA0, sB0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int64_t it = 0; it < nk; it += 2) {
+    if (it + 1 < nk) dma(kbeg + (it + 1) * NTK, sA1, sB1);
+    compute(sA0, same ? sA0 : sB0, kbeg + it * NTK);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (it + 1 < nk) {
+      if (it + 2 < nk) dma(kbeg + (it + 2) * NTK, sA0, sB0);
+      compute(sA1, same ? sA1 : sB1, kbeg + (it + 1) * NTK);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+  }
+
+  // epilogue as in gemm_f64_kernel: element v of tile (i, j) is C[row][col]
+  // with row = 16 i + lane / 16 + 4 v, col = 16 j + lane % 16 (wave-relative)
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rl = wm * WM + i * 16 + (lane >> 4) + 4 * v;
+        const int cl = wn * WN + j * 16 + (lane & 15);
+        const double x = acc[i][j][v];
+        if (MODE == GEMM_PARTIAL_LOWER) {
+          work[(((int64_t)split * ntiles + blockIdx.x) * BM + rl) * BN + cl] = x;
+        } else if (MODE == kPartialFull) {
+          const int64_t tile = ((int64_t)split * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+          work[(tile * BM + rl) * BN + cl] = x;
+        } else {
+          const int64_t row = m0 + rl, col = n0 + cl;
+          if (row < M && col < N && (MODE == GEMM_FULL || row >= col)) {
+            double* p = C + row * ldc + col;
+            *p = (beta == 0.0) ? alpha * x : alpha * x + beta * *p;
+          }
+        }
+      }
+}
+
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_reduce_full_kernel(int64_t M, int64_t N, int splits,
                                                                const double* __restrict__ work,
@@ -292,10 +445,71 @@ int64_t lower_tiles(int64_t M, int tile) {
   return t * (t + 1) / 2;
 }
 
+namespace {
+
+template <int BM, int MODE>
+int launch_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+              double* work, int splits) {
+  dim3 grid;
+  int64_t ntiles = 0, kps = K;
+  if (MODE == GEMM_FULL || MODE == GEMM_FULL_LOWER) {
+    grid = dim3((unsigned)cdiv(M, BM), (unsigned)cdiv(N, BM), 1);
+  } else if (MODE == kPartialFull) {
+    kps = round_up(cdiv(K, splits), NTK);
+    grid = dim3((unsigned)cdiv(M, BM), (unsigned)cdiv(N, BM), (unsigned)splits);
+  } else {
+    ntiles = lower_tiles(M, BM);
+    kps = (MODE == GEMM_PARTIAL_LOWER) ? round_up(cdiv(K, splits), NTK) : K;
+    grid = dim3((unsigned)ntiles, (MODE == GEMM_PARTIAL_LOWER) ? (unsigned)splits : 1u, 1);
+  }
+  if (grid.x == 0 || grid.y == 0) return 0;
+  hipLaunchKernelGGL((gemm_f64_nt_kernel<BM, MODE>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
+                     B, ldb, beta, C, ldc, work, kps, ntiles);
+  DNGD_LAUNCH_CHECK();
+  if (MODE == kPartialFull) {
+    dim3 g2(grid.x, grid.y, BM * BM / 256);
+    hipLaunchKernelGGL((gemm_reduce_full_kernel<BM, BM>), g2, dim3(256), 0, s, M, N, splits, work,
+                       alpha, beta, C, ldc);
+    DNGD_LAUNCH_CHECK();
+  }
+  return 0;
+}
+
+bool nt_ok(const double* A, int64_t lda, const double* B, int64_t ldb) {
+  return ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 &&
+         lda % 2 == 0 && ldb % 2 == 0;
+}
+
+}  // namespace
+
 int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
              int64_t K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
              double beta, double* C, int64_t ldc, double* work, int splits) {
   if (M <= 0 || N <= 0) return 0;
+  if (a_kcontig && b_kcontig && nt_ok(A, lda, B, ldb)) {
+    if (mode == GEMM_PARTIAL_LOWER)
+      return launch_nt<128, GEMM_PARTIAL_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                work, splits);
+    if (mode == GEMM_FULL_LOWER)
+      return launch_nt<64, GEMM_FULL_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                            work, 1);
+    if (mode == GEMM_SYRK_LOWER) {
+      if (M >= 1024)
+        return launch_nt<128, GEMM_SYRK_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                               work, 1);
+      return launch_nt<64, GEMM_SYRK_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
+                                            1);
+    }
+    if (splits > 1) {
+      DNGD_REQUIRE(work != nullptr, "gemm_f64: split-K needs a workspace");
+      return launch_nt<64, kPartialFull>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
+                                         splits);
+    }
+    if ((cdiv(M, 128) * cdiv(N, 128)) >= 512)
+      return launch_nt<128, GEMM_FULL>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work, 1);
+    return launch_nt<64, GEMM_FULL>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work, 1);
+  }
   if (mode == GEMM_PARTIAL_LOWER) {
     return launch<128, 128, true, true, GEMM_PARTIAL_LOWER>(s, M, N, K, alpha, A, lda, B, ldb,
                                                              beta, C, ldc, work, splits);
