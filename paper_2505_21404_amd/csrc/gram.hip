@@ -54,19 +54,26 @@ union Chunk {
   bf16x8 h;
 };
 
-// 256 x 256 tile of K per workgroup: 8 waves in a 2 x 4 grid, each wave a
-// 128 x 64 block = 4 x 2 MFMA 32x32 accumulators. K advances 32 elements per
-// step. The FP32 slabs of both row panels are loaded into registers one step
-// ahead (each lane 16 B of a row per load, 8 lanes per 128-byte row segment),
-// split once into bf16 hi (and lo) planes and stored in LDS, double-buffered,
-// so every element is converted once per workgroup and the MFMA fragments
-// are read as ready bf16 (one ds_read_b128 per operand).
-// LDS plane rows are 32 bf16 = 4 chunks of 16 B; chunk c of row r sits at
-// c ^ ((r >> 2) & 3), which makes the 16 rows a fragment read touches per
-// cycle land in 16 distinct 16-byte bank groups.
+// 256 x 256 tile of K per workgroup: 8 waves in a 2 x 4 grid (two per SIMD,
+// so one wave's conversion work runs under the other's MFMAs), each a
+// 128 x 64 block = 4 x 2 MFMA 32x32 accumulators. K advances 16 elements (one
+// MFMA K-slice) per step. The FP32 slabs of both row panels are loaded into
+// registers two steps ahead (each lane 32 B = 8 floats of a row), split once
+// into bf16 hi (and lo) planes and stored in LDS (one 16-byte store per
+// plane), double-buffered, so every element is converted once per workgroup
+// and the MFMA fragments are read as ready bf16 (one ds_read_b128 per
+// operand). The main loop has no branches: B is loaded even on diagonal
+// tiles, and the last, partial step of the K range reads a zero-padded copy
+// of the last columns.
+// LDS plane rows are 16 bf16 = 2 chunks of 16 B; chunk c of row r sits at
+// c ^ ((r >> 3) & 1), which makes the 16 rows a fragment read touches per
+// cycle land in 16 distinct 16-byte bank groups (64 banks).
 constexpr int BT = 256;   // tile edge
-constexpr int BKE = 32;   // K elements per step
+constexpr int BKE = 16;       // K elements per step (one MFMA K-slice)
 constexpr int PCH = BKE / 8;  // 16-byte bf16 chunks per plane row
+constexpr int LPR = BKE / 8;  // loading lanes per row (8 floats each)
+constexpr int NTH = 512;            // threads per workgroup
+constexpr int NQ = BT * LPR / NTH;  // rows per thread per panel and step
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -74,9 +81,14 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 __device__ inline unsigned int pk_bf16(float a, float b) {
   return __builtin_bit_cast(unsigned int, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
-__device__ inline int psw(int r) { return (r >> 2) & 3; }
+__device__ inline int psw(int r) { return (r >> 3) & (PCH - 1); }
 // byte offset of (row r, chunk c) in a plane
 __device__ inline int poff(int r, int c) { return r * (PCH * 16) + ((c ^ psw(r)) << 4); }
+
+// rounding residual of the pair packed in h: (x - hi(x), y - hi(y))
+__device__ inline unsigned int pk_lo(float x, float y, unsigned int h) {
+  return pk_bf16(x - __uint_as_float(h << 16), y - __uint_as_float(h & 0xffff0000u));
+}
 
 template <int PASSES>
 __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
@@ -84,7 +96,8 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
                                                         float* __restrict__ work,
                                                         int64_t k_per_split, int64_t ntiles,
                                                         int64_t per_xcd, int splits,
-                                                        int64_t split0) {
+                                                        int64_t split0,
+                                                        const float* __restrict__ Jt) {
   constexpr bool LO = (PASSES >= 3);
   constexpr bool LOLO = (PASSES == 4);
   constexpr int PLANE = BT * PCH * 16;  // bytes per plane per stage
@@ -100,7 +113,6 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
   const int64_t logical = slt % ntiles;
   int64_t ti, tj;
   tri_decode_g(logical, ti, tj);
-  const bool diag = (ti == tj);
   const int64_t kbeg = split * k_per_split;
   const int64_t kend = min(n, kbeg + k_per_split);
 
@@ -109,59 +121,61 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
   const int wave = t >> 6;
   const int wm = wave >> 2, wn = wave & 3;   // 2 x 4 waves
 
-  // load geometry: load q of a panel covers rows 64 q + 8 wave + lane / 8,
-  // floats 4 (lane % 8) .. +3 of the step. Rows beyond m read row m - 1
+  // load geometry: load q of a panel covers row (256 / LPR) q + t / LPR,
+  // floats 8 (t % LPR) .. +7 of the step. Rows beyond m read row m - 1
   // (their K entries are discarded).
-  const int fch = lane & 7;                 // float4 chunk within the step
-  int lrow[4];
-  const float* pa[4];
-  const float* pb[4];
+  // The last, partial step of the K range (n % BKE columns) is read from Jt,
+  // those columns copied zero-padded to BKE (row stride BKE), so that every
+  // step is the same vector load.
+  const int lch = t % LPR;                  // 8-float chunk within the step
+  int lrow[NQ];
+  const float* pa[NQ];
+  const float* pb[NQ];
+  const float* qa[NQ];
+  const float* qb[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    lrow[q] = 64 * q + 8 * wave + (lane >> 3);
-    pa[q] = J + min(ti * BT + lrow[q], m - 1) * ldJ + 4 * fch;
-    pb[q] = J + min(tj * BT + lrow[q], m - 1) * ldJ + 4 * fch;
+  for (int q = 0; q < NQ; ++q) {
+    lrow[q] = (NTH / LPR) * q + t / LPR;
+    const int64_t ra_ = min(ti * BT + lrow[q], m - 1), rb_ = min(tj * BT + lrow[q], m - 1);
+    pa[q] = J + ra_ * ldJ + kbeg + 8 * lch;
+    pb[q] = J + rb_ * ldJ + kbeg + 8 * lch;
+    qa[q] = Jt + ra_ * BKE + 8 * lch;
+    qb[q] = Jt + rb_ * BKE + 8 * lch;
   }
-  float4 ra[4], rb[4];
-  auto gload = [&](int64_t k0) {
-    const bool full = (k0 + BKE <= kend);
-    const int64_t kk = k0 + 4 * fch;
+  // two register sets of prefetched FP32 slabs: [set][q][half]
+  float4 ra[2][NQ][2], rb[2][NQ][2];
+  // step sidx of this split; B is loaded even on diagonal tiles (same rows,
+  // L2 hits), which keeps the main loop free of branches
+  const int64_t len = kend > kbeg ? kend - kbeg : 0;
+  const int64_t nfull = len / BKE;
+  const int64_t nk = nfull + ((len % BKE) != 0 ? 1 : 0);
+  auto gload = [&](int rs, int64_t sidx) {
+    const bool inJ = sidx < nfull;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (full) {
-        ra[q] = *reinterpret_cast<const float4*>(pa[q] + k0);
-        if (!diag) rb[q] = *reinterpret_cast<const float4*>(pb[q] + k0);
-      } else {
-        float a[4], b[4];
+    for (int q = 0; q < NQ; ++q) {
+      const float* a = inJ ? pa[q] + sidx * BKE : qa[q];
+      const float* b = inJ ? pb[q] + sidx * BKE : qb[q];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool ok = kk + e < kend;
-          a[e] = ok ? pa[q][k0 + e] : 0.0f;
-          b[e] = (ok && !diag) ? pb[q][k0 + e] : 0.0f;
-        }
-        ra[q] = float4{a[0], a[1], a[2], a[3]};
-        rb[q] = float4{b[0], b[1], b[2], b[3]};
+      for (int h = 0; h < 2; ++h) {
+        ra[rs][q][h] = *reinterpret_cast<const float4*>(a + 4 * h);
+        rb[rs][q][h] = *reinterpret_cast<const float4*>(b + 4 * h);
       }
     }
   };
-  // split one float4 into bf16 hi (and lo) and store both halves-of-chunk
-  auto put = [&](char* hp, char* lp, int r, const float4& x) {
-    const unsigned int h0 = pk_bf16(x.x, x.y), h1 = pk_bf16(x.z, x.w);
-    const int off = poff(r, fch >> 1) + 8 * (fch & 1);
-    *reinterpret_cast<uint2*>(hp + off) = uint2{h0, h1};
-    if (LO) {
-      const float e0 = x.x - __uint_as_float(h0 << 16);
-      const float e1 = x.y - __uint_as_float(h0 & 0xffff0000u);
-      const float e2 = x.z - __uint_as_float(h1 << 16);
-      const float e3 = x.w - __uint_as_float(h1 & 0xffff0000u);
-      *reinterpret_cast<uint2*>(lp + off) = uint2{pk_bf16(e0, e1), pk_bf16(e2, e3)};
-    }
+  // split 8 floats into bf16 hi (and lo) and store one 16-byte chunk per plane
+  auto put = [&](char* hp, char* lp, int r, const float4& x, const float4& y) {
+    const uint4 h{pk_bf16(x.x, x.y), pk_bf16(x.z, x.w), pk_bf16(y.x, y.y), pk_bf16(y.z, y.w)};
+    const int off = poff(r, lch);
+    *reinterpret_cast<uint4*>(hp + off) = h;
+    if (LO)
+      *reinterpret_cast<uint4*>(lp + off) = uint4{pk_lo(x.x, x.y, h.x), pk_lo(x.z, x.w, h.y),
+                                                  pk_lo(y.x, y.y, h.z), pk_lo(y.z, y.w, h.w)};
   };
-  auto stage_store = [&](int st) {
+  auto stage_store = [&](int rs, int st) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      put(lds[st][0], LO ? lds[st][2] : nullptr, lrow[q], ra[q]);
-      if (!diag) put(lds[st][1], LO ? lds[st][3] : nullptr, lrow[q], rb[q]);
+    for (int q = 0; q < NQ; ++q) {
+      put(lds[st][0], LO ? lds[st][2] : nullptr, lrow[q], ra[rs][q][0], ra[rs][q][1]);
+      put(lds[st][1], LO ? lds[st][3] : nullptr, lrow[q], rb[rs][q][0], rb[rs][q][1]);
     }
   };
 
@@ -178,61 +192,105 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
     c.u = *reinterpret_cast<const uint4*>(plane + poff(r, 2 * sl + (lane >> 5)));
     return c.h;
   };
+  // products of one stage; each accumulator is revisited only after the 15
+  // others, so back-to-back MFMAs never wait on each other
   auto compute = [&](int st) {
     const char* Ah = lds[st][0];
-    const char* Bh = diag ? lds[st][0] : lds[st][1];
+    const char* Bh = lds[st][1];
     const char* Al = LO ? lds[st][2] : nullptr;
-    const char* Bl = LO ? (diag ? lds[st][2] : lds[st][3]) : nullptr;
+    const char* Bl = LO ? lds[st][3] : nullptr;
 #pragma unroll
     for (int sl = 0; sl < BKE / 16; ++sl) {
-      bf16x8 bh[2], bl[2];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int r = wn * 64 + j * 32 + (lane & 31);
-        bh[j] = frag(Bh, r, sl);
-        if (LO) bl[j] = frag(Bl, r, sl);
-      }
+      bf16x8 ah[4], al[4], bh[2], bl[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = wm * 128 + i * 32 + (lane & 31);
-        const bf16x8 ah = frag(Ah, r, sl);
-        bf16x8 al;
-        if (LO) al = frag(Al, r, sl);
+        const int ra_ = wm * 128 + i * 32 + (lane & 31);
+        ah[i] = frag(Ah, ra_, sl);
+        if (LO) al[i] = frag(Al, ra_, sl);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int rb_ = wn * 64 + j * 32 + (lane & 31);
+        bh[j] = frag(Bh, rb_, sl);
+        if (LO) bl[j] = frag(Bl, rb_, sl);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-        if (LO) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      if (LO) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-        }
-        if (LOLO) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+      if (LOLO) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl[j], acc[i][j], 0, 0, 0);
-        }
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bl[j], acc[i][j], 0, 0, 0);
       }
     }
   };
 
-  const int64_t nk = (kend > kbeg) ? (kend - kbeg + BKE - 1) / BKE : 0;
+  // The steps are software-pipelined two deep: while step it is multiplied
+  // from LDS stage it%2, step it+1 (loaded one step earlier, so its data has
+  // arrived) is converted into the other stage and step it+2 is in flight.
+  // The scheduling hints spread the conversion and its LDS stores over the
+  // MFMAs of the step.
+  constexpr int NMF = 8 * (1 + (LO ? 2 : 0) + (LOLO ? 1 : 0));  // MFMAs per step
+  constexpr int NDW = 2 * NQ * (LO ? 2 : 1);                   // LDS stores per step
+  auto hints = [&]() {
+#pragma unroll
+    for (int i = 0; i < NMF; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two VALU
+      if (i % (NMF / NDW) == NMF / NDW - 1)
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // one LDS store
+    }
+  };
   if (nk > 0) {
-    gload(kbeg);
-    stage_store(0);
-  }
-  __syncthreads();
-  for (int64_t it = 0; it < nk; ++it) {
-    const int st = (int)(it & 1);
-    if (it + 1 < nk) gload(kbeg + (it + 1) * BKE);
-    compute(st);
-    if (it + 1 < nk) stage_store(st ^ 1);
+    int64_t it = 0;
+    gload(0, 0);
+    if (nk > 1) gload(1, 1);
+    stage_store(0, 0);
     __syncthreads();
+    // invariant: stage 0 holds step it, register set 1 holds step it+1
+    for (; it + 3 < nk; it += 2) {
+      gload(0, it + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0);
+      stage_store(1, 1);
+      hints();
+      __syncthreads();
+      gload(1, it + 3);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1);
+      stage_store(0, 0);
+      hints();
+      __syncthreads();
+    }
+    // drain the last one to three steps (stage st holds step it, register
+    // set 1 holds step it+1)
+    int st = 0;
+    for (; it < nk; ++it) {
+      compute(st);
+      if (it + 1 < nk) stage_store(1, st ^ 1);
+      __syncthreads();
+      if (it + 2 < nk) gload(1, it + 2);
+      st ^= 1;
+    }
   }
 
-  // accumulator v of tile (i, j): row 8 (v/4) + 4 (lane/32) + v%4, col lane%32
+  // accumulator v of block (i, j): row 8 (v/4) + 4 (lane/32) + v%4, col lane%32
   float* out = work + (lsplit * ntiles + logical) * (BT * BT);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -244,6 +302,15 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
         const int cl = wn * 64 + j * 32 + (lane & 31);
         out[rl * BT + cl] = acc[i][j][v];
       }
+}
+
+// Jt (m x BKE, row-major) = columns n0 .. n-1 of J, zero-padded to BKE columns.
+__global__ void gram_tail_kernel(int64_t m, int64_t n, int64_t n0, const float* __restrict__ J,
+                                 int64_t ldJ, float* __restrict__ Jt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m * BKE) return;
+  const int64_t r = i / BKE, c = n0 + i % BKE;
+  Jt[i] = c < n ? J[r * ldJ + c] : 0.0f;
 }
 
 // K (lower triangle) = [K +] sum of the partial tiles in split order [+ lambda I]:
@@ -304,7 +371,9 @@ size_t gram_workspace_bytes(int64_t m, int64_t n, int j_dtype, int passes, int* 
   const int64_t nt = lower_tiles(m, BT);
   const int64_t s = choose_splits_bf16(nt, n);
   if (splits_out) *splits_out = (int)s;
-  return (size_t)std::min<int64_t>(s, kSplitBatch) * (size_t)nt * BT * BT * sizeof(float);
+  // partial tiles, then the zero-padded last columns (m x BKE)
+  return (size_t)std::min<int64_t>(s, kSplitBatch) * (size_t)nt * BT * BT * sizeof(float) +
+         (size_t)round_up(m * BKE * (int64_t)sizeof(float), 256);
 }
 
 int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
@@ -313,8 +382,23 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
   int splits = 1;
   const size_t need = gram_workspace_bytes(m, n, j_dtype, passes, &splits);
   DNGD_REQUIRE(work_bytes >= need, "gram: workspace too small (%zu < %zu)", work_bytes, need);
+  const bool bf16_path = !(j_dtype == 0 || passes == kGramF64);
+  float* Jt = nullptr;
+  if (bf16_path) {
+    DNGD_REQUIRE(ldJ % 4 == 0 && reinterpret_cast<uintptr_t>(J) % 16 == 0,
+                 "gram: FP32 J needs ldJ %% 4 == 0 and a 16-byte aligned base");
+    const int64_t nt = lower_tiles(m, BT);
+    Jt = reinterpret_cast<float*>(static_cast<char*>(work) +
+                                  (size_t)std::min<int64_t>(splits, kSplitBatch) * nt * BT * BT *
+                                      sizeof(float));
+    if (n % BKE != 0) {
+      hipLaunchKernelGGL(gram_tail_kernel, dim3((unsigned)cdiv(m * BKE, 256)), dim3(256), 0, st,
+                         m, n, n - n % BKE, static_cast<const float*>(J), ldJ, Jt);
+      DNGD_LAUNCH_CHECK();
+    }
+  }
   if (ev_begin) DNGD_HIP(hipEventRecord(ev_begin, st));
-  if (j_dtype == 0 || passes == kGramF64) {
+  if (!bf16_path) {
     const int64_t nt = lower_tiles(m, GT);
     int rc = (j_dtype == 0)
                  ? gemm_f64(st, GEMM_PARTIAL_LOWER, true, true, m, m, n, 1.0,
@@ -330,7 +414,6 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
     DNGD_LAUNCH_CHECK();
     return 0;
   }
-  DNGD_REQUIRE(ldJ % 4 == 0, "gram: FP32 J needs ldJ %% 4 == 0");
   DNGD_REQUIRE(passes == 1 || passes == 3 || passes == 4, "gram: passes must be 1, 3, 4 or %d",
                kGramF64);
   const int64_t nt = lower_tiles(m, BT);
@@ -344,13 +427,13 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
     const float* Jf = static_cast<const float*>(J);
     if (passes == 4)
       hipLaunchKernelGGL(gram_bf16_kernel<4>, grid, dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt,
-                         per_xcd, sb, s0);
+                         per_xcd, sb, s0, Jt);
     else if (passes == 3)
       hipLaunchKernelGGL(gram_bf16_kernel<3>, grid, dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt,
-                         per_xcd, sb, s0);
+                         per_xcd, sb, s0, Jt);
     else
       hipLaunchKernelGGL(gram_bf16_kernel<1>, grid, dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt,
-                         per_xcd, sb, s0);
+                         per_xcd, sb, s0, Jt);
     DNGD_LAUNCH_CHECK();
     if (ev_end && s0 + sb >= splits) DNGD_HIP(hipEventRecord(ev_end, st));
     hipLaunchKernelGGL((gram_reduce_kernel<float, BT>), dim3((unsigned)nt, BT * BT / 1024),
