@@ -7,7 +7,7 @@
 //                 in LDS (8-column groups: a parallel update, then an 8-step
 //                 substitution inside one wave), workgroup 0 writes L11 and
 //                 the reciprocal pivots, the others solve their rows of
-//                 L21 = A21 L11^-T the same way.
+//                 L21 = A21 L11^-T in the same groups, alongside.
 //   update        A22 -= L21 L21^T on the FP64 matrix cores (lower tiles).
 // A non-positive or non-finite pivot records its 1-based column in *info
 // (first failure wins) and poisons the rest of the factor with NaN.
@@ -35,27 +35,38 @@ constexpr int GW = 8;  // columns per group
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-// S[i][c0 + j] -= sum_{k < c0} S[i][k] * Lr[c0 + j][k] for the group's 8
-// columns, rows i in [r_lo, 64), on the FP64 matrix cores: wave w owns rows
-// 16 w .. 16 w + 15 (a 16 x 16 tile whose columns 8..15 are padding) and
-// steps k by 4 (v_mfma_f64_16x16x4f64: A lane l = (row l % 16, k l / 16),
+// For the group's 8 columns c0 .. c0+7, subtract the finished columns k < c0:
+//   Ld[i][c0 + j] -= sum_k Ld[i][k] Ld[c0 + j][k]   (diagonal block, rows i >= c0)
+//   X[i][c0 + j]  -= sum_k X[i][k]  Ld[c0 + j][k]   (this workgroup's L21 rows)
+// on the FP64 matrix cores. Wave w owns rows 16 w .. 16 w + 15 (a 16 x 16
+// tile whose columns 8..15 are padding); k advances by 8 as two independent
+// v_mfma_f64_16x16x4f64 chains per matrix (A lane l = (row l % 16, k l / 16),
 // B lane l = (k l / 16, col l % 16), D element v of lane l = (row l / 16 + 4 v,
-// col l % 16)).
-__device__ inline void group_update(double (*S)[NB + 1], const double (*Lr)[NB + 1], int c0,
-                                    int r_lo) {
+// col l % 16)), so the dependent chains are a quarter of c0 / 4 long.
+__device__ inline void group_update(double (*Ld)[NB + 1], double (*X)[NB + 1], int c0,
+                                    bool has_x) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ar = 16 * wave + (lane & 15), kq = lane >> 4, bc = lane & 15;
-  f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < c0; k0 += 4) {
-    const double a = S[ar][k0 + kq];
-    const double b = (bc < GW) ? Lr[c0 + bc][k0 + kq] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  const bool has_d = 16 * wave + 15 >= c0;  // this wave holds diagonal rows still open
+  f64x4_t d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0, x0 = d0, x1 = d0;
+  for (int k0 = 0; k0 < c0; k0 += 8) {
+    const double b0 = (bc < GW) ? Ld[c0 + bc][k0 + kq] : 0.0;
+    const double b1 = (bc < GW) ? Ld[c0 + bc][k0 + 4 + kq] : 0.0;
+    if (has_d) {
+      d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ld[ar][k0 + kq], b0, d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ld[ar][k0 + 4 + kq], b1, d1, 0, 0, 0);
+    }
+    if (has_x) {
+      x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(X[ar][k0 + kq], b0, x0, 0, 0, 0);
+      x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(X[ar][k0 + 4 + kq], b1, x1, 0, 0, 0);
+    }
   }
   if (bc < GW) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * wave + kq + 4 * v;
-      if (r >= r_lo) S[r][c0 + bc] -= acc[v];
+      if (has_d && r >= c0) Ld[r][c0 + bc] -= d0[v] + d1[v];
+      if (has_x) X[r][c0 + bc] -= x0[v] + x1[v];
     }
   }
 }
@@ -90,7 +101,8 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
                                                           double* __restrict__ dinv,
                                                           double* __restrict__ lbuf) {
   // Ld: the diagonal block, factored in place (lower part). X: this
-  // workgroup's 64 panel rows below it (workgroups >= 1).
+  // workgroup's 64 panel rows below it (workgroups >= 1), solved
+  // X L11^T = A21 alongside, group by group.
   __shared__ double Ld[NB][NB + 1];
   __shared__ double X[NB][NB + 1];
   __shared__ double rinv[NB];
@@ -98,9 +110,12 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int nb = (int)min<int64_t>(NB, m - j0);
+  const bool has_x = blockIdx.x > 0;
+  const int64_t r0 = j0 + (int64_t)blockIdx.x * NB;
   if (t == 0) sbad = -1;
 
-  // ---- load the diagonal block, coalesced (identity padding beyond m)
+  // ---- load the diagonal block (identity padding beyond m) and this
+  //      workgroup's rows of the panel, coalesced
   {
     double v[16];
 #pragma unroll
@@ -113,26 +128,47 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
       const int e = q * 256 + t;
       Ld[e / NB][e % NB] = v[q];
     }
+    if (has_x) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = q * 256 + t, i = e / NB, k = e % NB;
+        v[q] = (r0 + i < m && k < nb) ? K[(r0 + i) * ldK + j0 + k] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = q * 256 + t;
+        X[e / NB][e % NB] = v[q];
+      }
+    }
   }
   __syncthreads();
-  // ---- factor the diagonal block:  L_jj = sqrt(a_jj - sum_k L_jk^2),
-  //      L_ij = (a_ij - sum_k L_ik L_jk) / L_jj
+  // ---- per group: the update, then the substitution in wave 0:
+  //      L_jj = sqrt(a_jj - sum_k L_jk^2),  L_ij = (a_ij - sum_k L_ik L_jk) / L_jj
+  //      for the diagonal block's rows i and this workgroup's rows alike
   for (int c0 = 0; c0 < NB; c0 += GW) {
-    if (c0 > 0) group_update(Ld, Ld, c0, c0);
+    if (c0 > 0) group_update(Ld, X, c0, has_x);
     __syncthreads();
     if (wave == 0) {
-      // lane i holds row i of the group in registers; row c0 + j of L (the
-      // multipliers of step j) is read from lane c0 + j
+      // lane i holds row i of the group (diagonal block: x, panel rows: y)
+      // in registers; row c0 + j of L (the multipliers of step j) is read
+      // from lane c0 + j of x
       const int i = lane;
-      double x[GW];
+      double x[GW], y[GW];
 #pragma unroll
-      for (int j = 0; j < GW; ++j) x[j] = Ld[i][c0 + j];
+      for (int j = 0; j < GW; ++j) {
+        x[j] = Ld[i][c0 + j];
+        y[j] = has_x ? X[i][c0 + j] : 0.0;
+      }
 #pragma unroll
       for (int j = 0; j < GW; ++j) {
         const int pj = c0 + j;
-        double sij = x[j];
+        double sij = x[j], yij = y[j];
 #pragma unroll
-        for (int k = 0; k < j; ++k) sij -= x[k] * lane_value(x[k], pj);
+        for (int k = 0; k < j; ++k) {
+          const double l = lane_value(x[k], pj);  // L[pj][c0 + k], uniform
+          sij -= x[k] * l;
+          yij -= y[k] * l;
+        }
         const double d = lane_value(sij, pj);  // the pivot, uniform
         double inv, ljj;
         if (d > 0.0 && __builtin_isfinite(d)) {
@@ -143,16 +179,19 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
           inv = ljj = __builtin_nan("");
         }
         x[j] = (i == pj) ? ljj : ((i > pj) ? sij * inv : x[j]);
+        y[j] = yij * inv;
         if (i == 0) rinv[pj] = inv;
       }
 #pragma unroll
-      for (int j = 0; j < GW; ++j)
+      for (int j = 0; j < GW; ++j) {
         if (i >= c0 + j) Ld[i][c0 + j] = x[j];
+        if (has_x) X[i][c0 + j] = y[j];
+      }
     }
     __syncthreads();
   }
 
-  if (blockIdx.x == 0) {
+  if (!has_x) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int e = q * 256 + t;
@@ -164,43 +203,6 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
       atomicCAS(p, 0ull, (unsigned long long)(j0 + sbad + 1));
     }
     return;
-  }
-
-  // ---- L21 rows: X L11^T = A21, by the same 8-column groups
-  const int64_t r0 = j0 + (int64_t)blockIdx.x * NB;
-  {
-    double v[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = q * 256 + t, i = e / NB, k = e % NB;
-      v[q] = (r0 + i < m && k < nb) ? K[(r0 + i) * ldK + j0 + k] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = q * 256 + t;
-      X[e / NB][e % NB] = v[q];
-    }
-  }
-  __syncthreads();
-  for (int c0 = 0; c0 < NB; c0 += GW) {
-    if (c0 > 0) group_update(X, Ld, c0, 0);
-    __syncthreads();
-    if (wave == 0) {
-      const int i = lane;
-      double x[GW];
-#pragma unroll
-      for (int j = 0; j < GW; ++j) x[j] = X[i][c0 + j];
-#pragma unroll
-      for (int j = 0; j < GW; ++j) {
-        double v = x[j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) v -= x[k] * Ld[c0 + j][c0 + k];
-        x[j] = v * rinv[c0 + j];
-      }
-#pragma unroll
-      for (int j = 0; j < GW; ++j) X[i][c0 + j] = x[j];
-    }
-    __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
