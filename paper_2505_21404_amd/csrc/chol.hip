@@ -112,7 +112,6 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
   const int nb = (int)min<int64_t>(NB, m - j0);
   const bool has_x = blockIdx.x > 0;
   const int64_t r0 = j0 + (int64_t)blockIdx.x * NB;
-  if (t == 0) sbad = -1;
 
   // ---- load the diagonal block (identity padding beyond m) and this
   //      workgroup's rows of the panel, coalesced
@@ -145,6 +144,8 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
   // ---- per group: the update, then the substitution in wave 0:
   //      L_jj = sqrt(a_jj - sum_k L_jk^2),  L_ij = (a_ij - sum_k L_ik L_jk) / L_jj
   //      for the diagonal block's rows i and this workgroup's rows alike
+  int bad = -1;  // wave 0: first failing pivot column of the block (uniform)
+#pragma unroll
   for (int c0 = 0; c0 < NB; c0 += GW) {
     if (c0 > 0) group_update(Ld, X, c0, has_x);
     __syncthreads();
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
           inv = rsqrt_f64(d);
           ljj = d * inv;
         } else {
-          if (i == 0 && sbad < 0) sbad = pj;
+          if (bad < 0) bad = pj;
           inv = ljj = __builtin_nan("");
         }
         x[j] = (i == pj) ? ljj : ((i > pj) ? sij * inv : x[j]);
@@ -191,6 +192,8 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
     __syncthreads();
   }
 
+  if (wave == 0 && lane == 0) sbad = bad;
+  __syncthreads();
   if (!has_x) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
