@@ -468,8 +468,10 @@ int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo
     if (r2 > 0) {
       DNGD_HIP(hipEventRecord(ev_panel, s));
       DNGD_HIP(hipStreamWaitEvent(side, ev_panel, 0));
+      // at most one of its workgroups per CU, so the panels and updates of
+      // the next block column on `s` find room on every CU
       rc = gemm_f64(side, GEMM_SYRK_LOWER, true, true, r2, r2, kb, -1.0, L21 + nxt * ldK, ldK,
-                    L21 + nxt * ldK, ldK, 1.0, A22 + nxt * ldK + nxt, ldK);
+                    L21 + nxt * ldK, ldK, 1.0, A22 + nxt * ldK + nxt, ldK, nullptr, 1, true);
       if (rc) return rc;
       DNGD_HIP(hipEventRecord(ev_trail, side));
       side_busy = true;

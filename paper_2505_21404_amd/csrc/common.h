@@ -97,9 +97,13 @@ enum GemmMode {
 // C[m*ldc + n] = alpha * sum_k opA[m][k] opB[n][k] + beta * C  (GEMM_FULL)
 // GEMM_SYRK_LOWER: only tiles/elements with m >= n (square M == N).
 // GEMM_PARTIAL_LOWER: lower tiles, split-K; tile partials to `work`.
+// one_per_cu (K-contiguous SYRK): the kernel reserves enough LDS that at most one of
+// its workgroups is resident per CU, which leaves room on every CU for the
+// workgroups of latency-bound kernels running beside it on another stream.
 int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
              int64_t K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-             double beta, double* C, int64_t ldc, double* work = nullptr, int splits = 1);
+             double beta, double* C, int64_t ldc, double* work = nullptr, int splits = 1,
+             bool one_per_cu = false);
 
 // Batched GEMM_FULL: matrix z = (z / n_inner, z % n_inner) starts at
 // A + zo * a_out + zi * a_in (likewise B, C); n_outer * n_inner matrices.

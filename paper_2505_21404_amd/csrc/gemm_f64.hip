@@ -447,10 +447,18 @@ int64_t lower_tiles(int64_t M, int tile) {
 
 namespace {
 
+// LDS of one CU; a launch that asks for more than half of it (with its static
+// arrays) gets at most one workgroup per CU
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr size_t kOnePerCuLds = 90 * 1024;
+
 template <int BM, int MODE>
 int launch_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-              double* work, int splits) {
+              double* work, int splits, bool one_per_cu = false) {
+  static_assert(2 * kOnePerCuLds > kLdsPerCu, "one workgroup per CU");
+  const size_t static_lds = 4 * (size_t)BM * 128;
+  const size_t dyn = one_per_cu && kOnePerCuLds > static_lds ? kOnePerCuLds - static_lds : 0;
   dim3 grid;
   int64_t ntiles = 0, kps = K;
   if (MODE == GEMM_FULL || MODE == GEMM_FULL_LOWER) {
@@ -464,8 +472,8 @@ int launch_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, cons
     grid = dim3((unsigned)ntiles, (MODE == GEMM_PARTIAL_LOWER) ? (unsigned)splits : 1u, 1);
   }
   if (grid.x == 0 || grid.y == 0) return 0;
-  hipLaunchKernelGGL((gemm_f64_nt_kernel<BM, MODE>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
-                     B, ldb, beta, C, ldc, work, kps, ntiles);
+  hipLaunchKernelGGL((gemm_f64_nt_kernel<BM, MODE>), grid, dim3(256), (unsigned)dyn, s, M, N, K,
+                     alpha, A, lda, B, ldb, beta, C, ldc, work, kps, ntiles);
   DNGD_LAUNCH_CHECK();
   if (MODE == kPartialFull) {
     dim3 g2(grid.x, grid.y, BM * BM / 256);
@@ -485,7 +493,7 @@ bool nt_ok(const double* A, int64_t lda, const double* B, int64_t ldb) {
 
 int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
              int64_t K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-             double beta, double* C, int64_t ldc, double* work, int splits) {
+             double beta, double* C, int64_t ldc, double* work, int splits, bool one_per_cu) {
   if (M <= 0 || N <= 0) return 0;
   if (a_kcontig && b_kcontig && nt_ok(A, lda, B, ldb)) {
     if (mode == GEMM_PARTIAL_LOWER)
@@ -497,9 +505,9 @@ int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64
     if (mode == GEMM_SYRK_LOWER) {
       if (M >= 1024)
         return launch_nt<128, GEMM_SYRK_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                                               work, 1);
+                                               work, 1, one_per_cu);
       return launch_nt<64, GEMM_SYRK_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
-                                            1);
+                                            1, one_per_cu);
     }
     if (splits > 1) {
       DNGD_REQUIRE(work != nullptr, "gemm_f64: split-K needs a workspace");
