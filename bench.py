@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--pcg-tol", type=float, default=1e-6)
     ap.add_argument("--pcg-iters", type=int, default=0,
                     help="with --pcg: also run this many optimiser iterations (PCG steps + line search)")
+    ap.add_argument("--pcg-ga", action="store_true",
+                    help="with --pcg: geodesic acceleration (second PCG solve for f_vv)")
     return ap.parse_args()
 
 
@@ -164,7 +166,7 @@ def progress(msg):
 
 
 def pcg_run(a, torch):
-    """One matrix-free Nystrom-PCG step (no GA) on the large 5-D Poisson
+    """One matrix-free Nystrom-PCG step (GA with --pcg-ga) on the large 5-D Poisson
     workload: n = 12.6M parameters, m = 50,000 residuals (45,000 interior,
     5,000 boundary), FP64 kernel-vector products."""
     import numpy as np
@@ -178,7 +180,7 @@ def pcg_run(a, torch):
     lam = min(L0, W.LAMBDA_CAP[3])
     I = torch.tensor(W.landmarks(p.m, a.pcg_landmarks, 0), device="cuda")
     alpha = torch.empty(prob.m, dtype=torch.float64, device="cuda")
-    opts = D.step_opts(solver=D.PCG, ga=False, landmarks=I, pcg_tol=a.pcg_tol,
+    opts = D.step_opts(solver=D.PCG, ga=a.pcg_ga, landmarks=I, pcg_tol=a.pcg_tol,
                        pcg_maxit=a.pcg_maxit, alpha_out=alpha)
     progress(f"PCG step: n={prob.n} m={prob.m} landmarks={a.pcg_landmarks}")
     t0 = time.perf_counter()
@@ -195,7 +197,8 @@ def pcg_run(a, torch):
     out = {
         "metric": "D-NGD PCG step (matrix-free, Nystrom preconditioner)", "unit": "s",
         "value": wall, "higher_is_better": False, "n_gpus": 1,
-        "config": {"workload": "poisson5d_mlp5-2048x4-1_m50000_pcg", "n": prob.n, "m": prob.m,
+        "config": {"workload": "poisson5d_mlp5-2048x4-1_m50000_pcg" + ("_ga" if a.pcg_ga else ""),
+                   "n": prob.n, "m": prob.m,
                    "landmarks": a.pcg_landmarks, "tol": a.pcg_tol, "maxit": a.pcg_maxit,
                    "lambda": lam},
         "pcg_iterations": st.pcg_iterations, "pcg_converged": bool(st.pcg_converged),
@@ -204,18 +207,24 @@ def pcg_run(a, torch):
         "ms_pcg_and_recovery": st.ms_solve_v, "ms_per_pcg_iteration": st.ms_solve_v / its,
         "ms_kvp_alone_incl_forward": kvp_ms, "dtheta_norm": float(dth.norm()),
     }
+    if a.pcg_ga:
+        out.update({"ms_fvv": st.ms_fvv, "ms_ga_pcg_and_recovery": st.ms_solve_a,
+                    "pcg_iterations_ga": st.pcg_iterations_ga, "ga_accepted": st.ga_accepted,
+                    "vnorm": st.vnorm, "anorm": st.anorm})
     if a.pcg_iters > 0:
         # optimiser iterations: fresh landmarks per step (seed + 3 + k), damping rule
         etas = [2.0 ** -k for k in range(31)]
         hist = []
         for k in range(a.pcg_iters):
             Ik = torch.tensor(W.landmarks(p.m, a.pcg_landmarks, 0, step=k), device="cuda")
-            ok = D.step_opts(solver=D.PCG, ga=False, landmarks=Ik, pcg_tol=a.pcg_tol,
+            ok = D.step_opts(solver=D.PCG, ga=a.pcg_ga, landmarks=Ik, pcg_tol=a.pcg_tol,
                              pcg_maxit=a.pcg_maxit)
             t0 = time.perf_counter()
             it = prob.iterate(th, etas, lam_cap=W.LAMBDA_CAP[3], opts=ok)
             hist.append({"loss": it.loss, "lam": it.lam, "eta": it.eta,
                          "pcg_iterations": it.step.pcg_iterations,
+                         "pcg_iterations_ga": it.step.pcg_iterations_ga,
+                         "ga_accepted": it.step.ga_accepted,
                          "pcg_rel_residual": it.step.pcg_rel_residual,
                          "s_step": it.step.ms_total / 1e3, "s_line_search": it.ms_line_search / 1e3,
                          "s_iteration": time.perf_counter() - t0})

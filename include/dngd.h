@@ -105,7 +105,7 @@ typedef struct {
                                refinement sweep of the v solve exceeds this (default 1e-5) */
   /* optional device outputs (NULL = not written): the dual solution
      alpha = (K + lambda I)^{-1} r (m FP64; dense and PCG) and f_vv (m FP64,
-     dense step with GA only) */
+     step with GA, dense and PCG) */
   double* alpha_out;
   double* fvv_out;
 } dngd_step_opts;
@@ -125,7 +125,7 @@ typedef struct {
   double pcg_rel_residual;    /* PCG: final recursive ||r|| / ||b|| */
   double ms_gram_kernel;      /* the Gram contraction kernel alone (HIP events on `stream`) */
   int32_t gram_attempts;      /* Gram + factorisation attempts (> 1 after an escalation) */
-  int32_t reserved1;
+  int32_t pcg_iterations_ga;  /* PCG with GA: iterations of the second (f_vv) solve */
 } dngd_step_stats;
 
 const char* dngd_last_error(void);
@@ -215,7 +215,10 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda,
 /* One D-NGD step (dense dual solver with geodesic acceleration, Section 4.1,
  * or the PCG step of Section 4.2): dtheta = -J^T (J J^T + lambda I)^{-1} r,
  * plus a/2 with a = -J^T (J J^T + lambda I)^{-1} f_vv when accepted
- * (2 ||a|| <= 0.5 ||v||). theta, dtheta: device n FP64. stats: host or NULL.
+ * (2 ||a|| <= 0.5 ||v||). With the PCG solver, the f_vv system is solved by a
+ * second PCG run with the same Nystrom preconditioner (Remark 3.5); if that run
+ * does not converge the correction is rejected (dtheta = v, ga_accepted = 0).
+ * theta, dtheta: device n FP64. stats: host or NULL.
  * Synchronises `stream` before returning. */
 int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_step_opts* opts,
               double* dtheta, dngd_step_stats* stats, void* stream);

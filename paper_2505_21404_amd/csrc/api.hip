@@ -888,7 +888,8 @@ int read_scalars(double* host, const double* dev, int n, hipStream_t s) {
 }
 
 // PCG (appendix algorithm) on (J J^T + lam I) y = b from y = 0.
-// Work vectors: y -> x (output); r = v.s; z = v.tmpm; p = v.beta; Ap = v.fvv.
+// Work vectors: y -> x (output); r = v.s; z = v.tmpm; p = v.rownorm2; Ap = v.alpha;
+// the kernel-vector product uses v.t. b is read only before the first iteration.
 int pcg_solve(dngd_problem* h, const double* theta, const Precond& P, const StepVecs& v,
               const Small& sm, const double* b, double* x, double tol, int64_t maxit,
               int* iters, double* relres, hipStream_t s) {
@@ -1026,17 +1027,49 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
       rc = copy(s, g.m, v.fvv, o.alpha_out);
       if (rc) return rc;
     }
-    // dtheta = -J^T alpha (matrix-free reverse pass)
-    rc = vjp(h, theta, v.fvv, v.v, s);
+    // v = -J^T alpha (matrix-free reverse pass); dtheta = v unless GA is accepted
+    rc = vjp(h, theta, v.fvv, v.t, s);
+    if (!rc) rc = fill(s, g.n, 0.0, v.v);
+    if (!rc) rc = axpy(s, g.n, -1.0, v.t, v.v);
+    if (!rc) rc = copy(s, g.n, v.v, dtheta);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[3], s));
-    rc = fill(s, g.n, 0.0, dtheta);
-    if (!rc) rc = axpy(s, g.n, -1.0, v.v, dtheta);
-    if (!rc) rc = sumsq(s, g.n, dtheta, v.scal + 8, v.red);
-    if (rc) return rc;
+    // GA (Section 3.2, with the same preconditioner, Remark 3.5): f_vv along v,
+    // beta from a second PCG solve, a = -J^T beta, combined as in the dense path
+    int its_ga = 0, pst_ga = DNGD_OK;
+    double rel_ga = 0.0;
+    if (o.ga) {
+      rc = tangent(h, theta, v.v, 2, v.fvv, s);
+      if (!rc && o.fvv_out) rc = copy(s, g.m, v.fvv, o.fvv_out);
+      if (rc) return rc;
+      DNGD_HIP(hipEventRecord(h->ev[5], s));
+      pst_ga = pcg_solve(h, theta, P, v, sm, v.fvv, v.beta, o.pcg_tol, o.pcg_maxit, &its_ga,
+                         &rel_ga, s);
+      if (pst_ga < 0 && pst_ga != DNGD_ENOCONV) return pst_ga;
+      if (pst_ga == DNGD_OK) {
+        rc = vjp(h, theta, v.beta, v.t, s);
+        if (!rc) rc = fill(s, g.n, 0.0, v.a);
+        if (!rc) rc = axpy(s, g.n, -1.0, v.t, v.a);
+        if (!rc) rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
+        if (!rc) rc = sumsq(s, g.n, v.a, v.scal + 1, v.red);
+        if (!rc) rc = ga_combine(s, g.n, v.v, v.a, v.scal, o.eps_norm, dtheta, sm.ga_flag);
+        if (rc) return rc;
+      }
+    } else {
+      DNGD_HIP(hipEventRecord(h->ev[5], s));
+    }
+    if (!o.ga || pst_ga != DNGD_OK) {
+      // no correction: dtheta = v as copied above
+      rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
+      if (!rc) rc = fill(s, 1, 0.0, v.scal + 1);
+      if (rc) return rc;
+    }
     DNGD_HIP(hipEventRecord(h->ev[7], s));
-    double vn2 = 0;
-    DNGD_HIP(hipMemcpyAsync(&vn2, v.scal + 8, 8, hipMemcpyDeviceToHost, s));
+    double nv[2] = {0, 0};
+    int gaf = 0;
+    DNGD_HIP(hipMemcpyAsync(nv, v.scal, sizeof(nv), hipMemcpyDeviceToHost, s));
+    if (o.ga && pst_ga == DNGD_OK)
+      DNGD_HIP(hipMemcpyAsync(&gaf, sm.ga_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     DNGD_HIP(hipStreamSynchronize(s));
     float ms = 0;
     hipEventElapsedTime(&ms, h->ev[0], h->ev[7]);
@@ -1047,11 +1080,24 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     st.ms_factor = ms;
     hipEventElapsedTime(&ms, h->ev[2], h->ev[3]);
     st.ms_solve_v = ms;
-    st.vnorm = std::sqrt(vn2);
+    if (o.ga) {
+      hipEventElapsedTime(&ms, h->ev[3], h->ev[5]);
+      st.ms_fvv = ms;
+      hipEventElapsedTime(&ms, h->ev[5], h->ev[7]);
+      st.ms_solve_a = ms;
+    }
+    st.vnorm = std::sqrt(nv[0]);
+    st.anorm = std::sqrt(nv[1]);
+    st.ga_accepted = (o.ga && pst_ga == DNGD_OK) ? gaf : 0;
     st.pcg_iterations = its;
+    st.pcg_iterations_ga = its_ga;
     st.pcg_converged = (pst == DNGD_OK);
     st.pcg_rel_residual = rel;
     if (stats) *stats = st;
+    if (pst == DNGD_OK && (!std::isfinite(st.vnorm) || !std::isfinite(st.anorm))) {
+      set_error("non-finite step");
+      return DNGD_ENAN;
+    }
     return pst;
   }
 

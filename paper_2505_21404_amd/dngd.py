@@ -58,7 +58,7 @@ class StepStats(C.Structure):
                 ("pcg_converged", C.c_int32), ("ir_residual", C.c_double * 8),
                 ("max_row_norm2", C.c_double), ("pcg_rel_residual", C.c_double),
                 ("ms_gram_kernel", C.c_double), ("gram_attempts", C.c_int32),
-                ("reserved1", C.c_int32)]
+                ("pcg_iterations_ga", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ir_residual"}

@@ -189,6 +189,35 @@ def test_pcg_step_matches_oracle_step():
     prob.close()
 
 
+@pytest.mark.parametrize("ell,seed", [(60, 1), (300, 2), (120, 5)])
+def test_pcg_step_with_ga_matches_oracle_step(ell, seed):
+    """dngd_step with the PCG solver and GA: f_vv along the PCG step v, a
+    second PCG solve with the same Nystrom preconditioner for beta, a =
+    -J^T beta and the acceptance test, against the oracle's dense GA step
+    (same mathematics, exact solves)."""
+    d = D()
+    p = W.config(1, scale=dict(widths=[5, 32, 32, 1], n_int=240, n_bdy=60))
+    th = W.glorot_theta(p.widths, seed)
+    lam = 1e-4
+    prob = d.Problem.from_workload(p)
+    I = torch.tensor(W.landmarks(p.m, ell, seed))
+    fvv = torch.empty(p.m, dtype=torch.float64, device="cuda")
+    o = d.step_opts(solver=d.PCG, ga=True, landmarks=I.cuda(), pcg_tol=1e-10, pcg_maxit=500,
+                    fvv_out=fvv)
+    dth, st = prob.step(th, lam, o)
+    ref = S.dense_step(p, th, lam, ga=True)
+    e = rel(dth.cpu().numpy(), ref.dtheta)
+    say("pcg+ga ell", ell, "seed", seed, "iters", st.pcg_iterations, st.pcg_iterations_ga,
+        "accepted", st.ga_accepted, "oracle", ref.accepted, "rel err", e)
+    assert st.pcg_converged and st.pcg_iterations_ga >= 1
+    assert st.ga_accepted == int(ref.accepted)
+    assert rel(fvv.cpu().numpy(), ref.fvv) <= 1e-6
+    assert abs(st.anorm - np.linalg.norm(ref.a)) <= 1e-6 * np.linalg.norm(ref.a)
+    assert abs(st.vnorm - np.linalg.norm(ref.v)) <= 1e-8 * np.linalg.norm(ref.v)
+    assert e <= 1e-6
+    prob.close()
+
+
 # --------------------------------------------------------------------------
 # mixed precision on a stiff serving job: the adaptive Gram
 
