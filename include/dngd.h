@@ -50,7 +50,15 @@ typedef enum {
 typedef enum { DNGD_F64 = 0, DNGD_F32 = 1 } dngd_dtype;
 typedef enum { DNGD_POISSON = 0, DNGD_HEAT = 1 } dngd_pde;
 typedef enum { DNGD_PLAIN = 0, DNGD_MIXED = 1 } dngd_precision;
-typedef enum { DNGD_DENSE = 0, DNGD_PCG = 1 } dngd_solver;
+/* Solvers of the step's linear systems.
+ *   DNGD_DENSE       dual: Cholesky of the m x m kernel J J^T + lambda I (Section 4.1)
+ *   DNGD_PCG         dual: Nystrom-preconditioned CG, matrix-free (Sections 3.3, 4.2)
+ *   DNGD_PRIMAL      primal Gauss-Newton: Cholesky of the n x n matrix J^T J + lambda I,
+ *                    v = -(J^T J + lambda I)^{-1} J^T r; the same step as the dual one
+ *                    (Proposition 3.1), the cheaper one when n < m
+ *   DNGD_DENSE_AUTO  DNGD_PRIMAL when n < m, else DNGD_DENSE (the cost model of the
+ *                    dense solvers: O(m n^2 + n^3) primal against O(m^2 n + m^3) dual) */
+typedef enum { DNGD_DENSE = 0, DNGD_PCG = 1, DNGD_PRIMAL = 2, DNGD_DENSE_AUTO = 3 } dngd_solver;
 
 /* Problem statement (Section 2.1 and 2.2 of the paper: the PINN loss and the
  * residual map).  Residuals:
@@ -83,7 +91,8 @@ typedef struct {
   int32_t precision;    /* DNGD_PLAIN: FP64 J, FP64-MFMA Gram.
                            DNGD_MIXED: FP32 J, BF16-MFMA Gram with FP32
                            accumulation, FP64 Cholesky and refinement. */
-  int32_t solver;       /* DNGD_DENSE (Cholesky) or DNGD_PCG (Nystrom-PCG) */
+  int32_t solver;       /* dngd_solver: DNGD_DENSE (default), DNGD_PCG, DNGD_PRIMAL,
+                           DNGD_DENSE_AUTO */
   int32_t ga;           /* 1: geodesic acceleration (Section 3.2), 0: off */
   int32_t ir_sweeps;    /* mixed dense: iterative-refinement sweeps per solve (default 2) */
   int32_t gram_passes;  /* mixed: 1 (bf16 x bf16), 3 (split J ~ hi + lo, hi hi^T + hi lo^T
@@ -104,8 +113,8 @@ typedef struct {
   double ir_tol;            /* mixed, auto Gram: escalate when ||s|| / ||r|| before the last
                                refinement sweep of the v solve exceeds this (default 1e-5) */
   /* optional device outputs (NULL = not written): the dual solution
-     alpha = (K + lambda I)^{-1} r (m FP64; dense and PCG) and f_vv (m FP64,
-     step with GA, dense and PCG) */
+     alpha = (K + lambda I)^{-1} r (m FP64; dual solvers only: DNGD_DENSE, DNGD_PCG,
+     and DNGD_DENSE_AUTO when it picks the dual) and f_vv (m FP64, any step with GA) */
   double* alpha_out;
   double* fvv_out;
 } dngd_step_opts;
@@ -126,6 +135,8 @@ typedef struct {
   double ms_gram_kernel;      /* the Gram contraction kernel alone (HIP events on `stream`) */
   int32_t gram_attempts;      /* Gram + factorisation attempts (> 1 after an escalation) */
   int32_t pcg_iterations_ga;  /* PCG with GA: iterations of the second (f_vv) solve */
+  int32_t primal;             /* 1 if the step solved the primal n x n system */
+  int32_t reserved2;
 } dngd_step_stats;
 
 const char* dngd_last_error(void);
@@ -215,7 +226,10 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda,
 /* One D-NGD step (dense dual solver with geodesic acceleration, Section 4.1,
  * or the PCG step of Section 4.2): dtheta = -J^T (J J^T + lambda I)^{-1} r,
  * plus a/2 with a = -J^T (J J^T + lambda I)^{-1} f_vv when accepted
- * (2 ||a|| <= 0.5 ||v||). With the PCG solver, the f_vv system is solved by a
+ * (2 ||a|| <= 0.5 ||v||). The primal solver computes the same v and a as
+ * -(J^T J + lambda I)^{-1} J^T r and -(J^T J + lambda I)^{-1} J^T f_vv
+ * (Proposition 3.1), with the same Gram precisions, refinement and escalation
+ * applied to J^T. With the PCG solver, the f_vv system is solved by a
  * second PCG run with the same Nystrom preconditioner (Remark 3.5); if that run
  * does not converge the correction is rejected (dtheta = v, ga_accepted = 0).
  * theta, dtheta: device n FP64. stats: host or NULL.

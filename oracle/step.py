@@ -112,6 +112,23 @@ def dense_step(problem, theta, lam, ga=True, eps_norm=0.0, J=None, r=None):
     return StepResult(r, J, K, alpha, v, f, beta, a, acc, dtheta)
 
 
+def primal_dense_step(problem, theta, lam, ga=True, eps_norm=0.0):
+    """One D-NGD step through the primal normal equations (Prop. 3.1): v from
+    (J^T J + lam I_n) v = -J^T r, f_vv along v, a from (J^T J + lam I_n) a =
+    -J^T f_vv (Prop. 3.4), the same acceptance rule. K holds J^T J; alpha and
+    beta are not formed."""
+    r = network.residual(problem, theta)
+    J = network.jacobian(problem, theta)
+    v = primal_step(J, r, lam)
+    if not ga:
+        return StepResult(r, J, J.T @ J, None, v, None, None, None, False, v.copy())
+    f = network.fvv(problem, theta, v)
+    a = primal_accel(J, f, lam)
+    acc = ga_accept(v, a, eps_norm)
+    dtheta = v + 0.5 * a if acc else v.copy()
+    return StepResult(r, J, J.T @ J, None, v, f, None, a, acc, dtheta)
+
+
 def backward_error(K, lam, x, b):
     """Normwise backward error ||(K+lam I)x - b|| / (||K+lam I|| ||x|| + ||b||)."""
     A = K + lam * np.eye(K.shape[0])

@@ -56,7 +56,7 @@ struct dngd_problem {
   // tangent streams (lazy)
   double *Z1 = nullptr, *Z2 = nullptr, *A1[2] = {nullptr, nullptr}, *A2[2] = {nullptr, nullptr};
   // step / solver workspace (lazy, grown on demand)
-  DevBuf J, K, vecs, work, gram_work, solve_aux, small, iter;
+  DevBuf J, Jt, K, vecs, work, gram_work, solve_aux, small, iter;
   int J_dtype = -1;
   int64_t ldJ = 0, ldK = 0;
   hipEvent_t ev[10] = {nullptr};
@@ -268,6 +268,7 @@ int vjp(dngd_problem* h, const double* theta, const double* p, double* gout, hip
 struct StepVecs {
   double *r, *alpha, *s, *fvv, *beta, *tmpm, *rownorm2;  // m each
   double *v, *a, *t, *thtmp;                                      // n each
+  double *pg, *px, *ps;  // n each: primal right-hand side, solution, refinement residual
   double* red;   // reduction scratch (256 doubles)
   double* scal;  // 64 device scalars
   double* gemv_work;
@@ -276,10 +277,12 @@ struct StepVecs {
 size_t step_vec_bytes(const Geometry& g) {
   // gemv_t scratch: J^T x (m rows, n columns) and the preconditioner's M x
   // (at most 64 row bands of m columns)
-  const size_t gw = std::max(gemv_t_workspace_bytes(std::max<int64_t>(g.m, 1), std::max<int64_t>(g.n, 1)),
-                             (size_t)64 * (size_t)std::max<int64_t>(g.m, 1) * sizeof(double));
-  // each of the 13 segments is padded to 32 doubles (256-byte aligned starts)
-  return (size_t)(7 * g.m + 4 * g.n + 64 + 13 * 32) * sizeof(double) + kReduceWorkBytes + gw;
+  // (primal step: J^T x and its transpose product, the same sizes swapped)
+  const int64_t m1 = std::max<int64_t>(g.m, 1), n1 = std::max<int64_t>(g.n, 1);
+  const size_t gw = std::max({gemv_t_workspace_bytes(m1, n1), gemv_t_workspace_bytes(n1, m1),
+                              (size_t)64 * (size_t)m1 * sizeof(double)});
+  // each of the 16 segments is padded to 32 doubles (256-byte aligned starts)
+  return (size_t)(7 * g.m + 7 * g.n + 64 + 16 * 32) * sizeof(double) + kReduceWorkBytes + gw;
 }
 
 int carve_vecs(dngd_problem* h, StepVecs& v) {
@@ -303,6 +306,9 @@ int carve_vecs(dngd_problem* h, StepVecs& v) {
   v.a = take(g.n);
   v.t = take(g.n);
   v.thtmp = take(g.n);
+  v.pg = take(g.n);
+  v.px = take(g.n);
+  v.ps = take(g.n);
   v.scal = take(64);
   v.red = take(256);
   v.gemv_work = p;
@@ -325,29 +331,41 @@ int carve_small(dngd_problem* h, Small& sm) {
 }
 
 
-int dense_solve(dngd_problem* h, const StepVecs& v, const Small& sm, const double* rhs, double* x,
-                double lambda, int ir_sweeps, const void* J, int j_dtype, double* ir_out,
-                hipStream_t s) {
-  const Geometry& g = h->g;
+// The dense solvers factor K = A A^T + lambda I for an operator A (M x N,
+// row-major, FP32 or FP64): A = J for the dual step (M = m residuals, N = n
+// parameters, Section 4.1) and A = J^T for the primal step (M = n, N = m,
+// Proposition 3.1). tN (N entries) and sM (M entries) are refinement scratch.
+struct DenseOp {
+  const void* A;
+  int64_t M, N, ldA;
+  int jd;
+  double* tN;
+  double* sM;
+};
+
+// x = (K + lam I)^{-1} rhs with the factor in h->K, then ir_sweeps sweeps of
+// refinement against the exact operator: s = rhs - (A (A^T x) + lam x), computed
+// with FP32/FP64 A and FP64 accumulation; ||s||^2 of sweep k -> ir_out[k].
+int dense_solve(dngd_problem* h, const DenseOp& op, const StepVecs& v, const double* rhs,
+                double* x, double lambda, int ir_sweeps, double* ir_out, hipStream_t s) {
   double* K = static_cast<double*>(h->K.p);
   const double* aux = static_cast<const double*>(h->solve_aux.p);
-  int rc = copy(s, g.m, rhs, x);
+  int rc = copy(s, op.M, rhs, x);
   if (rc) return rc;
-  rc = chol_solve(s, g.m, K, h->ldK, aux, x);
+  rc = chol_solve(s, op.M, K, h->ldK, aux, x);
   if (rc) return rc;
   for (int k = 0; k < ir_sweeps; ++k) {
-    // s = rhs - (J (J^T x) + lambda x), computed with FP32/FP64 J and FP64 accumulation
-    rc = gemv_t(s, g.m, g.n, J, h->ldJ, j_dtype, x, 1.0, v.t, v.gemv_work);
+    rc = gemv_t(s, op.M, op.N, op.A, op.ldA, op.jd, x, 1.0, op.tN, v.gemv_work);
     if (rc) return rc;
-    rc = gemv_n_residual(s, g.m, g.n, J, h->ldJ, j_dtype, v.t, rhs, x, lambda, v.s);
+    rc = gemv_n_residual(s, op.M, op.N, op.A, op.ldA, op.jd, op.tN, rhs, x, lambda, op.sM);
     if (rc) return rc;
     if (ir_out && k < 8) {
-      rc = sumsq(s, g.m, v.s, ir_out + k, v.red);
+      rc = sumsq(s, op.M, op.sM, ir_out + k, v.red);
       if (rc) return rc;
     }
-    rc = chol_solve(s, g.m, K, h->ldK, aux, v.s);
+    rc = chol_solve(s, op.M, K, h->ldK, aux, op.sM);
     if (rc) return rc;
-    rc = axpy(s, g.m, 1.0, v.s, x);
+    rc = axpy(s, op.M, 1.0, op.sM, x);
     if (rc) return rc;
   }
   return 0;
@@ -448,12 +466,22 @@ size_t footprint_bytes(const Geometry& g, const dngd_step_opts* o) {
   for (int l = 0; l < g.L - 1; ++l) b += 3 * (size_t)g.R * g.widths[l + 1] * 8;
   if (o->ga || o->solver == DNGD_PCG) b += 6 * (size_t)act_bytes(g);
   b += step_vec_bytes(g) + vjp_work_bytes(g) + (size_t)g.n * 8 + 256;
-  if (o->solver == DNGD_DENSE) {
+  if (o->solver != DNGD_PCG) {
     const int jd = (o->precision == DNGD_PLAIN) ? DNGD_F64 : DNGD_F32;
+    const size_t esz = (jd == DNGD_F64) ? 8 : 4;
     const int64_t ldJ = round_up(g.n, 256);
-    b += (size_t)g.m * ldJ * (jd == DNGD_F64 ? 8 : 4);
-    b += (size_t)g.m * g.m * 8 + chol_solve_aux_bytes(g.m);
-    b += gram_workspace_bytes(g.m, g.n, jd, 3, nullptr);
+    b += (size_t)g.m * ldJ * esz;
+    const bool primal =
+        o->solver == DNGD_PRIMAL || (o->solver == DNGD_DENSE_AUTO && g.n < g.m);
+    if (primal) {
+      // J^T, and K, Gram and solve workspaces of the n x n system
+      b += (size_t)g.n * round_up(g.m, 256) * esz;
+      b += (size_t)g.n * g.n * 8 + chol_solve_aux_bytes(g.n);
+      b += gram_workspace_bytes(g.n, g.m, jd, 3, nullptr);
+    } else {
+      b += (size_t)g.m * g.m * 8 + chol_solve_aux_bytes(g.m);
+      b += gram_workspace_bytes(g.m, g.n, jd, 3, nullptr);
+    }
   } else {
     const int64_t ell = std::max<int64_t>(1, o->n_landmarks);
     const int64_t ldM = round_up(g.m, 4);
@@ -992,7 +1020,9 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   dngd_step_opts_default(&def);
   const dngd_step_opts& o = opts ? *opts : def;
   DNGD_REQUIRE(o.precision == DNGD_PLAIN || o.precision == DNGD_MIXED, "bad precision");
-  DNGD_REQUIRE(o.solver == DNGD_DENSE || o.solver == DNGD_PCG, "bad solver");
+  DNGD_REQUIRE(o.solver == DNGD_DENSE || o.solver == DNGD_PCG || o.solver == DNGD_PRIMAL ||
+                   o.solver == DNGD_DENSE_AUTO,
+               "bad solver");
   DNGD_REQUIRE(o.ir_sweeps >= 0 && o.ir_sweeps <= 8, "ir_sweeps must be in [0, 8]");
   DNGD_REQUIRE(o.gram_passes == 0 || o.gram_passes == 1 || o.gram_passes == 3 ||
                    o.gram_passes == 4 || o.gram_passes == DNGD_GRAM_F64,
@@ -1101,32 +1131,56 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     return pst;
   }
 
-  // ---------------- dense dual solver ----------------
+  // ---------------- dense solvers: dual (Section 4.1) or primal (Proposition 3.1) --------
   const int jd = (o.precision == DNGD_PLAIN) ? DNGD_F64 : DNGD_F32;
+  const size_t esz = (jd == DNGD_F64) ? 8 : 4;
+  // the primal system is n x n, the dual m x m: same step, the smaller solve
+  const bool primal = o.solver == DNGD_PRIMAL || (o.solver == DNGD_DENSE_AUTO && g.n < g.m);
   const int64_t ldJ = round_up(g.n, 256);
-  rc = ensure(h, h->J, (size_t)g.m * ldJ * (jd == DNGD_F64 ? 8 : 4));
-  if (!rc) rc = ensure(h, h->K, (size_t)g.m * g.m * 8);
+  rc = ensure(h, h->J, (size_t)g.m * ldJ * esz);
   if (rc) return rc;
   h->ldJ = ldJ;
-  h->ldK = g.m;
   h->J_dtype = jd;
   void* J = h->J.p;
-  double* K = static_cast<double*>(h->K.p);
 
   // residual + Jacobian (Section 2.2)
   rc = forward(h, theta, v.r, s);
   if (!rc) rc = backward(h, theta, nullptr, s);
   if (!rc) rc = write_jacobian(h, J, ldJ, jd, v.rownorm2, s);
   if (rc) return rc;
+
+  // the operator of K = A A^T + lam I and the first system K x = b:
+  // dual A = J, b = r, x = alpha; primal A = J^T, b = J^T r, x = -v
+  DenseOp op;
+  const double* rhs1;
+  double* x1;
+  const double* diag;  // ||A_i||^2, the diagonal of K
+  if (primal) {
+    const int64_t ldJt = round_up(g.m, 256);
+    rc = ensure(h, h->Jt, (size_t)g.n * ldJt * esz);
+    if (!rc) rc = transpose_rm(s, g.m, g.n, J, ldJ, jd, h->Jt.p, ldJt);
+    if (!rc) rc = rownorm2(s, g.n, g.m, h->Jt.p, ldJt, jd, v.ps);
+    if (!rc) rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.r, 1.0, v.pg, v.gemv_work);
+    if (rc) return rc;
+    op = DenseOp{h->Jt.p, g.n, g.m, ldJt, jd, v.tmpm, v.ps};
+    rhs1 = v.pg;
+    x1 = v.px;
+    diag = v.ps;
+  } else {
+    op = DenseOp{J, g.m, g.n, ldJ, jd, v.t, v.s};
+    rhs1 = v.r;
+    x1 = v.alpha;
+    diag = v.rownorm2;
+  }
   DNGD_HIP(hipEventRecord(h->ev[1], s));
 
-  // Gram K = J J^T + lam I
+  // Gram K = A A^T + lam I
   int passes = 1;
   if (jd == DNGD_F32) {
     passes = o.gram_passes;
-    // max_i ||J_i||^2: decides the bf16 split when passes == 0 (auto)
-    std::vector<double> rn(g.m);
-    DNGD_HIP(hipMemcpyAsync(rn.data(), v.rownorm2, g.m * 8, hipMemcpyDeviceToHost, s));
+    // D = max_i ||A_i||^2: decides the bf16 split when passes == 0 (auto)
+    std::vector<double> rn(op.M);
+    DNGD_HIP(hipMemcpyAsync(rn.data(), diag, op.M * 8, hipMemcpyDeviceToHost, s));
     DNGD_HIP(hipStreamSynchronize(s));
     double dmax = 0.0;
     for (double x : rn) dmax = std::max(dmax, x);
@@ -1141,25 +1195,28 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
       else passes = 4;
     }
   }
-  rc = ensure(h, h->solve_aux, chol_solve_aux_bytes(g.m));
+  rc = ensure(h, h->K, (size_t)op.M * op.M * 8);
+  if (!rc) rc = ensure(h, h->solve_aux, chol_solve_aux_bytes(op.M));
   if (rc) return rc;
+  h->ldK = op.M;
+  double* K = static_cast<double*>(h->K.p);
   const int ir = (jd == DNGD_F32) ? o.ir_sweeps : 0;
   const bool adaptive = (jd == DNGD_F32 && o.gram_passes == 0);
   int64_t info = 0;
   int attempts = 0;
   for (;;) {
     ++attempts;
-    const size_t gw = gram_workspace_bytes(g.m, g.n, jd, passes, nullptr);
+    const size_t gw = gram_workspace_bytes(op.M, op.N, jd, passes, nullptr);
     rc = ensure(h, h->gram_work, gw);
     if (!rc)
-      rc = gram_launch(s, g.m, g.n, J, ldJ, jd, passes, lambda, K, g.m, h->gram_work.p, gw,
-                       h->ev[8], h->ev[9]);
+      rc = gram_launch(s, op.M, op.N, op.A, op.ldA, jd, passes, lambda, K, op.M,
+                       h->gram_work.p, gw, h->ev[8], h->ev[9]);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[2], s));
     // Cholesky of K + lam I
     double* cwork = static_cast<double*>(h->solve_aux.p);  // reused by the solves after
-    rc = o.no_lookahead ? chol_factor(s, g.m, K, g.m, sm.info, cwork, nullptr)
-                        : chol_factor(s, g.m, K, g.m, sm.info, cwork, nullptr, h->side,
+    rc = o.no_lookahead ? chol_factor(s, op.M, K, op.M, sm.info, cwork, nullptr)
+                        : chol_factor(s, op.M, K, op.M, sm.info, cwork, nullptr, h->side,
                                       h->cev[0], h->cev[1]);
     if (rc) return rc;
     const bool can_escalate = adaptive && passes != DNGD_GRAM_F64;
@@ -1171,18 +1228,18 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
         continue;
       }
     }
-    rc = chol_prepare_solve(s, g.m, K, g.m, static_cast<double*>(h->solve_aux.p));
+    rc = chol_prepare_solve(s, op.M, K, op.M, static_cast<double*>(h->solve_aux.p));
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[3], s));
 
-    // alpha = (K + lam I)^{-1} r (+ refinement), v = -J^T alpha
-    rc = dense_solve(h, v, sm, v.r, v.alpha, lambda, ir, J, jd, v.scal + 16, s);
+    // x = (K + lam I)^{-1} b (+ refinement)
+    rc = dense_solve(h, op, v, rhs1, x1, lambda, ir, v.scal + 16, s);
     if (rc) return rc;
     if (can_escalate && ir > 0) {
       // refinement did not bring the residual below ir_tol: the Gram is too
       // coarse for this damping
       double sc2[9];
-      rc = sumsq(s, g.m, v.r, v.scal + 15, v.red);
+      rc = sumsq(s, op.M, rhs1, v.scal + 15, v.red);
       if (rc) return rc;
       DNGD_HIP(hipMemcpyAsync(sc2, v.scal + 15, sizeof(sc2), hipMemcpyDeviceToHost, s));
       DNGD_HIP(hipStreamSynchronize(s));
@@ -1197,19 +1254,33 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   }
   st.gram_passes_used = passes;
   st.gram_attempts = attempts;
-  rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.alpha, -1.0, v.v, v.gemv_work);
-  if (!rc && o.alpha_out) rc = copy(s, g.m, v.alpha, o.alpha_out);
+  // v = -J^T alpha (dual) or v = -x (primal)
+  if (primal) {
+    rc = fill(s, g.n, 0.0, v.v);
+    if (!rc) rc = axpy(s, g.n, -1.0, x1, v.v);
+  } else {
+    rc = gemv_t(s, g.m, g.n, J, ldJ, jd, x1, -1.0, v.v, v.gemv_work);
+    if (!rc && o.alpha_out) rc = copy(s, g.m, x1, o.alpha_out);
+  }
   if (rc) return rc;
   DNGD_HIP(hipEventRecord(h->ev[4], s));
 
   if (o.ga) {
-    // f_vv along v (Section 3.2), beta = (K + lam I)^{-1} f_vv, a = -J^T beta
+    // f_vv along v (Section 3.2); a = -J^T (K + lam I)^{-1} f_vv (dual) or
+    // a = -(J^T J + lam I)^{-1} J^T f_vv (primal)
     rc = tangent(h, theta, v.v, 2, v.fvv, s);
     if (!rc && o.fvv_out) rc = copy(s, g.m, v.fvv, o.fvv_out);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[5], s));
-    rc = dense_solve(h, v, sm, v.fvv, v.beta, lambda, ir, J, jd, nullptr, s);
-    if (!rc) rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.beta, -1.0, v.a, v.gemv_work);
+    if (primal) {
+      rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.fvv, 1.0, v.t, v.gemv_work);
+      if (!rc) rc = dense_solve(h, op, v, v.t, v.px, lambda, ir, nullptr, s);
+      if (!rc) rc = fill(s, g.n, 0.0, v.a);
+      if (!rc) rc = axpy(s, g.n, -1.0, v.px, v.a);
+    } else {
+      rc = dense_solve(h, op, v, v.fvv, v.beta, lambda, ir, nullptr, s);
+      if (!rc) rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.beta, -1.0, v.a, v.gemv_work);
+    }
     if (!rc) rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
     if (!rc) rc = sumsq(s, g.n, v.a, v.scal + 1, v.red);
     if (!rc) rc = ga_combine(s, g.n, v.v, v.a, v.scal, o.eps_norm, dtheta, sm.ga_flag);
@@ -1221,7 +1292,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     if (rc) return rc;
   }
   if (ir > 0) {
-    rc = sumsq(s, g.m, v.r, v.scal + 15, v.red);
+    rc = sumsq(s, op.M, rhs1, v.scal + 15, v.red);
     if (rc) return rc;
   }
   DNGD_HIP(hipEventRecord(h->ev[6], s));
@@ -1252,6 +1323,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   st.vnorm = std::sqrt(sc[0]);
   st.anorm = o.ga ? std::sqrt(sc[1]) : 0.0;
   st.ga_accepted = o.ga ? gaf : 0;
+  st.primal = primal ? 1 : 0;
   if (ir > 0) {
     const double nr = std::sqrt(sc[15]);
     for (int k = 0; k < ir && k < 8; ++k) st.ir_residual[k] = nr > 0 ? std::sqrt(sc[16 + k]) / nr : 0;

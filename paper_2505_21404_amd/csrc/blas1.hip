@@ -198,6 +198,44 @@ __global__ void fill_kernel(int64_t n, double v, double* __restrict__ y) {
   if (i < n) y[i] = v;
 }
 
+// dst[j][i] = src[i][j] for src rows x cols (row-major, lds), dst cols x rows
+// (row-major, ldd): 64 x 64 tiles through LDS, both sides coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_rm_kernel(int64_t rows, int64_t cols,
+                                                           const T* __restrict__ src, int64_t lds,
+                                                           T* __restrict__ dst, int64_t ldd) {
+  __shared__ T tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    tile[i][tx] = (r < rows && c < cols) ? src[r * lds + c] : T(0);
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < cols && r < rows) dst[c * ldd + r] = tile[tx][i];
+  }
+}
+
+// out[i] = sum_k A[i][k]^2 (one workgroup per row, fixed reduction order)
+template <typename T>
+__global__ __launch_bounds__(256) void rownorm2_kernel(int64_t cols, const T* __restrict__ A,
+                                                       int64_t lda, double* __restrict__ out) {
+  __shared__ double red[4];
+  const T* a = A + (int64_t)blockIdx.x * lda;
+  double ss = 0.0;
+  for (int64_t k = threadIdx.x; k < cols; k += 256) {
+    const double x = (double)a[k];
+    ss += x * x;
+  }
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 __global__ void ga_combine_kernel(int64_t n, const double* __restrict__ v, const double* __restrict__ a,
                                   const double* __restrict__ norms2, double eps,
                                   double* __restrict__ dtheta, int* flag_out) {
@@ -318,6 +356,34 @@ int ga_combine(hipStream_t s, int64_t n, const double* v, const double* a, const
                double eps, double* dtheta, int* flag_out) {
   hipLaunchKernelGGL(ga_combine_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, v, a,
                      norms2, eps, dtheta, flag_out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int transpose_rm(hipStream_t s, int64_t rows, int64_t cols, const void* src, int64_t lds,
+                 int j_dtype, void* dst, int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return 0;
+  DNGD_REQUIRE(lds >= cols && ldd >= rows, "transpose_rm: leading dimension too small");
+  const dim3 grid((unsigned)cdiv(cols, 64), (unsigned)cdiv(rows, 64));
+  if (j_dtype == 0)
+    hipLaunchKernelGGL(transpose_rm_kernel<double>, grid, dim3(256), 0, s, rows, cols,
+                       static_cast<const double*>(src), lds, static_cast<double*>(dst), ldd);
+  else
+    hipLaunchKernelGGL(transpose_rm_kernel<float>, grid, dim3(256), 0, s, rows, cols,
+                       static_cast<const float*>(src), lds, static_cast<float*>(dst), ldd);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int rownorm2(hipStream_t s, int64_t rows, int64_t cols, const void* A, int64_t lda, int j_dtype,
+             double* out) {
+  if (rows <= 0) return 0;
+  if (j_dtype == 0)
+    hipLaunchKernelGGL(rownorm2_kernel<double>, dim3((unsigned)rows), dim3(256), 0, s, cols,
+                       static_cast<const double*>(A), lda, out);
+  else
+    hipLaunchKernelGGL(rownorm2_kernel<float>, dim3((unsigned)rows), dim3(256), 0, s, cols,
+                       static_cast<const float*>(A), lda, out);
   DNGD_LAUNCH_CHECK();
   return 0;
 }

@@ -188,6 +188,12 @@ int gather_cols(hipStream_t s, int64_t ell, const double* A, int64_t lda, const 
 constexpr size_t kReduceWorkBytes = 256 * sizeof(double);
 int copy(hipStream_t s, int64_t n, const double* x, double* y);
 int fill(hipStream_t s, int64_t n, double v, double* y);
+// dst (cols x rows, row-major ldd) = src^T for src (rows x cols, row-major lds), FP32 or FP64
+int transpose_rm(hipStream_t s, int64_t rows, int64_t cols, const void* src, int64_t lds,
+                 int j_dtype, void* dst, int64_t ldd);
+// out[i] = ||A_i||^2 for the rows of A (rows x cols, row-major, FP32 or FP64)
+int rownorm2(hipStream_t s, int64_t rows, int64_t cols, const void* A, int64_t lda, int j_dtype,
+             double* out);
 // dtheta = v + coef * a with coef = 0.5 if ||v|| > eps and 2||a|| <= 0.5 ||v|| else 0;
 // norms2 = {||v||^2, ||a||^2} on device; flag_out (device int) = accepted.
 int ga_combine(hipStream_t s, int64_t n, const double* v, const double* a, const double* norms2,

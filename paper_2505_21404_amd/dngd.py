@@ -21,7 +21,7 @@ F64, F32 = 0, 1
 GRAM_F64 = 64   # gram_passes value: FP64-product Gram of an FP32 J
 POISSON, HEAT = 0, 1
 PLAIN, MIXED = 0, 1
-DENSE, PCG = 0, 1
+DENSE, PCG, PRIMAL, DENSE_AUTO = 0, 1, 2, 3
 
 _STATUS = {ENOCONV: "DNGD_ENOCONV", EINVAL: "DNGD_EINVAL", ENOMEM: "DNGD_ENOMEM", EHIP: "DNGD_EHIP",
            ENOTPD: "DNGD_ENOTPD", ENAN: "DNGD_ENAN", ETIMEOUT: "DNGD_ETIMEOUT"}
@@ -58,7 +58,8 @@ class StepStats(C.Structure):
                 ("pcg_converged", C.c_int32), ("ir_residual", C.c_double * 8),
                 ("max_row_norm2", C.c_double), ("pcg_rel_residual", C.c_double),
                 ("ms_gram_kernel", C.c_double), ("gram_attempts", C.c_int32),
-                ("pcg_iterations_ga", C.c_int32)]
+                ("pcg_iterations_ga", C.c_int32), ("primal", C.c_int32),
+                ("reserved2", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ir_residual"}

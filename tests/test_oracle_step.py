@@ -100,3 +100,23 @@ def test_config0_training_gate():
     err = N.relative_l2(p, th, xe, W.exact_solution("sinsin", xe))
     print("config0 relative L2 after 20 steps:", err, "loss", losses[-1])
     assert err <= 1e-2
+
+
+@pytest.mark.parametrize("widths,n_int,n_bdy,lam", [([2, 8, 1], 60, 20, 1e-3),
+                                                   ([2, 6, 6, 1], 90, 30, 1e-6)])
+def test_primal_dense_step_equals_dual_step(widths, n_int, n_bdy, lam):
+    """The whole primal step (n x n systems, n < m here) equals the dual step
+    (m x m systems): the same v, f_vv, a, acceptance and dtheta."""
+    p = W.config(0, scale=dict(widths=widths, n_int=n_int, n_bdy=n_bdy))
+    th = W.glorot_theta(p.widths, 3)
+    n = sum(a * b + b for a, b in zip(widths[:-1], widths[1:]))
+    assert n < p.m
+    pr = S.primal_dense_step(p, th, lam)
+    du = S.dense_step(p, th, lam)
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    assert rel(pr.v, du.v) <= 1e-9
+    assert rel(pr.fvv, du.fvv) <= 1e-9
+    assert rel(pr.a, du.a) <= 1e-8
+    assert pr.accepted == du.accepted
+    assert rel(pr.dtheta, du.dtheta) <= 1e-8
