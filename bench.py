@@ -62,6 +62,9 @@ def parse():
                     help="with --pcg: also run this many optimiser iterations (PCG steps + line search)")
     ap.add_argument("--pcg-ga", action="store_true",
                     help="with --pcg: geodesic acceleration (second PCG solve for f_vv)")
+    ap.add_argument("--regime-map", action="store_true",
+                    help="instead: primal vs dual dense step times over m x n shapes "
+                         "(2-D Poisson, hidden width 50, FP64, GA)")
     return ap.parse_args()
 
 
@@ -165,6 +168,41 @@ def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def regime_map(torch, ms=(300, 1300, 3300, 6300), ks=(0, 1, 2, 4), steps=3):
+    """Primal (n x n) against dual (m x m) dense FP64 steps with GA on 2-D
+    Poisson networks 2-50-...-50-1 with k + 1 hidden layers (n = 201 + 2550 k)
+    and m residuals (4:1 interior to boundary); median ms over `steps` steps
+    after one warmup, and the solver the cost rule (primal iff n < m) picks."""
+    import workloads as W
+    from paper_2505_21404_amd import dngd as D
+    rows = []
+    for k in ks:
+        widths = [2] + [50] * (k + 1) + [1]
+        for m in ms:
+            p = W.config(0, scale=dict(widths=widths, n_int=4 * m // 5, n_bdy=m - 4 * m // 5))
+            th = torch.tensor(W.glorot_theta(p.widths, 0), device="cuda")
+            prob = D.Problem.from_workload(p)
+            t = {}
+            for name, solver in (("primal", D.PRIMAL), ("dual", D.DENSE)):
+                o = D.step_opts(precision=D.PLAIN, solver=solver, ga=True)
+                prob.step(th, 1e-4, o)
+                ws = []
+                for _ in range(steps):
+                    t0 = time.perf_counter()
+                    prob.step(th, 1e-4, o)
+                    ws.append((time.perf_counter() - t0) * 1e3)
+                t[name] = statistics.median(ws)
+            auto = "primal" if prob.n < prob.m else "dual"
+            rows.append({"m": prob.m, "n": prob.n, "ms_primal": t["primal"], "ms_dual": t["dual"],
+                         "faster": min(t, key=t.get), "auto": auto})
+            progress(f"regime m={prob.m} n={prob.n}: primal {t['primal']:.2f} ms, dual {t['dual']:.2f} ms")
+            prob.close()
+    agree = sum(r["faster"] == r["auto"] for r in rows)
+    return {"metric": "dense D-NGD step time, primal vs dual (FP64, GA)", "unit": "ms",
+            "n_gpus": 1, "data": "synthetic", "rows": rows,
+            "auto_picks_faster": f"{agree}/{len(rows)}"}
+
+
 def pcg_run(a, torch):
     """One matrix-free Nystrom-PCG step (GA with --pcg-ga) on the large 5-D Poisson
     workload: n = 12.6M parameters, m = 50,000 residuals (45,000 interior,
@@ -247,6 +285,9 @@ def main():
         return 0
     if a.pcg:
         print(json.dumps(pcg_run(a, torch)), flush=True)
+        return 0
+    if a.regime_map:
+        print(json.dumps(regime_map(torch)), flush=True)
         return 0
     import workloads as W
     from paper_2505_21404_amd import dngd as D
