@@ -62,6 +62,9 @@ def parse():
                     help="with --pcg: also run this many optimiser iterations (PCG steps + line search)")
     ap.add_argument("--pcg-ga", action="store_true",
                     help="with --pcg: geodesic acceleration (second PCG solve for f_vv)")
+    ap.add_argument("--structured", type=int, default=-1, metavar="CFG",
+                    help="instead: the dense step on the structured FP64 kernel (no J) against "
+                         "the mixed J step, on workload CFG (1: 5-D Poisson, 2: heat)")
     ap.add_argument("--regime-map", action="store_true",
                     help="instead: primal vs dual dense step times over m x n shapes "
                          "(2-D Poisson, hidden width 50, FP64, GA)")
@@ -166,6 +169,45 @@ def serving_run(n_jobs, steps, slots, torch):
 
 def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def structured_run(cfg, torch, steps=3):
+    """Dense dual step with GA on workload `cfg`: the structured FP64 kernel
+    (per-layer products of activations and adjoints, J never formed) against
+    the mixed step on the materialised FP32 J; median step times, phases and
+    the relative difference of the two steps."""
+    import workloads as W
+    from paper_2505_21404_amd import dngd as D
+    p = W.config(cfg)
+    th = torch.tensor(W.glorot_theta(p.widths, 0), device="cuda")
+    prob = D.Problem.from_workload(p)
+    r = prob.residual(th)
+    lam = min(0.5 * float((r * r).sum()), W.LAMBDA_CAP[cfg])
+    out = {"metric": "dense D-NGD step, structured FP64 kernel vs mixed J", "unit": "ms",
+           "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": W.CONFIG_NAMES[cfg], "m": prob.m, "n": prob.n, "lambda": lam}}
+    dths = {}
+    for name, o in (("structured", D.step_opts(solver=D.STRUCTURED, ga=True)),
+                    ("mixed", D.step_opts(precision=D.MIXED, ga=True))):
+        prob.step(th, lam, o)
+        ws, sts = [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            dth, st = prob.step(th, lam, o)
+            ws.append((time.perf_counter() - t0) * 1e3)
+            sts.append(st.as_dict())
+        dths[name] = dth.clone()
+        out[name] = {"ms_per_step": statistics.median(ws),
+                     "phase_ms": {k: statistics.median(x[k] for x in sts) for k in (
+                         "ms_residual_jacobian", "ms_gram", "ms_gram_kernel", "ms_factor",
+                         "ms_solve_v", "ms_fvv", "ms_solve_a")},
+                     "footprint_bytes": prob.footprint(o) if hasattr(prob, "footprint") else None}
+        progress(f"structured run {name}: {out[name]['ms_per_step']:.1f} ms/step")
+        torch.cuda.empty_cache()
+    out["rel_diff_structured_vs_mixed"] = float(
+        ((dths["structured"] - dths["mixed"]).norm() / dths["structured"].norm()).item())
+    prob.close()
+    return out
 
 
 def regime_map(torch, ms=(300, 1300, 3300, 6300), ks=(0, 1, 2, 4), steps=3):
@@ -288,6 +330,9 @@ def main():
         return 0
     if a.regime_map:
         print(json.dumps(regime_map(torch)), flush=True)
+        return 0
+    if a.structured >= 0:
+        print(json.dumps(structured_run(a.structured, torch)), flush=True)
         return 0
     import workloads as W
     from paper_2505_21404_amd import dngd as D

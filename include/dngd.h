@@ -57,8 +57,19 @@ typedef enum { DNGD_PLAIN = 0, DNGD_MIXED = 1 } dngd_precision;
  *                    v = -(J^T J + lambda I)^{-1} J^T r; the same step as the dual one
  *                    (Proposition 3.1), the cheaper one when n < m
  *   DNGD_DENSE_AUTO  DNGD_PRIMAL when n < m, else DNGD_DENSE (the cost model of the
- *                    dense solvers: O(m n^2 + n^3) primal against O(m^2 n + m^3) dual) */
-typedef enum { DNGD_DENSE = 0, DNGD_PCG = 1, DNGD_PRIMAL = 2, DNGD_DENSE_AUTO = 3 } dngd_solver;
+ *                    dense solvers: O(m n^2 + n^3) primal against O(m^2 n + m^3) dual)
+ *   DNGD_STRUCTURED  dual Cholesky on K = J J^T assembled per layer from activations and
+ *                    adjoints in FP64, J never formed (Section 4); v and a by the
+ *                    matrix-free reverse pass. FP64 throughout (precision, gram_passes
+ *                    and ir_sweeps do not apply). Cheaper than the J Gram when the
+ *                    layers are wide against the jet rows per point. */
+typedef enum {
+  DNGD_DENSE = 0,
+  DNGD_PCG = 1,
+  DNGD_PRIMAL = 2,
+  DNGD_DENSE_AUTO = 3,
+  DNGD_STRUCTURED = 4
+} dngd_solver;
 
 /* Problem statement (Section 2.1 and 2.2 of the paper: the PINN loss and the
  * residual map).  Residuals:
@@ -92,7 +103,7 @@ typedef struct {
                            DNGD_MIXED: FP32 J, BF16-MFMA Gram with FP32
                            accumulation, FP64 Cholesky and refinement. */
   int32_t solver;       /* dngd_solver: DNGD_DENSE (default), DNGD_PCG, DNGD_PRIMAL,
-                           DNGD_DENSE_AUTO */
+                           DNGD_DENSE_AUTO, DNGD_STRUCTURED */
   int32_t ga;           /* 1: geodesic acceleration (Section 3.2), 0: off */
   int32_t ir_sweeps;    /* mixed dense: iterative-refinement sweeps per solve (default 2) */
   int32_t gram_passes;  /* mixed: 1 (bf16 x bf16), 3 (split J ~ hi + lo, hi hi^T + hi lo^T
@@ -114,7 +125,8 @@ typedef struct {
                                refinement sweep of the v solve exceeds this (default 1e-5) */
   /* optional device outputs (NULL = not written): the dual solution
      alpha = (K + lambda I)^{-1} r (m FP64; dual solvers only: DNGD_DENSE, DNGD_PCG,
-     and DNGD_DENSE_AUTO when it picks the dual) and f_vv (m FP64, any step with GA) */
+     DNGD_STRUCTURED, and DNGD_DENSE_AUTO when it picks the dual) and f_vv (m FP64,
+     any step with GA) */
   double* alpha_out;
   double* fvv_out;
 } dngd_step_opts;

@@ -466,7 +466,12 @@ size_t footprint_bytes(const Geometry& g, const dngd_step_opts* o) {
   for (int l = 0; l < g.L - 1; ++l) b += 3 * (size_t)g.R * g.widths[l + 1] * 8;
   if (o->ga || o->solver == DNGD_PCG) b += 6 * (size_t)act_bytes(g);
   b += step_vec_bytes(g) + vjp_work_bytes(g) + (size_t)g.n * 8 + 256;
-  if (o->solver != DNGD_PCG) {
+  if (o->solver == DNGD_STRUCTURED) {
+    // K, solve workspace, point offsets and the two chunk products (no J)
+    const int64_t RC = nystrom_chunk_rows(g, g.R);
+    b += (size_t)g.m * g.m * 8 + chol_solve_aux_bytes(g.m);
+    b += (size_t)round_up(g.m + 1, 32) * 8 + 2 * (size_t)RC * g.R * 8;
+  } else if (o->solver != DNGD_PCG) {
     const int jd = (o->precision == DNGD_PLAIN) ? DNGD_F64 : DNGD_F32;
     const size_t esz = (jd == DNGD_F64) ? 8 : 4;
     const int64_t ldJ = round_up(g.n, 256);
@@ -759,6 +764,56 @@ int losses_impl(dngd_problem* h, const double* theta, const double* dtheta, int 
 
 namespace {
 
+// K (m x m, lower triangle, row-major ldK) = J J^T + lam I without forming J.
+// Per affine layer l with adjoints G_l and inputs H_l (R jet rows), the rows
+// of J for point i are sum_c G_l[c] (x) H_l[c] over its jet rows c, so
+//   J_i . J_j = sum_l sum_{c of i, c' of j} (G_l[c] . G_l[c']) (H_l[c] . H_l[c'])
+//               + G_l[i value] . G_l[j value]   (bias)
+// (the per-layer structured form the paper builds its kernel from, Section 4).
+// Jet rows are taken in chunks; a chunk's G and H rows are multiplied (FP64
+// MFMA) by the rows of all points up to the chunk's last one, and the combine
+// kernel sums the channel pairs into K[p][q], q <= p.
+int structured_gram(dngd_problem* h, const double* theta, double lambda, double* K,
+                    int64_t ldK, hipStream_t s) {
+  const Geometry& g = h->g;
+  std::vector<int64_t> qoff(g.m + 1, 0);
+  for (int64_t p = 0; p < g.m; ++p) qoff[p + 1] = qoff[p] + (p < g.n_int ? g.C_int : 1);
+  const int64_t R = qoff[g.m];
+  const int64_t RC = nystrom_chunk_rows(g, R);
+  // work (h->J): point row offsets, then the chunk products Gp, Hp (RC x R)
+  const size_t bOff = (size_t)round_up(g.m + 1, 32) * 8;
+  int rc = ensure(h, h->J, bOff + 2 * (size_t)RC * R * 8);
+  if (rc) return rc;
+  int64_t* dQoff = static_cast<int64_t*>(h->J.p);
+  double* Gp = reinterpret_cast<double*>(static_cast<char*>(h->J.p) + bOff);
+  double* Hp = Gp + (size_t)RC * R;
+  DNGD_HIP(hipMemcpyAsync(dQoff, qoff.data(), (g.m + 1) * 8, hipMemcpyHostToDevice, s));
+  rc = backward(h, theta, nullptr, s);
+  if (rc) return rc;
+  for (int l = 0; l < g.L; ++l) {
+    const int win = g.widths[l], wout = g.widths[l + 1];
+    const double* Gl = (l < g.L - 1) ? h->Zb[l] : h->seed;
+    const double* Hl = act_in(h, l);
+    for (int64_t p0 = 0; p0 < g.m;) {
+      int64_t p1 = p0;
+      if (p0 < g.n_int) p1 = std::min<int64_t>(g.n_int, p0 + std::max<int64_t>(1, RC / g.C_int));
+      else p1 = std::min<int64_t>(g.m, p0 + RC);
+      const int64_t row0 = qoff[p0], row1 = qoff[p1], nr = row1 - row0;
+      rc = gemm_f64(s, GEMM_FULL, true, true, nr, row1, wout, 1.0, Gl + row0 * wout, wout, Gl,
+                    wout, 0.0, Gp, R);
+      if (!rc)
+        rc = gemm_f64(s, GEMM_FULL, true, true, nr, row1, win, 1.0, Hl + row0 * win, win, Hl, win,
+                      0.0, Hp, R);
+      if (!rc)
+        rc = net_nystrom_combine(s, h->rm, p0, p1 - p0, row0, Gp, Hp, R, p1, dQoff, K, ldK,
+                                 l > 0 ? 1 : 0, 1);
+      if (rc) return rc;
+      p0 = p1;
+    }
+  }
+  return add_diag(s, g.m, K, ldK, lambda);
+}
+
 int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t* I, int64_t ell,
               Precond& P, hipStream_t s) {
   const Geometry& g = h->g;
@@ -1021,7 +1076,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   const dngd_step_opts& o = opts ? *opts : def;
   DNGD_REQUIRE(o.precision == DNGD_PLAIN || o.precision == DNGD_MIXED, "bad precision");
   DNGD_REQUIRE(o.solver == DNGD_DENSE || o.solver == DNGD_PCG || o.solver == DNGD_PRIMAL ||
-                   o.solver == DNGD_DENSE_AUTO,
+                   o.solver == DNGD_DENSE_AUTO || o.solver == DNGD_STRUCTURED,
                "bad solver");
   DNGD_REQUIRE(o.ir_sweeps >= 0 && o.ir_sweeps <= 8, "ir_sweeps must be in [0, 8]");
   DNGD_REQUIRE(o.gram_passes == 0 || o.gram_passes == 1 || o.gram_passes == 3 ||
@@ -1129,6 +1184,99 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
       return DNGD_ENAN;
     }
     return pst;
+  }
+
+  // ---------------- dense dual solver on the structured FP64 kernel (J never formed) ------
+  if (o.solver == DNGD_STRUCTURED) {
+    rc = forward(h, theta, v.r, s);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[1], s));
+    rc = ensure(h, h->K, (size_t)g.m * g.m * 8);
+    if (!rc) rc = ensure(h, h->solve_aux, chol_solve_aux_bytes(g.m));
+    if (rc) return rc;
+    h->ldK = g.m;
+    double* K = static_cast<double*>(h->K.p);
+    DNGD_HIP(hipEventRecord(h->ev[8], s));
+    rc = structured_gram(h, theta, lambda, K, g.m, s);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[9], s));
+    DNGD_HIP(hipEventRecord(h->ev[2], s));
+    double* aux = static_cast<double*>(h->solve_aux.p);
+    rc = o.no_lookahead ? chol_factor(s, g.m, K, g.m, sm.info, aux, nullptr)
+                        : chol_factor(s, g.m, K, g.m, sm.info, aux, nullptr, h->side, h->cev[0],
+                                      h->cev[1]);
+    if (!rc) rc = chol_prepare_solve(s, g.m, K, g.m, aux);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[3], s));
+    // alpha = (K + lam I)^{-1} r; v = -J^T alpha (matrix-free reverse pass)
+    rc = copy(s, g.m, v.r, v.alpha);
+    if (!rc) rc = chol_solve(s, g.m, K, g.m, aux, v.alpha);
+    if (!rc && o.alpha_out) rc = copy(s, g.m, v.alpha, o.alpha_out);
+    if (!rc) rc = vjp(h, theta, v.alpha, v.t, s);
+    if (!rc) rc = fill(s, g.n, 0.0, v.v);
+    if (!rc) rc = axpy(s, g.n, -1.0, v.t, v.v);
+    if (rc) return rc;
+    DNGD_HIP(hipEventRecord(h->ev[4], s));
+    if (o.ga) {
+      rc = tangent(h, theta, v.v, 2, v.fvv, s);
+      if (!rc && o.fvv_out) rc = copy(s, g.m, v.fvv, o.fvv_out);
+      if (rc) return rc;
+      DNGD_HIP(hipEventRecord(h->ev[5], s));
+      rc = copy(s, g.m, v.fvv, v.beta);
+      if (!rc) rc = chol_solve(s, g.m, K, g.m, aux, v.beta);
+      if (!rc) rc = vjp(h, theta, v.beta, v.t, s);
+      if (!rc) rc = fill(s, g.n, 0.0, v.a);
+      if (!rc) rc = axpy(s, g.n, -1.0, v.t, v.a);
+      if (!rc) rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
+      if (!rc) rc = sumsq(s, g.n, v.a, v.scal + 1, v.red);
+      if (!rc) rc = ga_combine(s, g.n, v.v, v.a, v.scal, o.eps_norm, dtheta, sm.ga_flag);
+      if (rc) return rc;
+    } else {
+      DNGD_HIP(hipEventRecord(h->ev[5], s));
+      rc = copy(s, g.n, v.v, dtheta);
+      if (!rc) rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
+      if (rc) return rc;
+    }
+    DNGD_HIP(hipEventRecord(h->ev[6], s));
+    double sc[2] = {0, 0};
+    int gaf = 0;
+    int64_t info = 0;
+    DNGD_HIP(hipMemcpyAsync(sc, v.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+    DNGD_HIP(hipMemcpyAsync(&info, sm.info, 8, hipMemcpyDeviceToHost, s));
+    DNGD_HIP(hipMemcpyAsync(&gaf, sm.ga_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    DNGD_HIP(hipStreamSynchronize(s));
+    float ms = 0;
+    hipEventElapsedTime(&ms, h->ev[0], h->ev[6]);
+    st.ms_total = ms;
+    hipEventElapsedTime(&ms, h->ev[0], h->ev[1]);
+    st.ms_residual_jacobian = ms;
+    hipEventElapsedTime(&ms, h->ev[1], h->ev[2]);
+    st.ms_gram = ms;
+    hipEventElapsedTime(&ms, h->ev[8], h->ev[9]);
+    st.ms_gram_kernel = ms;
+    hipEventElapsedTime(&ms, h->ev[2], h->ev[3]);
+    st.ms_factor = ms;
+    hipEventElapsedTime(&ms, h->ev[3], h->ev[4]);
+    st.ms_solve_v = ms;
+    hipEventElapsedTime(&ms, h->ev[4], h->ev[5]);
+    st.ms_fvv = ms;
+    hipEventElapsedTime(&ms, h->ev[5], h->ev[6]);
+    st.ms_solve_a = ms;
+    st.vnorm = std::sqrt(sc[0]);
+    st.anorm = o.ga ? std::sqrt(sc[1]) : 0.0;
+    st.ga_accepted = o.ga ? gaf : 0;
+    st.gram_passes_used = DNGD_GRAM_F64;
+    st.gram_attempts = 1;
+    if (stats) *stats = st;
+    if (info != 0) {
+      set_error("Cholesky of K + lambda I: non-positive pivot at column %lld", (long long)info);
+      return DNGD_ENOTPD;
+    }
+    if (!std::isfinite(st.vnorm) || !std::isfinite(st.anorm)) {
+      set_error("non-finite step");
+      return DNGD_ENAN;
+    }
+    return DNGD_OK;
   }
 
   // ---------------- dense solvers: dual (Section 4.1) or primal (Proposition 3.1) --------

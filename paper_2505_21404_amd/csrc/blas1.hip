@@ -236,6 +236,11 @@ __global__ __launch_bounds__(256) void rownorm2_kernel(int64_t cols, const T* __
   if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+__global__ void add_diag_kernel(int64_t n, double* __restrict__ K, int64_t ldK, double v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) K[i * ldK + i] += v;
+}
+
 __global__ void ga_combine_kernel(int64_t n, const double* __restrict__ v, const double* __restrict__ a,
                                   const double* __restrict__ norms2, double eps,
                                   double* __restrict__ dtheta, int* flag_out) {
@@ -384,6 +389,13 @@ int rownorm2(hipStream_t s, int64_t rows, int64_t cols, const void* A, int64_t l
   else
     hipLaunchKernelGGL(rownorm2_kernel<float>, dim3((unsigned)rows), dim3(256), 0, s, cols,
                        static_cast<const float*>(A), lda, out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int add_diag(hipStream_t s, int64_t n, double* K, int64_t ldK, double v) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, K, ldK, v);
   DNGD_LAUNCH_CHECK();
   return 0;
 }

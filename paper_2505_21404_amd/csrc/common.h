@@ -191,6 +191,8 @@ int fill(hipStream_t s, int64_t n, double v, double* y);
 // dst (cols x rows, row-major ldd) = src^T for src (rows x cols, row-major lds), FP32 or FP64
 int transpose_rm(hipStream_t s, int64_t rows, int64_t cols, const void* src, int64_t lds,
                  int j_dtype, void* dst, int64_t ldd);
+// K[i][i] += v for i < n
+int add_diag(hipStream_t s, int64_t n, double* K, int64_t ldK, double v);
 // out[i] = ||A_i||^2 for the rows of A (rows x cols, row-major, FP32 or FP64)
 int rownorm2(hipStream_t s, int64_t rows, int64_t cols, const void* A, int64_t lda, int j_dtype,
              double* out);
@@ -228,7 +230,8 @@ int net_gather_rows(hipStream_t s, int64_t nrows, int w, const int64_t* rows, co
                     double* dst);
 int net_nystrom_combine(hipStream_t s, const RowMap& rm, int64_t p0, int64_t np, int64_t row0,
                         const double* Gp, const double* Hp, int64_t ld, int64_t ell,
-                        const int64_t* qoff, double* Mt, int64_t ldM, int accumulate);
+                        const int64_t* qoff, double* Mt, int64_t ldM, int accumulate,
+                        int lower = 0);
 int net_colsum_value_rows(hipStream_t s, const RowMap& rm, int w, const double* Zbar, double* out,
                           double* work);
 

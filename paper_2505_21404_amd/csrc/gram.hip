@@ -56,24 +56,29 @@ union Chunk {
 
 // 256 x 256 tile of K per workgroup: 8 waves in a 2 x 4 grid (two per SIMD,
 // so one wave's conversion work runs under the other's MFMAs), each a
-// 128 x 64 block = 4 x 2 MFMA 32x32 accumulators. K advances 16 elements (one
-// MFMA K-slice) per step. The FP32 slabs of both row panels are loaded into
-// registers two steps ahead (each lane 32 B = 8 floats of a row), split once
-// into bf16 hi (and lo) planes and stored in LDS (one 16-byte store per
-// plane), double-buffered, so every element is converted once per workgroup
-// and the MFMA fragments are read as ready bf16 (one ds_read_b128 per
-// operand). The main loop has no branches: B is loaded even on diagonal
-// tiles, and the last, partial step of the K range reads a zero-padded copy
-// of the last columns.
-// LDS plane rows are 16 bf16 = 2 chunks of 16 B; chunk c of row r sits at
-// c ^ ((r >> 3) & 1), which makes the 16 rows a fragment read touches per
+// 128 x 64 block = 4 x 2 MFMA 32x32 accumulators. K advances SK elements per
+// step (SK = 16: one MFMA K-slice; SK = 32: two). The FP32 slabs of both row
+// panels are loaded into registers ahead of use (each lane 32 B = 8 floats of
+// a row), split once into bf16 hi (and lo) planes and stored in LDS (one
+// 16-byte store per plane), double-buffered, so every element is converted
+// once per workgroup and the MFMA fragments are read as ready bf16 (one
+// ds_read_b128 per operand). The main loop has no branches: B is loaded even
+// on diagonal tiles, and the last, partial step of the K range reads a
+// zero-padded copy of the last columns.
+//   SK = 16 prefetches two steps ahead (two register sets): each step converts
+//           data that arrived a step earlier;
+//   SK = 32 prefetches one step ahead (the registers of a second set would
+//           not fit) but touches each row of J half as often per byte, which
+//           wins when rows are far apart (a row per 2 MB page or more: the
+//           address translations, not the bytes, then bound the loads).
+// Scheduling hints interleave the conversion and its LDS stores with the
+// MFMAs. LDS plane rows are SK bf16 = SK/8 chunks of 16 B; chunk c of row r
+// sits at c ^ swizzle(r), which makes the 16 rows a fragment read touches per
 // cycle land in 16 distinct 16-byte bank groups (64 banks).
 constexpr int BT = 256;   // tile edge
-constexpr int BKE = 16;       // K elements per step (one MFMA K-slice)
-constexpr int PCH = BKE / 8;  // 16-byte bf16 chunks per plane row
-constexpr int LPR = BKE / 8;  // loading lanes per row (8 floats each)
-constexpr int NTH = 512;            // threads per workgroup
-constexpr int NQ = BT * LPR / NTH;  // rows per thread per panel and step
+constexpr int NTH = 512;  // threads per workgroup
+constexpr int SKMAX = 32;  // widest step; K-split lengths are multiples of it
+constexpr int JTS = SKMAX;  // row stride of the zero-padded copy of J's last columns
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -81,16 +86,20 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 __device__ inline unsigned int pk_bf16(float a, float b) {
   return __builtin_bit_cast(unsigned int, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
-__device__ inline int psw(int r) { return (r >> 3) & (PCH - 1); }
-// byte offset of (row r, chunk c) in a plane
-__device__ inline int poff(int r, int c) { return r * (PCH * 16) + ((c ^ psw(r)) << 4); }
+// byte offset of (row r, chunk c) in a plane of SK-element rows
+template <int SK>
+__device__ inline int poff(int r, int c) {
+  constexpr int PCH = SK / 8;
+  const int sw = (SK == 32) ? ((r >> 2) & 3) : ((r >> 3) & 1);
+  return r * (PCH * 16) + ((c ^ sw) << 4);
+}
 
 // rounding residual of the pair packed in h: (x - hi(x), y - hi(y))
 __device__ inline unsigned int pk_lo(float x, float y, unsigned int h) {
   return pk_bf16(x - __uint_as_float(h << 16), y - __uint_as_float(h & 0xffff0000u));
 }
 
-template <int PASSES>
+template <int PASSES, int SK>
 __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
                                                         const float* __restrict__ J, int64_t ldJ,
                                                         float* __restrict__ work,
@@ -100,7 +109,11 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
                                                         const float* __restrict__ Jt) {
   constexpr bool LO = (PASSES >= 3);
   constexpr bool LOLO = (PASSES == 4);
-  constexpr int PLANE = BT * PCH * 16;  // bytes per plane per stage
+  constexpr int PCH = SK / 8;              // 16-byte bf16 chunks per plane row
+  constexpr int LPR = SK / 8;              // loading lanes per row (8 floats each)
+  constexpr int NQ = BT * LPR / NTH;       // rows per thread per panel and step
+  constexpr int DEEP = (SK == 16) ? 2 : 1;  // register sets of prefetched steps
+  constexpr int PLANE = BT * PCH * 16;     // bytes per plane per stage
   // stage s: A hi, B hi, A lo, B lo
   __shared__ __attribute__((aligned(16))) char lds[2][LO ? 4 : 2][PLANE];
 
@@ -121,12 +134,11 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
   const int wave = t >> 6;
   const int wm = wave >> 2, wn = wave & 3;   // 2 x 4 waves
 
-  // load geometry: load q of a panel covers row (256 / LPR) q + t / LPR,
+  // load geometry: load q of a panel covers row (NTH / LPR) q + t / LPR,
   // floats 8 (t % LPR) .. +7 of the step. Rows beyond m read row m - 1
-  // (their K entries are discarded).
-  // The last, partial step of the K range (n % BKE columns) is read from Jt,
-  // those columns copied zero-padded to BKE (row stride BKE), so that every
-  // step is the same vector load.
+  // (their K entries are discarded). The last, partial step of the K range
+  // (n % SK columns) is read from Jt, those columns copied zero-padded (row
+  // stride JTS), so that every step is the same vector load.
   const int lch = t % LPR;                  // 8-float chunk within the step
   int lrow[NQ];
   const float* pa[NQ];
@@ -139,22 +151,22 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
     const int64_t ra_ = min(ti * BT + lrow[q], m - 1), rb_ = min(tj * BT + lrow[q], m - 1);
     pa[q] = J + ra_ * ldJ + kbeg + 8 * lch;
     pb[q] = J + rb_ * ldJ + kbeg + 8 * lch;
-    qa[q] = Jt + ra_ * BKE + 8 * lch;
-    qb[q] = Jt + rb_ * BKE + 8 * lch;
+    qa[q] = Jt + ra_ * JTS + 8 * lch;
+    qb[q] = Jt + rb_ * JTS + 8 * lch;
   }
-  // two register sets of prefetched FP32 slabs: [set][q][half]
-  float4 ra[2][NQ][2], rb[2][NQ][2];
+  // prefetched FP32 slabs: [register set][q][half]
+  float4 ra[DEEP][NQ][2], rb[DEEP][NQ][2];
   // step sidx of this split; B is loaded even on diagonal tiles (same rows,
   // L2 hits), which keeps the main loop free of branches
   const int64_t len = kend > kbeg ? kend - kbeg : 0;
-  const int64_t nfull = len / BKE;
-  const int64_t nk = nfull + ((len % BKE) != 0 ? 1 : 0);
+  const int64_t nfull = len / SK;
+  const int64_t nk = nfull + ((len % SK) != 0 ? 1 : 0);
   auto gload = [&](int rs, int64_t sidx) {
     const bool inJ = sidx < nfull;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const float* a = inJ ? pa[q] + sidx * BKE : qa[q];
-      const float* b = inJ ? pb[q] + sidx * BKE : qb[q];
+      const float* a = inJ ? pa[q] + sidx * SK : qa[q];
+      const float* b = inJ ? pb[q] + sidx * SK : qb[q];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         ra[rs][q][h] = *reinterpret_cast<const float4*>(a + 4 * h);
@@ -165,7 +177,7 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
   // split 8 floats into bf16 hi (and lo) and store one 16-byte chunk per plane
   auto put = [&](char* hp, char* lp, int r, const float4& x, const float4& y) {
     const uint4 h{pk_bf16(x.x, x.y), pk_bf16(x.z, x.w), pk_bf16(y.x, y.y), pk_bf16(y.z, y.w)};
-    const int off = poff(r, lch);
+    const int off = poff<SK>(r, lch);
     *reinterpret_cast<uint4*>(hp + off) = h;
     if (LO)
       *reinterpret_cast<uint4*>(lp + off) = uint4{pk_lo(x.x, x.y, h.x), pk_lo(x.z, x.w, h.y),
@@ -189,10 +201,10 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
 
   auto frag = [&](const char* plane, int r, int sl) -> bf16x8 {
     Chunk c;
-    c.u = *reinterpret_cast<const uint4*>(plane + poff(r, 2 * sl + (lane >> 5)));
+    c.u = *reinterpret_cast<const uint4*>(plane + poff<SK>(r, 2 * sl + (lane >> 5)));
     return c.h;
   };
-  // products of one stage; each accumulator is revisited only after the 15
+  // products of one stage; each accumulator is revisited only after the 7
   // others, so back-to-back MFMAs never wait on each other
   auto compute = [&](int st) {
     const char* Ah = lds[st][0];
@@ -200,7 +212,7 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
     const char* Al = LO ? lds[st][2] : nullptr;
     const char* Bl = LO ? lds[st][3] : nullptr;
 #pragma unroll
-    for (int sl = 0; sl < BKE / 16; ++sl) {
+    for (int sl = 0; sl < SK / 16; ++sl) {
       bf16x8 ah[4], al[4], bh[2], bl[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -241,52 +253,68 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
     }
   };
 
-  // The steps are software-pipelined two deep: while step it is multiplied
-  // from LDS stage it%2, step it+1 (loaded one step earlier, so its data has
-  // arrived) is converted into the other stage and step it+2 is in flight.
-  // The scheduling hints spread the conversion and its LDS stores over the
-  // MFMAs of the step.
-  constexpr int NMF = 8 * (1 + (LO ? 2 : 0) + (LOLO ? 1 : 0));  // MFMAs per step
-  constexpr int NDW = 2 * NQ * (LO ? 2 : 1);                   // LDS stores per step
+  constexpr int NMF = (SK / 16) * 8 * (1 + (LO ? 2 : 0) + (LOLO ? 1 : 0));  // MFMAs per step
+  constexpr int NDW = 2 * NQ * (LO ? 2 : 1);                              // LDS stores per step
+  // SK = 16: the conversion spreads over the whole step (its data arrived a
+  // step ago); SK = 32: over the second half (its loads were issued at the
+  // start of this step)
   auto hints = [&]() {
+    constexpr int FREE = (DEEP == 2) ? 0 : NMF / 2;  // leading MFMAs without conversion work
+    constexpr int PER = (NMF - FREE) / NDW;
 #pragma unroll
-    for (int i = 0; i < NMF; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
-      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two VALU
-      if (i % (NMF / NDW) == NMF / NDW - 1)
-        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // one LDS store
+    for (int i = 0; i < FREE; ++i) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+#pragma unroll
+    for (int i = 0; i < NMF - FREE; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);               // one MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, DEEP == 2 ? 2 : 4, 0);  // VALU
+      if (i % PER == PER - 1) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS store
     }
   };
   if (nk > 0) {
     int64_t it = 0;
-    gload(0, 0);
-    if (nk > 1) gload(1, 1);
-    stage_store(0, 0);
-    __syncthreads();
-    // invariant: stage 0 holds step it, register set 1 holds step it+1
-    for (; it + 3 < nk; it += 2) {
-      gload(0, it + 2);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(0);
-      stage_store(1, 1);
-      hints();
-      __syncthreads();
-      gload(1, it + 3);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(1);
+    if constexpr (DEEP == 2) {
+      gload(0, 0);
+      if (nk > 1) gload(1, 1);
       stage_store(0, 0);
-      hints();
       __syncthreads();
-    }
-    // drain the last one to three steps (stage st holds step it, register
-    // set 1 holds step it+1)
-    int st = 0;
-    for (; it < nk; ++it) {
-      compute(st);
-      if (it + 1 < nk) stage_store(1, st ^ 1);
+      // invariant: stage 0 holds step it, register set 1 holds step it+1
+      for (; it + 3 < nk; it += 2) {
+        gload(0, it + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(0);
+        stage_store(1, 1);
+        hints();
+        __syncthreads();
+        gload(1, it + 3);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(1);
+        stage_store(0, 0);
+        hints();
+        __syncthreads();
+      }
+      // drain the last one to three steps (stage st holds step it, register
+      // set 1 holds step it+1)
+      int st = 0;
+      for (; it < nk; ++it) {
+        compute(st);
+        if (it + 1 < nk) stage_store(1, st ^ 1);
+        __syncthreads();
+        if (it + 2 < nk) gload(1, it + 2);
+        st ^= 1;
+      }
+    } else {
+      gload(0, 0);
+      stage_store(0, 0);
       __syncthreads();
-      if (it + 2 < nk) gload(1, it + 2);
-      st ^= 1;
+      for (; it + 1 < nk; ++it) {
+        gload(0, it + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute((int)(it & 1));
+        stage_store(0, (int)(it & 1) ^ 1);
+        hints();
+        __syncthreads();
+      }
+      compute((int)(it & 1));
     }
   }
 
@@ -304,12 +332,12 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
       }
 }
 
-// Jt (m x BKE, row-major) = columns n0 .. n-1 of J, zero-padded to BKE columns.
+// Jt (m x JTS, row-major) = columns n0 .. n-1 of J, zero-padded to JTS columns.
 __global__ void gram_tail_kernel(int64_t m, int64_t n, int64_t n0, const float* __restrict__ J,
                                  int64_t ldJ, float* __restrict__ Jt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m * BKE) return;
-  const int64_t r = i / BKE, c = n0 + i % BKE;
+  if (i >= m * JTS) return;
+  const int64_t r = i / JTS, c = n0 + i % JTS;
   Jt[i] = c < n ? J[r * ldJ + c] : 0.0f;
 }
 
@@ -355,9 +383,14 @@ int choose_splits_f64(int64_t ntiles, int64_t n) {
 constexpr int kSplitBatch = 64;
 int64_t choose_splits_bf16(int64_t ntiles, int64_t n) {
   int64_t s = std::max<int64_t>(cdiv(n, 4096), std::min<int64_t>(cdiv(3072, ntiles), kSplitBatch));
-  s = std::min<int64_t>(s, std::max<int64_t>(1, cdiv(n, BKE)));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, cdiv(n, SKMAX)));
   return std::max<int64_t>(1, s);
 }
+
+// Step length of the bf16 kernel: 32 once a row of J spans a 2 MB page or
+// more (then each row touched costs an address translation, so fewer touches
+// per byte win), else 16 (two steps in flight).
+int gram_step_len(int64_t ldJ) { return ldJ * (int64_t)sizeof(float) >= (2 << 20) ? 32 : 16; }
 
 }  // namespace
 
@@ -371,9 +404,9 @@ size_t gram_workspace_bytes(int64_t m, int64_t n, int j_dtype, int passes, int* 
   const int64_t nt = lower_tiles(m, BT);
   const int64_t s = choose_splits_bf16(nt, n);
   if (splits_out) *splits_out = (int)s;
-  // partial tiles, then the zero-padded last columns (m x BKE)
+  // partial tiles, then the zero-padded last columns (m x JTS)
   return (size_t)std::min<int64_t>(s, kSplitBatch) * (size_t)nt * BT * BT * sizeof(float) +
-         (size_t)round_up(m * BKE * (int64_t)sizeof(float), 256);
+         (size_t)round_up(m * JTS * (int64_t)sizeof(float), 256);
 }
 
 int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ, int j_dtype,
@@ -391,9 +424,10 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
     Jt = reinterpret_cast<float*>(static_cast<char*>(work) +
                                   (size_t)std::min<int64_t>(splits, kSplitBatch) * nt * BT * BT *
                                       sizeof(float));
-    if (n % BKE != 0) {
-      hipLaunchKernelGGL(gram_tail_kernel, dim3((unsigned)cdiv(m * BKE, 256)), dim3(256), 0, st,
-                         m, n, n - n % BKE, static_cast<const float*>(J), ldJ, Jt);
+    const int sk = gram_step_len(ldJ);
+    if (n % sk != 0) {
+      hipLaunchKernelGGL(gram_tail_kernel, dim3((unsigned)cdiv(m * JTS, 256)), dim3(256), 0, st,
+                         m, n, n - n % sk, static_cast<const float*>(J), ldJ, Jt);
       DNGD_LAUNCH_CHECK();
     }
   }
@@ -417,7 +451,8 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
   DNGD_REQUIRE(passes == 1 || passes == 3 || passes == 4, "gram: passes must be 1, 3, 4 or %d",
                kGramF64);
   const int64_t nt = lower_tiles(m, BT);
-  const int64_t kps = round_up(cdiv(n, splits), BKE);
+  const int64_t kps = round_up(cdiv(n, splits), SKMAX);
+  const int sk = gram_step_len(ldJ);
   for (int64_t s0 = 0; s0 < splits; s0 += kSplitBatch) {
     const int sb = (int)std::min<int64_t>(kSplitBatch, splits - s0);
     const int64_t per_xcd = cdiv(nt * sb, NXCD);
@@ -426,14 +461,14 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
     float* w = static_cast<float*>(work);
     const float* Jf = static_cast<const float*>(J);
     if (passes == 4)
-      hipLaunchKernelGGL(gram_bf16_kernel<4>, grid, dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt,
-                         per_xcd, sb, s0, Jt);
+      hipLaunchKernelGGL((sk == 16 ? gram_bf16_kernel<4, 16> : gram_bf16_kernel<4, 32>), grid,
+                         dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt, per_xcd, sb, s0, Jt);
     else if (passes == 3)
-      hipLaunchKernelGGL(gram_bf16_kernel<3>, grid, dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt,
-                         per_xcd, sb, s0, Jt);
+      hipLaunchKernelGGL((sk == 16 ? gram_bf16_kernel<3, 16> : gram_bf16_kernel<3, 32>), grid,
+                         dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt, per_xcd, sb, s0, Jt);
     else
-      hipLaunchKernelGGL(gram_bf16_kernel<1>, grid, dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt,
-                         per_xcd, sb, s0, Jt);
+      hipLaunchKernelGGL((sk == 16 ? gram_bf16_kernel<1, 16> : gram_bf16_kernel<1, 32>), grid,
+                         dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt, per_xcd, sb, s0, Jt);
     DNGD_LAUNCH_CHECK();
     if (ev_end && s0 + sb >= splits) DNGD_HIP(hipEventRecord(ev_end, st));
     hipLaunchKernelGGL((gram_reduce_kernel<float, BT>), dim3((unsigned)nt, BT * BT / 1024),

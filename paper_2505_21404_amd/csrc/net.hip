@@ -468,14 +468,17 @@ __global__ void gather_rows_kernel(int64_t nrows, int w, const int64_t* __restri
 // Mt[q][p] (=, or += when accumulate) for points p in [p0, p0 + np) and all
 // landmarks q; Gp, Hp hold the rows of the chunk starting at jet row row0,
 // one column per landmark jet row (ld = total landmark rows).
+// lower != 0 (all points are landmarks, q = point q): write K[p0 + i][q]
+// (row-major, ldM) for q <= p0 + i only, the lower triangle.
 __global__ void nystrom_combine_kernel(RowMap rm, int64_t p0, int64_t np, int64_t row0,
                                        const double* __restrict__ Gp,
                                        const double* __restrict__ Hp, int64_t ld, int64_t ell,
                                        const int64_t* __restrict__ qoff, double* __restrict__ Mt,
-                                       int64_t ldM, int accumulate) {
+                                       int64_t ldM, int accumulate, int lower) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= np * ell) return;
   const int64_t i = e / ell, q = e % ell;  // consecutive threads: consecutive landmarks
+  if (lower && q > p0 + i) return;
   int64_t base;
   int C;
   point_rows(rm, p0 + i, base, C);
@@ -487,7 +490,7 @@ __global__ void nystrom_combine_kernel(RowMap rm, int64_t p0, int64_t np, int64_
     const double* h = Hp + (rb + c) * ld + o;
     for (int64_t c2 = 0; c2 < Cq; ++c2) sum += g[c2] * h[c2];
   }
-  double* out = Mt + q * ldM + p0 + i;
+  double* out = lower ? Mt + (p0 + i) * ldM + q : Mt + q * ldM + p0 + i;
   *out = accumulate ? *out + sum : sum;
 }
 
@@ -654,10 +657,11 @@ int net_gather_rows(hipStream_t s, int64_t nrows, int w, const int64_t* rows, co
 
 int net_nystrom_combine(hipStream_t s, const RowMap& rm, int64_t p0, int64_t np, int64_t row0,
                         const double* Gp, const double* Hp, int64_t ld, int64_t ell,
-                        const int64_t* qoff, double* Mt, int64_t ldM, int accumulate) {
+                        const int64_t* qoff, double* Mt, int64_t ldM, int accumulate,
+                        int lower) {
   if (np * ell <= 0) return 0;
   hipLaunchKernelGGL(nystrom_combine_kernel, dim3(blocks_for(np * ell)), dim3(256), 0, s, rm, p0,
-                     np, row0, Gp, Hp, ld, ell, qoff, Mt, ldM, accumulate);
+                     np, row0, Gp, Hp, ld, ell, qoff, Mt, ldM, accumulate, lower);
   DNGD_LAUNCH_CHECK();
   return 0;
 }

@@ -21,7 +21,7 @@ F64, F32 = 0, 1
 GRAM_F64 = 64   # gram_passes value: FP64-product Gram of an FP32 J
 POISSON, HEAT = 0, 1
 PLAIN, MIXED = 0, 1
-DENSE, PCG, PRIMAL, DENSE_AUTO = 0, 1, 2, 3
+DENSE, PCG, PRIMAL, DENSE_AUTO, STRUCTURED = 0, 1, 2, 3, 4
 
 _STATUS = {ENOCONV: "DNGD_ENOCONV", EINVAL: "DNGD_EINVAL", ENOMEM: "DNGD_ENOMEM", EHIP: "DNGD_EHIP",
            ENOTPD: "DNGD_ENOTPD", ENAN: "DNGD_ENAN", ETIMEOUT: "DNGD_ETIMEOUT"}

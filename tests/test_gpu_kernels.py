@@ -105,7 +105,9 @@ def test_gram_f64(m, n):
 
 
 @pytest.mark.parametrize("passes", [1, 3, 4])
-@pytest.mark.parametrize("m,n", [(70, 333), (300, 5003), (700, 20000), (300, 300001)])
+# (270, 530001): rows 2.1 MB apart, the kernel with 32-element steps
+@pytest.mark.parametrize("m,n", [(70, 333), (300, 5003), (700, 20000), (300, 300001),
+                                 (270, 530001)])
 def test_gram_bf16(m, n, passes):
     say("case gram_bf16", m, n, passes)
     rng = np.random.default_rng(m + n + passes)
