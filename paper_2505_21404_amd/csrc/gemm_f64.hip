@@ -514,7 +514,7 @@ int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64
       return launch_nt<64, kPartialFull>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
                                          splits);
     }
-    if ((cdiv(M, 128) * cdiv(N, 128)) >= 512)
+    if ((cdiv(M, 128) * cdiv(N, 128)) >= 256)
       return launch_nt<128, GEMM_FULL>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work, 1);
     return launch_nt<64, GEMM_FULL>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work, 1);
   }
