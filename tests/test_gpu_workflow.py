@@ -86,6 +86,42 @@ def test_config0_training_20_steps():
     prob.close()
 
 
+@pytest.mark.parametrize("solver", ["PRIMAL", "DENSE_AUTO", "STRUCTURED"])
+def test_iterate_with_other_dense_solvers(solver):
+    """Five iterations of the workflow (damping rule, GA step, line search,
+    update) with the primal, automatic and structured solvers (plain FP64) on
+    a problem with n < m: the loss never increases and every step matches the
+    oracle's dense step at the GPU's own iterate."""
+    d = D()
+    p = W.config(0, scale=dict(widths=[2, 16, 16, 1], n_int=300, n_bdy=100))
+    theta = torch.tensor(W.glorot_theta(p.widths, 5), device="cuda")
+    prob = d.Problem.from_workload(p)
+    assert prob.n < prob.m
+    opts = d.step_opts(precision=d.PLAIN, solver=getattr(d, solver), ga=True)
+    dbuf = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    prev = None
+    u64 = np.finfo(np.float64).eps / 2
+    for k in range(5):
+        th_k = theta.cpu().numpy().copy()
+        st = prob.iterate(theta, [2.0 ** -j for j in range(31)], lam_cap=1e-3, opts=opts,
+                          dtheta_out=dbuf)
+        ref = S.dense_step(p, th_k, st.lam, ga=True)
+        cond = np.linalg.cond(ref.K + st.lam * np.eye(p.m))
+        e = rel(dbuf.cpu().numpy(), ref.dtheta)
+        say("solver", solver, "iter", k, "loss", st.loss, "lam", st.lam, "err", e,
+            "primal", st.step.primal)
+        assert e <= max(1e-10, 100 * u64 * cond)
+        assert st.step.ga_accepted == int(ref.accepted)
+        assert st.step.primal == (1 if solver != "STRUCTURED" else 0)
+        assert st.loss_new <= st.loss * (1 + 1e-12)
+        if prev is not None:
+            assert abs(st.loss - prev) <= 1e-12 * prev
+        prev = st.loss_new
+        eta, ls = S.line_search(p, th_k, dbuf.cpu().numpy())
+        assert abs(ls.min() - st.loss_new) <= 1e-10 * ls.min()
+    prob.close()
+
+
 def test_driver_train_damping_rule():
     """driver.train with the damping rule lambda_k = min(L(theta_k), cap):
     the lambda it reports is min(loss, cap) and theta moves as recorded."""
