@@ -6,11 +6,14 @@ Two summaries are made from them:
 
   kernels  per-kernel call count, total and average duration (the
            ``--kernel-trace --stats`` view), for the top kernels of a run;
+  counters per-dispatch averages of any counters for chosen kernels, with the
+           matrix-core busy fraction when its counters are present;
   traffic  HBM bytes per dispatch of one kernel from two counter runs
            (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled by
            what the same counter reads for a device copy of known size.
 
     python -m paper_2505_21404_amd.profiling kernels DIR --cmd "..." --out FILE
+    python -m paper_2505_21404_amd.profiling counters DIR --kernels NAME... --cmd "..." --out FILE
     python -m paper_2505_21404_amd.profiling traffic --kernel NAME --source FILE \
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \
         --copy-bytes B --cmd "..." --out FILE
@@ -114,6 +117,44 @@ def traffic_summary(kernel: str, source: str, fetch: str, write: str, copy_fetch
     return "\n".join(lines) + "\n"
 
 
+def counters_summary(path: str, kernels: List[str], cmd: str, title: str, simds: int = 1024,
+                     xcds: int = 8) -> str:
+    """Per-dispatch averages of every counter in a ``--pmc`` run for the
+    kernels whose short names contain one of ``kernels``. With
+    SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE present, also the matrix-core
+    busy fraction: busy cycles summed over the ``simds`` SIMDs, divided by
+    ``simds`` times the active cycles of one XCD (GRBM_GUI_ACTIVE summed over
+    the ``xcds`` XCDs, divided by ``xcds``)."""
+    con = sqlite3.connect(_db(path))
+    rows = con.execute("select kernel_name, counter_name, value, duration from counters_collection"
+                       ).fetchall()
+    con.close()
+    agg: Dict[str, Dict[str, List[float]]] = {}
+    for k, c, v, d in rows:
+        n = short_name(k).replace("void ", "")
+        if not any(q in n for q in kernels):
+            continue
+        a = agg.setdefault(n, {})
+        a.setdefault(c, []).append(float(v))
+        a.setdefault("duration_ns", []).append(float(d))
+    lines = [f"# {title}", "", "command:", f"  {cmd}", ""]
+    for n in sorted(agg, key=lambda x: -sum(agg[x]["duration_ns"])):
+        a = agg[n]
+        nd = len(a["duration_ns"])
+        avg = {c: sum(v) / len(v) for c, v in a.items()}
+        lines.append(f"kernel: {n}")
+        lines.append(f"  counter samples: {nd}, avg duration under counters: "
+                     f"{avg['duration_ns'] / 1e3:.1f} us")
+        for c in sorted(avg):
+            if c != "duration_ns":
+                lines.append(f"  {c}: {avg[c]:.6g}")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and avg.get("GRBM_GUI_ACTIVE", 0) > 0:
+            frac = avg["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * avg["GRBM_GUI_ACTIVE"] / xcds)
+            lines.append(f"  mfma_busy_frac: {frac:.3f}")
+        lines.append("")
+    return "\n".join(lines)
+
+
 def read_traffic(path: str, repo_root: str) -> Optional[Dict[str, str]]:
     """The traffic record at ``path`` if its kernel source is unchanged,
     else None."""
@@ -140,6 +181,12 @@ def main(argv=None):
     k.add_argument("--title", default="rocprofv3 --kernel-trace --stats")
     k.add_argument("--limit", type=int, default=25)
     k.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--kernels", nargs="+", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--title", default="rocprofv3 --pmc counters per dispatch")
+    c.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     for a in ("--kernel", "--source", "--fetch", "--write", "--copy-fetch", "--copy-write",
               "--cmd", "--out"):
@@ -151,6 +198,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.what == "kernels":
         text = kernels_summary(a.dir, a.cmd, a.title, a.limit)
+    elif a.what == "counters":
+        text = counters_summary(a.dir, a.kernels, a.cmd, a.title)
     else:
         text = traffic_summary(a.kernel, a.source, a.fetch, a.write, a.copy_fetch, a.copy_write,
                                a.copy_bytes, a.cmd, a.title, a.copy_kernel,
