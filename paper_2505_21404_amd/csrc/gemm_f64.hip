@@ -196,20 +196,26 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
 // ---------------------------------------------------------------------------
 // K-contiguous operands (C = alpha A B^T + beta C, A: M x K and B: N x K both
 // row-major), the common case of every product on this path: BM x BM tiles,
-// 4 waves in a 2 x 2 grid, K advancing 16 doubles per stage. Both row panels
-// go from HBM straight into LDS (global_load_lds, 16 B per lane), double
-// buffered, rows of 8 chunks of 16 B with chunk c of row r stored at
-// c ^ ((r >> 1) & 7). Each MFMA pair takes both values of one 16-byte read: lane
-// group g = lane / 16 feeds k = k0 + 2 g to the first v_mfma_f64_16x16x4f64 and
-// k0 + 2 g + 1 to the second (the order of the k terms is a permutation).
+// 4 waves in a 2 x 2 grid, K advancing NTK doubles per stage (16, or 32 for
+// the short-K updates of the factorisation, whose time is one DMA round trip
+// per stage). Both row panels go from HBM straight into LDS (global_load_lds,
+// 16 B per lane), double buffered; a plane row holds NTK/2 chunks of 16 B,
+// chunk c of row r stored at c ^ sw(r) with sw(r) = (r >> 1) & 7 for 8 chunks
+// (two 128-byte rows share a 256-byte bank window) and r & 15 for 16 chunks,
+// so the 16 rows of a fragment read hit 16 distinct bank groups. Each MFMA
+// pair takes both values of one 16-byte read: lane group g = lane / 16 feeds
+// k = k0 + 2 g to the first v_mfma_f64_16x16x4f64 and k0 + 2 g + 1 to the
+// second (the order of the k terms is a permutation).
 // Needs lda, ldb even and 16-byte aligned A, B (the host checks).
 typedef __attribute__((address_space(3))) void lds_void_t;
-constexpr int NTK = 16;  // doubles of K per stage
+constexpr int NTK = 16;  // default doubles of K per stage
 
-__device__ inline int ntsw(int r) { return (r >> 1) & 7; }
-__device__ inline int ntoff(int r, int c) { return r * 128 + ((c ^ ntsw(r)) << 4); }
+template <int KS>
+__device__ inline int ntsw(int r) { return KS == 16 ? ((r >> 1) & 7) : (r & 15); }
+template <int KS>
+__device__ inline int ntoff(int r, int c) { return r * (KS * 8) + ((c ^ ntsw<KS>(r)) << 4); }
 
-template <int BM, int MODE>
+template <int BM, int MODE, int KS = NTK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_f64_nt_kernel(
     int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
@@ -217,8 +223,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   constexpr int BN = BM;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int JPT = BM / 32;  // DMA instructions per wave per operand per stage
-  constexpr int PLANE = BM * 128;
+  constexpr int CH = KS / 2;          // 16-byte chunks per plane row
+  constexpr int RPI = 64 / CH;        // plane rows per DMA instruction (1 KB)
+  constexpr int JPT = BM / RPI / 4;   // DMA instructions per wave per operand per stage
+  constexpr int PLANE = BM * KS * 8;
   __shared__ __attribute__((aligned(16))) char sA0[PLANE];
   __shared__ __attribute__((aligned(16))) char sB0[PLANE];
   __shared__ __attribute__((aligned(16))) char sA1[PLANE];
@@ -244,13 +252,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   const int wm = wave >> 1, wn = wave & 1;
 
   // DMA geometry: wave w, instruction j fills slots ((w JPT + j) * 64 + lane):
-  // row (w JPT + j) * 8 + lane / 8, physical chunk lane % 8 <- logical chunk
-  // (lane % 8) ^ sw(row). Rows beyond M (N) read the last row.
+  // row (w JPT + j) * RPI + lane / CH, physical chunk lane % CH <- logical chunk
+  // (lane % CH) ^ sw(row). Rows beyond M (N) read the last row.
   auto dma = [&](int64_t k0, char* dA, char* dB) {
 #pragma unroll
     for (int j = 0; j < JPT; ++j) {
-      const int r = (wave * JPT + j) * 8 + (lane >> 3);
-      const int64_t k = k0 + 2 * ((lane & 7) ^ ntsw(r));
+      const int r = (wave * JPT + j) * RPI + lane / CH;
+      const int64_t k = k0 + 2 * ((lane % CH) ^ ntsw<KS>(r));
       const int64_t kk = (k < K) ? k : 0;  // in bounds; k >= kend is masked at the read
       __builtin_amdgcn_global_load_lds(A + min(m0 + r, M - 1) * lda + kk,
                                        (lds_void_t*)(dA + (wave * JPT + j) * 1024), 16, 0, 0);
@@ -268,9 +276,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 
   const int g = lane >> 4;
   auto compute = [&](const char* SA, const char* SB, int64_t k0) {
-    const bool tail = (k0 + NTK > kend);
+    const bool tail = (k0 + KS > kend);
 #pragma unroll
-    for (int kp = 0; kp < NTK / 8; ++kp) {
+    for (int kp = 0; kp < KS / 8; ++kp) {
       const int c = kp * 4 + g;  // logical chunk: k = k0 + 2 c, 2 c + 1
       bool ok0 = true, ok1 = true;
       if (tail) {
@@ -280,13 +288,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
       double2 a[TM], b[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        a[i] = *reinterpret_cast<const double2*>(SA + ntoff(wm * WM + i * 16 + (lane & 15), c));
+        a[i] = *reinterpret_cast<const double2*>(SA + ntoff<KS>(wm * WM + i * 16 + (lane & 15), c));
         if (!ok0) a[i].x = 0.0;
         if (!ok1) a[i].y = 0.0;
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        b[j] = *reinterpret_cast<const double2*>(SB + ntoff(wn * WN + j * 16 + (lane & 15), c));
+        b[j] = *reinterpret_cast<const double2*>(SB + ntoff<KS>(wn * WN + j * 16 + (lane & 15), c));
         if (!ok0) b[j].x = 0.0;
         if (!ok1) b[j].y = 0.0;
       }
@@ -303,18 +311,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     }
   };
 
-  const int64_t nk = (kend > kbeg) ? (kend - kbeg + NTK - 1) / NTK : 0;
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg + KS - 1) / KS : 0;
   if (nk > 0) dma(kbeg, sA0, sB0);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   for (int64_t it = 0; it < nk; it += 2) {
-    if (it + 1 < nk) dma(kbeg + (it + 1) * NTK, sA1, sB1);
-    compute(sA0, same ? sA0 : sB0, kbeg + it * NTK);
+    if (it + 1 < nk) dma(kbeg + (it + 1) * KS, sA1, sB1);
+    compute(sA0, same ? sA0 : sB0, kbeg + it * KS);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (it + 1 < nk) {
-      if (it + 2 < nk) dma(kbeg + (it + 2) * NTK, sA0, sB0);
-      compute(sA1, same ? sA1 : sB1, kbeg + (it + 1) * NTK);
+      if (it + 2 < nk) dma(kbeg + (it + 2) * KS, sA0, sB0);
+      compute(sA1, same ? sA1 : sB1, kbeg + (it + 1) * KS);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
     }
@@ -452,27 +460,27 @@ namespace {
 constexpr size_t kLdsPerCu = 160 * 1024;
 constexpr size_t kOnePerCuLds = 90 * 1024;
 
-template <int BM, int MODE>
+template <int BM, int MODE, int KS = NTK>
 int launch_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
               double* work, int splits, bool one_per_cu = false) {
   static_assert(2 * kOnePerCuLds > kLdsPerCu, "one workgroup per CU");
-  const size_t static_lds = 4 * (size_t)BM * 128;
+  const size_t static_lds = 4 * (size_t)BM * KS * 8;
   const size_t dyn = one_per_cu && kOnePerCuLds > static_lds ? kOnePerCuLds - static_lds : 0;
   dim3 grid;
   int64_t ntiles = 0, kps = K;
   if (MODE == GEMM_FULL || MODE == GEMM_FULL_LOWER) {
     grid = dim3((unsigned)cdiv(M, BM), (unsigned)cdiv(N, BM), 1);
   } else if (MODE == kPartialFull) {
-    kps = round_up(cdiv(K, splits), NTK);
+    kps = round_up(cdiv(K, splits), KS);
     grid = dim3((unsigned)cdiv(M, BM), (unsigned)cdiv(N, BM), (unsigned)splits);
   } else {
     ntiles = lower_tiles(M, BM);
-    kps = (MODE == GEMM_PARTIAL_LOWER) ? round_up(cdiv(K, splits), NTK) : K;
+    kps = (MODE == GEMM_PARTIAL_LOWER) ? round_up(cdiv(K, splits), KS) : K;
     grid = dim3((unsigned)ntiles, (MODE == GEMM_PARTIAL_LOWER) ? (unsigned)splits : 1u, 1);
   }
   if (grid.x == 0 || grid.y == 0) return 0;
-  hipLaunchKernelGGL((gemm_f64_nt_kernel<BM, MODE>), grid, dim3(256), (unsigned)dyn, s, M, N, K,
+  hipLaunchKernelGGL((gemm_f64_nt_kernel<BM, MODE, KS>), grid, dim3(256), (unsigned)dyn, s, M, N, K,
                      alpha, A, lda, B, ldb, beta, C, ldc, work, kps, ntiles);
   DNGD_LAUNCH_CHECK();
   if (MODE == kPartialFull) {
@@ -499,9 +507,9 @@ int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64
     if (mode == GEMM_PARTIAL_LOWER)
       return launch_nt<128, GEMM_PARTIAL_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
                                                 work, splits);
-    if (mode == GEMM_FULL_LOWER)
-      return launch_nt<64, GEMM_FULL_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                                            work, 1);
+    if (mode == GEMM_FULL_LOWER)  // short-K factorisation updates: 32 per stage
+      return launch_nt<64, GEMM_FULL_LOWER, 32>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                work, 1);
     if (mode == GEMM_SYRK_LOWER) {
       if (M >= 1024)
         return launch_nt<128, GEMM_SYRK_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
