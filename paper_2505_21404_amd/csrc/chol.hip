@@ -22,6 +22,11 @@ namespace dngd {
 namespace {
 
 constexpr int NB = 64;
+#ifndef DNGD_SIDE_FREE_EXTRA
+#define DNGD_SIDE_FREE_EXTRA 0
+#endif
+// CUs kept free of the look-ahead's trailing update beyond one per panel workgroup
+constexpr int kSideFreeExtra = DNGD_SIDE_FREE_EXTRA;
 
 // Grouped right-to-left elimination of one 64-wide panel, 8 columns at a
 // time. For group g (columns c0 .. c0+7):
@@ -417,14 +422,21 @@ int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo
   // Block columns of width NB2 = 4 NB. Inside one, each 64-wide panel is
   // factored (diagonal block + the rows below) and applied to the remaining
   // columns of the same block column. The block column's update of the
-  // trailing matrix is split in two: the next block column (on `s`, needed
-  // by the next panels) and the rest (on `side` when given, overlapping the
-  // next block column's panels: look-ahead of one block). The two updates
-  // touch disjoint columns; `s` waits for the side update of block b before
-  // it updates block b + 2's columns itself.
+  // trailing matrix is split: the next block column (on `s`, needed by the
+  // next panels) and the rest (on `side` when given, overlapping the next
+  // block columns' panels). The side stream updates block b + 2's columns
+  // first and records ev_trail; `s` waits for that before it updates block
+  // b + 2's columns itself. The remainder (block b + 3 on) is done before
+  // the side stream's next update, which `s` waits for in turn.
   constexpr int NB2 = 4 * NB;
   const bool ahead = side != nullptr && ev_panel != nullptr && ev_trail != nullptr;
-  bool side_busy = false;
+  bool side_busy = false, side_used = false;
+  int ncu = 0;
+  if (ahead) {
+    int dev = 0;
+    DNGD_HIP(hipGetDevice(&dev));
+    DNGD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  }
   hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, dinfo, (int64_t)0);
   DNGD_LAUNCH_CHECK();
   for (int64_t jb = 0; jb < m; jb += NB2) {
@@ -455,31 +467,46 @@ int chol_factor(hipStream_t s, int64_t m, double* K, int64_t ldK, int64_t* dinfo
       if (rc) return rc;
       continue;
     }
-    // (i) the next block column, rows jend..m (lower part), on s; it overlaps
-    //     the previous side update's region, so wait for that first
+    // (i) the next block column, rows jend..m (lower part), on s; the
+    //     previous side update covered its columns first, so wait for that
     if (side_busy) DNGD_HIP(hipStreamWaitEvent(s, ev_trail, 0));
     const int64_t nxt = std::min<int64_t>(NB2, rest);
     int rc = gemm_f64(s, GEMM_FULL_LOWER, true, true, rest, nxt, kb, -1.0, L21, ldK, L21, ldK,
                       1.0, A22, ldK);
     if (rc) return rc;
     // (ii) everything right of it, on the side stream once this block's
-    //      panels are final
+    //      panels are final: first the block column after next (what s
+    //      waits for before its next update there), then the remainder
     const int64_t r2 = rest - nxt;
     if (r2 > 0) {
       DNGD_HIP(hipEventRecord(ev_panel, s));
       DNGD_HIP(hipStreamWaitEvent(side, ev_panel, 0));
-      // at most one of its workgroups per CU, so the panels and updates of
-      // the next block column on `s` find room on every CU
-      rc = gemm_f64(side, GEMM_SYRK_LOWER, true, true, r2, r2, kb, -1.0, L21 + nxt * ldK, ldK,
-                    L21 + nxt * ldK, ldK, 1.0, A22 + nxt * ldK + nxt, ldK, nullptr, 1, true);
+      const int64_t nx2 = std::min<int64_t>(NB2, r2);
+      rc = gemm_f64(side, GEMM_FULL_LOWER, true, true, r2, nx2, kb, -1.0, L21 + nxt * ldK, ldK,
+                    L21 + nxt * ldK, ldK, 1.0, A22 + nxt * ldK + nxt, ldK);
       if (rc) return rc;
       DNGD_HIP(hipEventRecord(ev_trail, side));
-      side_busy = true;
+      side_busy = side_used = true;
+      const int64_t r3 = r2 - nx2, o3 = nxt + nx2;
+      if (r3 > 0) {
+        // on CUs of its own: the FP64 VALU chain of a panel workgroup runs
+        // at half speed beside an update workgroup, so the remainder leaves
+        // one CU free per workgroup of the next panel (plus kSideFreeExtra),
+        // where the next block columns' panels and in-block updates run
+        const int64_t busy = cdiv(rest, NB) + kSideFreeExtra;
+        const int own = (int)std::max<int64_t>(ncu / 2, ncu - busy);
+        rc = gemm_f64(side, GEMM_SYRK_LOWER, true, true, r3, r3, kb, -1.0, L21 + o3 * ldK, ldK,
+                      L21 + o3 * ldK, ldK, 1.0, A22 + o3 * ldK + o3, ldK, nullptr, 1, own);
+        if (rc) return rc;
+      }
     } else {
       side_busy = false;
     }
   }
-  if (ahead && side_busy) DNGD_HIP(hipStreamWaitEvent(s, ev_trail, 0));
+  if (side_used) {  // everything on the side stream, the last remainder included
+    DNGD_HIP(hipEventRecord(ev_trail, side));
+    DNGD_HIP(hipStreamWaitEvent(s, ev_trail, 0));
+  }
   hipLaunchKernelGGL(diag_writeback_kernel, dim3((unsigned)cdiv(m, NB)), dim3(256), 0, s, m, K,
                      ldK, work);
   DNGD_LAUNCH_CHECK();

@@ -97,13 +97,14 @@ enum GemmMode {
 // C[m*ldc + n] = alpha * sum_k opA[m][k] opB[n][k] + beta * C  (GEMM_FULL)
 // GEMM_SYRK_LOWER: only tiles/elements with m >= n (square M == N).
 // GEMM_PARTIAL_LOWER: lower tiles, split-K; tile partials to `work`.
-// one_per_cu (K-contiguous SYRK): the kernel reserves enough LDS that at most one of
-// its workgroups is resident per CU, which leaves room on every CU for the
-// workgroups of latency-bound kernels running beside it on another stream.
+// own_cus > 0 (K-contiguous SYRK): a persistent launch of at most own_cus
+// workgroups, each reserving a whole CU's LDS, so no other workgroup shares
+// their CUs; the remaining CUs stay free for latency-bound kernels running
+// beside it on another stream.
 int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
              int64_t K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
              double beta, double* C, int64_t ldc, double* work = nullptr, int splits = 1,
-             bool one_per_cu = false);
+             int own_cus = 0);
 
 // Batched GEMM_FULL: matrix z = (z / n_inner, z % n_inner) starts at
 // A + zo * a_out + zi * a_in (likewise B, C); n_outer * n_inner matrices.

@@ -215,6 +215,10 @@ __device__ inline int ntsw(int r) { return KS == 16 ? ((r >> 1) & 7) : (r & 15);
 template <int KS>
 __device__ inline int ntoff(int r, int c) { return r * (KS * 8) + ((c ^ ntsw<KS>(r)) << 4); }
 
+// (waves_per_eu caps the VGPRs at 256 so that two workgroups fit a CU; the
+// CU-owning SYRK instance cannot have two for its LDS, and says so)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wpass-failed"
 template <int BM, int MODE, int KS = NTK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_f64_nt_kernel(
     int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
@@ -233,126 +237,134 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   __shared__ __attribute__((aligned(16))) char sB1[PLANE];
 
   constexpr bool PARTIAL = (MODE == GEMM_PARTIAL_LOWER || MODE == kPartialFull);
-  int64_t tm, tn;
-  if (MODE == GEMM_FULL || MODE == kPartialFull || MODE == GEMM_FULL_LOWER) {
-    tm = blockIdx.x;
-    tn = blockIdx.y;
-  } else {
-    tri_decode(blockIdx.x, tm, tn);
-  }
-  const int64_t m0 = tm * BM, n0 = tn * BN;
-  const int split = (MODE == GEMM_PARTIAL_LOWER) ? blockIdx.y : ((MODE == kPartialFull) ? blockIdx.z : 0);
-  const int64_t kbeg = PARTIAL ? (int64_t)split * k_per_split : 0;
-  const int64_t kend = PARTIAL ? min(K, kbeg + k_per_split) : K;
-  // the B panel is the A panel (a diagonal tile of a symmetric product)
-  const bool same = (A == B) && (lda == ldb) && (m0 == n0);
-
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-
-  // DMA geometry: wave w, instruction j fills slots ((w JPT + j) * 64 + lane):
-  // row (w JPT + j) * RPI + lane / CH, physical chunk lane % CH <- logical chunk
-  // (lane % CH) ^ sw(row). Rows beyond M (N) read the last row.
-  auto dma = [&](int64_t k0, char* dA, char* dB) {
-#pragma unroll
-    for (int j = 0; j < JPT; ++j) {
-      const int r = (wave * JPT + j) * RPI + lane / CH;
-      const int64_t k = k0 + 2 * ((lane % CH) ^ ntsw<KS>(r));
-      const int64_t kk = (k < K) ? k : 0;  // in bounds; k >= kend is masked at the read
-      __builtin_amdgcn_global_load_lds(A + min(m0 + r, M - 1) * lda + kk,
-                                       (lds_void_t*)(dA + (wave * JPT + j) * 1024), 16, 0, 0);
-      if (!same)
-        __builtin_amdgcn_global_load_lds(B + min(n0 + r, N - 1) * ldb + kk,
-                                         (lds_void_t*)(dB + (wave * JPT + j) * 1024), 16, 0, 0);
+  // A SYRK launch with fewer workgroups than tiles is persistent: workgroup b
+  // takes tiles b, b + gridDim.x, ... (the main loop ends on a barrier, so the
+  // LDS planes are free for the next tile). Every other launch: one tile.
+  for (int64_t bx = blockIdx.x;; bx += gridDim.x) {
+    if (MODE == GEMM_SYRK_LOWER && bx >= ntiles) break;
+    int64_t tm, tn;
+    if (MODE == GEMM_FULL || MODE == kPartialFull || MODE == GEMM_FULL_LOWER) {
+      tm = bx;
+      tn = blockIdx.y;
+    } else {
+      tri_decode(bx, tm, tn);
     }
-  };
+    const int64_t m0 = tm * BM, n0 = tn * BN;
+    const int split = (MODE == GEMM_PARTIAL_LOWER) ? blockIdx.y : ((MODE == kPartialFull) ? blockIdx.z : 0);
+    const int64_t kbeg = PARTIAL ? (int64_t)split * k_per_split : 0;
+    const int64_t kend = PARTIAL ? min(K, kbeg + k_per_split) : K;
+    // the B panel is the A panel (a diagonal tile of a symmetric product)
+    const bool same = (A == B) && (lda == ldb) && (m0 == n0);
 
-  f64x4 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
 
-  const int g = lane >> 4;
-  auto compute = [&](const char* SA, const char* SB, int64_t k0) {
-    const bool tail = (k0 + KS > kend);
+    // DMA geometry: wave w, instruction j fills slots ((w JPT + j) * 64 + lane):
+    // row (w JPT + j) * RPI + lane / CH, physical chunk lane % CH <- logical chunk
+    // (lane % CH) ^ sw(row). Rows beyond M (N) read the last row.
+    auto dma = [&](int64_t k0, char* dA, char* dB) {
 #pragma unroll
-    for (int kp = 0; kp < KS / 8; ++kp) {
-      const int c = kp * 4 + g;  // logical chunk: k = k0 + 2 c, 2 c + 1
-      bool ok0 = true, ok1 = true;
-      if (tail) {
-        ok0 = k0 + 2 * c < kend;
-        ok1 = k0 + 2 * c + 1 < kend;
+      for (int j = 0; j < JPT; ++j) {
+        const int r = (wave * JPT + j) * RPI + lane / CH;
+        const int64_t k = k0 + 2 * ((lane % CH) ^ ntsw<KS>(r));
+        const int64_t kk = (k < K) ? k : 0;  // in bounds; k >= kend is masked at the read
+        __builtin_amdgcn_global_load_lds(A + min(m0 + r, M - 1) * lda + kk,
+                                         (lds_void_t*)(dA + (wave * JPT + j) * 1024), 16, 0, 0);
+        if (!same)
+          __builtin_amdgcn_global_load_lds(B + min(n0 + r, N - 1) * ldb + kk,
+                                           (lds_void_t*)(dB + (wave * JPT + j) * 1024), 16, 0, 0);
       }
-      double2 a[TM], b[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        a[i] = *reinterpret_cast<const double2*>(SA + ntoff<KS>(wm * WM + i * 16 + (lane & 15), c));
-        if (!ok0) a[i].x = 0.0;
-        if (!ok1) a[i].y = 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        b[j] = *reinterpret_cast<const double2*>(SB + ntoff<KS>(wn * WN + j * 16 + (lane & 15), c));
-        if (!ok0) b[j].x = 0.0;
-        if (!ok1) b[j].y = 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc[i][j], 0, 0, 0);
-    }
-  };
+    };
 
-  const int64_t nk = (kend > kbeg) ? (kend - kbeg + KS - 1) / KS : 0;
-  if (nk > 0) dma(kbeg, sA0, sB0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  for (int64_t it = 0; it < nk; it += 2) {
-    if (it + 1 < nk) dma(kbeg + (it + 1) * KS, sA1, sB1);
-    compute(sA0, same ? sA0 : sB0, kbeg + it * KS);
+    f64x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    const int g = lane >> 4;
+    auto compute = [&](const char* SA, const char* SB, int64_t k0) {
+      const bool tail = (k0 + KS > kend);
+#pragma unroll
+      for (int kp = 0; kp < KS / 8; ++kp) {
+        const int c = kp * 4 + g;  // logical chunk: k = k0 + 2 c, 2 c + 1
+        bool ok0 = true, ok1 = true;
+        if (tail) {
+          ok0 = k0 + 2 * c < kend;
+          ok1 = k0 + 2 * c + 1 < kend;
+        }
+        double2 a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          a[i] = *reinterpret_cast<const double2*>(SA + ntoff<KS>(wm * WM + i * 16 + (lane & 15), c));
+          if (!ok0) a[i].x = 0.0;
+          if (!ok1) a[i].y = 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          b[j] = *reinterpret_cast<const double2*>(SB + ntoff<KS>(wn * WN + j * 16 + (lane & 15), c));
+          if (!ok0) b[j].x = 0.0;
+          if (!ok1) b[j].y = 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc[i][j], 0, 0, 0);
+      }
+    };
+
+    const int64_t nk = (kend > kbeg) ? (kend - kbeg + KS - 1) / KS : 0;
+    if (nk > 0) dma(kbeg, sA0, sB0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (it + 1 < nk) {
-      if (it + 2 < nk) dma(kbeg + (it + 2) * KS, sA0, sB0);
-      compute(sA1, same ? sA1 : sB1, kbeg + (it + 1) * KS);
+    for (int64_t it = 0; it < nk; it += 2) {
+      if (it + 1 < nk) dma(kbeg + (it + 1) * KS, sA1, sB1);
+      compute(sA0, same ? sA0 : sB0, kbeg + it * KS);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
+      if (it + 1 < nk) {
+        if (it + 2 < nk) dma(kbeg + (it + 2) * KS, sA0, sB0);
+        compute(sA1, same ? sA1 : sB1, kbeg + (it + 1) * KS);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+      }
     }
-  }
 
-  // epilogue as in gemm_f64_kernel: element v of tile (i, j) is C[row][col]
-  // with row = 16 i + lane / 16 + 4 v, col = 16 j + lane % 16 (wave-relative)
+    // epilogue as in gemm_f64_kernel: element v of tile (i, j) is C[row][col]
+    // with row = 16 i + lane / 16 + 4 v, col = 16 j + lane % 16 (wave-relative)
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rl = wm * WM + i * 16 + (lane >> 4) + 4 * v;
-        const int cl = wn * WN + j * 16 + (lane & 15);
-        const double x = acc[i][j][v];
-        if (MODE == GEMM_PARTIAL_LOWER) {
-          work[(((int64_t)split * ntiles + blockIdx.x) * BM + rl) * BN + cl] = x;
-        } else if (MODE == kPartialFull) {
-          const int64_t tile = ((int64_t)split * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-          work[(tile * BM + rl) * BN + cl] = x;
-        } else {
-          const int64_t row = m0 + rl, col = n0 + cl;
-          if (row < M && col < N && (MODE == GEMM_FULL || row >= col)) {
-            double* p = C + row * ldc + col;
-            *p = (beta == 0.0) ? alpha * x : alpha * x + beta * *p;
+        for (int v = 0; v < 4; ++v) {
+          const int rl = wm * WM + i * 16 + (lane >> 4) + 4 * v;
+          const int cl = wn * WN + j * 16 + (lane & 15);
+          const double x = acc[i][j][v];
+          if (MODE == GEMM_PARTIAL_LOWER) {
+            work[(((int64_t)split * ntiles + bx) * BM + rl) * BN + cl] = x;
+          } else if (MODE == kPartialFull) {
+            const int64_t tile = ((int64_t)split * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            work[(tile * BM + rl) * BN + cl] = x;
+          } else {
+            const int64_t row = m0 + rl, col = n0 + cl;
+            if (row < M && col < N && (MODE == GEMM_FULL || row >= col)) {
+              double* p = C + row * ldc + col;
+              *p = (beta == 0.0) ? alpha * x : alpha * x + beta * *p;
+            }
           }
         }
-      }
+    if (MODE != GEMM_SYRK_LOWER) break;
+  }
 }
+#pragma clang diagnostic pop
 
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_reduce_full_kernel(int64_t M, int64_t N, int splits,
@@ -455,18 +467,17 @@ int64_t lower_tiles(int64_t M, int tile) {
 
 namespace {
 
-// LDS of one CU; a launch that asks for more than half of it (with its static
-// arrays) gets at most one workgroup per CU
+// LDS of one CU: a workgroup that reserves all of it (static arrays plus
+// dynamic LDS) has its CU to itself
 constexpr size_t kLdsPerCu = 160 * 1024;
-constexpr size_t kOnePerCuLds = 90 * 1024;
 
 template <int BM, int MODE, int KS = NTK>
 int launch_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-              double* work, int splits, bool one_per_cu = false) {
-  static_assert(2 * kOnePerCuLds > kLdsPerCu, "one workgroup per CU");
+              double* work, int splits, int own_cus = 0) {
   const size_t static_lds = 4 * (size_t)BM * KS * 8;
-  const size_t dyn = one_per_cu && kOnePerCuLds > static_lds ? kOnePerCuLds - static_lds : 0;
+  static_assert(4 * (size_t)BM * KS * 8 <= kLdsPerCu, "LDS planes exceed a CU");
+  const size_t dyn = own_cus > 0 ? kLdsPerCu - static_lds : 0;
   dim3 grid;
   int64_t ntiles = 0, kps = K;
   if (MODE == GEMM_FULL || MODE == GEMM_FULL_LOWER) {
@@ -480,6 +491,10 @@ int launch_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, cons
     grid = dim3((unsigned)ntiles, (MODE == GEMM_PARTIAL_LOWER) ? (unsigned)splits : 1u, 1);
   }
   if (grid.x == 0 || grid.y == 0) return 0;
+  if (own_cus > 0) {  // persistent: as few workgroups as the same number of rounds needs
+    const int64_t rounds = cdiv(grid.x, own_cus);
+    grid.x = (unsigned)cdiv(grid.x, rounds);
+  }
   hipLaunchKernelGGL((gemm_f64_nt_kernel<BM, MODE, KS>), grid, dim3(256), (unsigned)dyn, s, M, N, K,
                      alpha, A, lda, B, ldb, beta, C, ldc, work, kps, ntiles);
   DNGD_LAUNCH_CHECK();
@@ -501,7 +516,7 @@ bool nt_ok(const double* A, int64_t lda, const double* B, int64_t ldb) {
 
 int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64_t M, int64_t N,
              int64_t K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-             double beta, double* C, int64_t ldc, double* work, int splits, bool one_per_cu) {
+             double beta, double* C, int64_t ldc, double* work, int splits, int own_cus) {
   if (M <= 0 || N <= 0) return 0;
   if (a_kcontig && b_kcontig && nt_ok(A, lda, B, ldb)) {
     if (mode == GEMM_PARTIAL_LOWER)
@@ -511,11 +526,15 @@ int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64
       return launch_nt<64, GEMM_FULL_LOWER, 32>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
                                                 work, 1);
     if (mode == GEMM_SYRK_LOWER) {
+      // a workgroup that owns its CU has the LDS for 32 doubles of K per stage
+      if (M >= 1024 && own_cus > 0)
+        return launch_nt<128, GEMM_SYRK_LOWER, 32>(s, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                   ldc, work, 1, own_cus);
       if (M >= 1024)
         return launch_nt<128, GEMM_SYRK_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                                               work, 1, one_per_cu);
+                                               work, 1);
       return launch_nt<64, GEMM_SYRK_LOWER>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
-                                            1, one_per_cu);
+                                            1, own_cus);
     }
     if (splits > 1) {
       DNGD_REQUIRE(work != nullptr, "gemm_f64: split-K needs a workspace");
