@@ -121,28 +121,24 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(int64_t m, double* __r
   // ---- load the diagonal block (identity padding beyond m) and this
   //      workgroup's rows of the panel, coalesced
   {
-    double v[16];
+    // every load unconditional, from a clamped in-bounds address, and both
+    // blocks' loads in flight together (a conditional load is waited for
+    // before the next one is issued); workgroup 0 reads its X rows (the
+    // diagonal block's) and drops them
+    double v[16], w[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int e = q * 256 + t, i = e / NB, k = e % NB;
-      v[q] = (i < nb && k <= i) ? K[(j0 + i) * ldK + j0 + k] : ((i >= nb && k == i) ? 1.0 : 0.0);
+      v[q] = K[(j0 + min(i, nb - 1)) * ldK + j0 + min(k, nb - 1)];
+      w[q] = K[min(r0 + i, m - 1) * ldK + j0 + min(k, nb - 1)];
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int e = q * 256 + t;
-      Ld[e / NB][e % NB] = v[q];
-    }
-    if (has_x) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int e = q * 256 + t, i = e / NB, k = e % NB;
-        v[q] = (r0 + i < m && k < nb) ? K[(r0 + i) * ldK + j0 + k] : 0.0;
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int e = q * 256 + t;
-        X[e / NB][e % NB] = v[q];
-      }
+      const int e = q * 256 + t, i = e / NB, k = e % NB;
+      if (!(i < nb && k <= i)) v[q] = (i >= nb && k == i) ? 1.0 : 0.0;
+      if (!(r0 + i < m && k < nb)) w[q] = 0.0;
+      Ld[i][k] = v[q];
+      if (has_x) X[i][k] = w[q];
     }
   }
   __syncthreads();
