@@ -80,29 +80,32 @@ __global__ __launch_bounds__(256) void gemv_n_kernel(int64_t m, int64_t n, const
   double acc[GN_ROWS];
 #pragma unroll
   for (int q = 0; q < GN_ROWS; ++q) acc[q] = 0.0;
+  // all loads of an iteration unconditional (rows beyond m read row m - 1 and
+  // are dropped at the end): a conditional load is waited for before the
+  // next one is issued
   for (int64_t k = (int64_t)threadIdx.x * 4; k < n; k += 1024) {
-    double tv[4];
-    const bool full = (k + 3 < n);
-    if (full) {
+    double tv[4], v[GN_ROWS][4];
+    if (k + 3 < n) {
       Vec4<double>::load(t + k, tv);
+#pragma unroll
+      for (int q = 0; q < GN_ROWS; ++q) Vec4<T>::load(J + min(row0 + q, m - 1) * ldJ + k, v[q]);
     } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) tv[e] = (k + e < n) ? t[k + e] : 0.0;
-    }
+      for (int e = 0; e < 4; ++e) {
+        const int64_t kc = min(k + e, n - 1);
+        tv[e] = t[kc];
 #pragma unroll
-    for (int q = 0; q < GN_ROWS; ++q) {
-      const int64_t row = row0 + q;
-      if (row < m) {
-        double v[4];
-        if (full) {
-          Vec4<T>::load(J + row * ldJ + k, v);
-        } else {
+        for (int q = 0; q < GN_ROWS; ++q) v[q][e] = (double)J[min(row0 + q, m - 1) * ldJ + kc];
+        if (k + e >= n) {
+          tv[e] = 0.0;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (k + e < n) ? (double)J[row * ldJ + k + e] : 0.0;
+          for (int q = 0; q < GN_ROWS; ++q) v[q][e] = 0.0;
         }
-        acc[q] += v[0] * tv[0] + v[1] * tv[1] + v[2] * tv[2] + v[3] * tv[3];
       }
     }
+#pragma unroll
+    for (int q = 0; q < GN_ROWS; ++q)
+      acc[q] += v[q][0] * tv[0] + v[q][1] * tv[1] + v[q][2] * tv[2] + v[q][3] * tv[3];
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll

@@ -324,20 +324,23 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t M, int64_t K,
   double acc[GR_ROWS];
 #pragma unroll
   for (int q = 0; q < GR_ROWS; ++q) acc[q] = 0.0;
+  // loads are unconditional, from clamped in-bounds addresses, and masked
+  // afterwards (a conditional load is waited for before the next one)
   for (int64_t k0 = 0; k0 < K; k0 += 1024) {
     const int64_t k = k0 + (int64_t)threadIdx.x * 4;
-    double xv[4];
+    double xv[4], av[GR_ROWS][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) xv[e] = (k + e < K) ? x[k + e] : 0.0;
+    for (int e = 0; e < 4; ++e) xv[e] = x[min(k + e, K - 1)];
 #pragma unroll
-    for (int q = 0; q < GR_ROWS; ++q) {
-      if (r0 + q < M) {
-        const double* a = A + (r0 + q) * lda + k;
+    for (int q = 0; q < GR_ROWS; ++q)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (k + e < K) acc[q] += a[e] * xv[e];
+      for (int e = 0; e < 4; ++e) av[q][e] = A[min(r0 + q, M - 1) * lda + min(k + e, K - 1)];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (k + e < K) {
+#pragma unroll
+        for (int q = 0; q < GR_ROWS; ++q) acc[q] += av[q][e] * xv[e];
       }
-    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll

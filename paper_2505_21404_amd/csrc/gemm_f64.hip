@@ -23,6 +23,39 @@ constexpr int KS = 16;  // K step
 constexpr int kPartialFull = 3;  // split-K full GEMM: tile partials, then gemm_reduce_full
 constexpr int kBatched = 5;      // full GEMM over a batch of matrices (blockIdx.z)
 
+// C[row][col] = alpha x + beta C[row][col] for one wave's TM x TN accumulator
+// tiles: element v of tile (i, j) sits at row = r0 + 16 i + 4 v, col = c0 + 16 j
+// (r0, c0 carry the wave's and the lane's offsets). Elements outside M x N,
+// or above the diagonal when `lower`, are left alone. With beta != 0 the C
+// values of one tile row are read together, unconditionally from clamped
+// in-bounds addresses (a conditional load is waited for before the next one
+// is issued); beta == 0 reads nothing.
+template <int TM, int TN>
+__device__ inline void store_c(const f64x4 (&acc)[TM][TN], int64_t M, int64_t N, double alpha,
+                               double beta, double* __restrict__ C, int64_t ldc, int64_t r0,
+                               int64_t c0, bool lower) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    double old[TN][4];
+    if (beta != 0.0) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          old[j][v] = C[min(r0 + 16 * i + 4 * v, M - 1) * ldc + min(c0 + 16 * j, N - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + 16 * i + 4 * v, col = c0 + 16 * j;
+        if (row < M && col < N && (!lower || row >= col))
+          C[row * ldc + col] =
+              (beta == 0.0) ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * old[j][v];
+      }
+  }
+}
+
 __device__ inline void tri_decode(int64_t t, int64_t& i, int64_t& j) {
   int64_t ii = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
@@ -168,29 +201,27 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
   // epilogue: accumulator element v of tile (i, j) is C[row][col] with
   // row = 16 i + lane / 16 + 4 v, col = 16 j + lane % 16 (wave-relative;
   // lane layout of v_mfma_f64_16x16x4f64 checked on the device)
+  if (MODE == GEMM_PARTIAL_LOWER || MODE == kPartialFull) {
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rl = wm * WM + i * 16 + (lane >> 4) + 4 * v;
-        const int cl = wn * WN + j * 16 + (lane & 15);
-        const double x = acc[i][j][v];
-        if (MODE == GEMM_PARTIAL_LOWER) {
-          work[(((int64_t)split * ntiles + blockIdx.x) * BM + rl) * BN + cl] = x;
-        } else if (MODE == kPartialFull) {
-          const int64_t tile = ((int64_t)split * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-          work[(tile * BM + rl) * BN + cl] = x;
-        } else {
-          const int64_t row = m0 + rl, col = n0 + cl;
-          if (row < M && col < N &&
-              (MODE == GEMM_FULL || MODE == kBatched || row >= col)) {  // *_LOWER: row >= col
-            double* p = C + row * ldc + col;
-            *p = (beta == 0.0) ? alpha * x : alpha * x + beta * *p;
+        for (int v = 0; v < 4; ++v) {
+          const int rl = wm * WM + i * 16 + (lane >> 4) + 4 * v;
+          const int cl = wn * WN + j * 16 + (lane & 15);
+          const double x = acc[i][j][v];
+          if (MODE == GEMM_PARTIAL_LOWER) {
+            work[(((int64_t)split * ntiles + blockIdx.x) * BM + rl) * BN + cl] = x;
+          } else {
+            const int64_t tile = ((int64_t)split * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            work[(tile * BM + rl) * BN + cl] = x;
           }
         }
-      }
+  } else {  // *_LOWER: row >= col only
+    store_c(acc, M, N, alpha, beta, C, ldc, m0 + wm * WM + (lane >> 4),
+            n0 + wn * WN + (lane & 15), !(MODE == GEMM_FULL || MODE == kBatched));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -339,28 +370,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 
     // epilogue as in gemm_f64_kernel: element v of tile (i, j) is C[row][col]
     // with row = 16 i + lane / 16 + 4 v, col = 16 j + lane % 16 (wave-relative)
+    if (MODE == GEMM_PARTIAL_LOWER || MODE == kPartialFull) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int rl = wm * WM + i * 16 + (lane >> 4) + 4 * v;
-          const int cl = wn * WN + j * 16 + (lane & 15);
-          const double x = acc[i][j][v];
-          if (MODE == GEMM_PARTIAL_LOWER) {
-            work[(((int64_t)split * ntiles + bx) * BM + rl) * BN + cl] = x;
-          } else if (MODE == kPartialFull) {
-            const int64_t tile = ((int64_t)split * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-            work[(tile * BM + rl) * BN + cl] = x;
-          } else {
-            const int64_t row = m0 + rl, col = n0 + cl;
-            if (row < M && col < N && (MODE == GEMM_FULL || row >= col)) {
-              double* p = C + row * ldc + col;
-              *p = (beta == 0.0) ? alpha * x : alpha * x + beta * *p;
+          for (int v = 0; v < 4; ++v) {
+            const int rl = wm * WM + i * 16 + (lane >> 4) + 4 * v;
+            const int cl = wn * WN + j * 16 + (lane & 15);
+            const double x = acc[i][j][v];
+            if (MODE == GEMM_PARTIAL_LOWER) {
+              work[(((int64_t)split * ntiles + bx) * BM + rl) * BN + cl] = x;
+            } else {
+              const int64_t tile =
+                  ((int64_t)split * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+              work[(tile * BM + rl) * BN + cl] = x;
             }
           }
-        }
+    } else {
+      store_c(acc, M, N, alpha, beta, C, ldc, m0 + wm * WM + (lane >> 4),
+              n0 + wn * WN + (lane & 15), MODE != GEMM_FULL);
+    }
     if (MODE != GEMM_SYRK_LOWER) break;
   }
 }
