@@ -220,8 +220,13 @@ struct JacLayers {
 
 constexpr int JOC = 256;  // outputs per staged adjoint chunk
 
+// FP32 J rows are written once and read back only after the whole matrix
+// (far larger than the caches) is done: nontemporal stores, each wave's one
+// contiguous KB. (The FP64 rows' two 16-byte halves per lane leave gaps in
+// each store instruction; there the cached stores, merged in L2, are faster.)
+typedef float f32x4_nt __attribute__((ext_vector_type(4)));
 __device__ inline void store4(float* p, const float (&v)[4]) {
-  *reinterpret_cast<float4*>(p) = float4{v[0], v[1], v[2], v[3]};
+  __builtin_nontemporal_store(f32x4_nt{v[0], v[1], v[2], v[3]}, reinterpret_cast<f32x4_nt*>(p));
 }
 __device__ inline void store4(double* p, const double (&v)[4]) {
   reinterpret_cast<double2*>(p)[0] = double2{v[0], v[1]};
