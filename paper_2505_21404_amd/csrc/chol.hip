@@ -22,11 +22,9 @@ namespace dngd {
 namespace {
 
 constexpr int NB = 64;
-#ifndef DNGD_SIDE_FREE_EXTRA
-#define DNGD_SIDE_FREE_EXTRA 0
-#endif
-// CUs kept free of the look-ahead's trailing update beyond one per panel workgroup
-constexpr int kSideFreeExtra = DNGD_SIDE_FREE_EXTRA;
+// CUs kept free of the look-ahead's trailing update beyond one per panel
+// workgroup (more leave the main stream's block-column update short of CUs)
+constexpr int kSideFreeExtra = 0;
 
 // Grouped right-to-left elimination of one 64-wide panel, 8 columns at a
 // time. For group g (columns c0 .. c0+7):
