@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
             work[(tile * BM + rl) * BN + cl] = x;
           }
         }
-  } else {  // *_LOWER: row >= col only
+  } else {  // C itself (the *_LOWER modes: elements with row >= col only)
     store_c(acc, M, N, alpha, beta, C, ldc, m0 + wm * WM + (lane >> 4),
             n0 + wn * WN + (lane & 15), !(MODE == GEMM_FULL || MODE == kBatched));
   }
@@ -228,9 +228,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
 // K-contiguous operands (C = alpha A B^T + beta C, A: M x K and B: N x K both
 // row-major), the common case of every product on this path: BM x BM tiles,
 // 4 waves in a 2 x 2 grid, K advancing NTK doubles per stage (16, or 32 for
-// the short-K updates of the factorisation, whose time is one DMA round trip
-// per stage). Both row panels go from HBM straight into LDS (global_load_lds,
-// 16 B per lane), double buffered; a plane row holds NTK/2 chunks of 16 B,
+// the factorisation's short-K updates, whose time is one DMA round trip per
+// stage, and for its CU-owning trailing update, which has the LDS). Both row
+// panels go from HBM straight into LDS (global_load_lds, 16 B per lane),
+// double buffered; a plane row holds NTK/2 chunks of 16 B,
 // chunk c of row r stored at c ^ sw(r) with sw(r) = (r >> 1) & 7 for 8 chunks
 // (two 128-byte rows share a 256-byte bank window) and r & 15 for 16 chunks,
 // so the 16 rows of a fragment read hit 16 distinct bank groups. Each MFMA
