@@ -62,6 +62,9 @@ def parse():
                     help="with --pcg: also run this many optimiser iterations (PCG steps + line search)")
     ap.add_argument("--pcg-ga", action="store_true",
                     help="with --pcg: geodesic acceleration (second PCG solve for f_vv)")
+    ap.add_argument("--landmark-study", type=str, default="", metavar="L1,L2,...",
+                    help="instead: --pcg runs with --pcg-iters optimiser iterations (default 6) "
+                         "for each landmark count; PCG iterations per step over training")
     ap.add_argument("--structured", type=int, default=-1, metavar="CFG",
                     help="instead: the dense step on the structured FP64 kernel (no J) against "
                          "the mixed J step, on workload CFG (1: 5-D Poisson, 2: heat)")
@@ -324,6 +327,22 @@ def main():
     import torch
     if a.copy_calibration:
         copy_calibration(torch)
+        return 0
+    if a.landmark_study:
+        rows = []
+        for ell in (int(x) for x in a.landmark_study.split(",")):
+            a.pcg_landmarks = ell
+            a.pcg_iters = a.pcg_iters or 6
+            out = pcg_run(a, torch)
+            rows.append({"landmarks": ell, "first_step_s": out["value"],
+                         "ms_nystrom_build": out["ms_nystrom_build"],
+                         "ms_per_pcg_iteration": out["ms_per_pcg_iteration"],
+                         "iterations": out["iterations"]})
+        print(json.dumps({"metric": "PCG iterations per D-NGD step vs landmark count",
+                          "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": "poisson5d_mlp5-2048x4-1_m50000_pcg",
+                                     "tol": a.pcg_tol, "iterations": a.pcg_iters},
+                          "rows": rows}), flush=True)
         return 0
     if a.pcg:
         print(json.dumps(pcg_run(a, torch)), flush=True)
