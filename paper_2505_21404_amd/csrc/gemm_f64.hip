@@ -56,6 +56,39 @@ __device__ inline void store_c(const f64x4 (&acc)[TM][TN], int64_t M, int64_t N,
   }
 }
 
+// The same update with all of a small tile's C values read up front
+// (load_c, unconditional from clamped addresses): issued before the first
+// operand stage, the loads travel with it instead of costing the epilogue a
+// round trip of its own.
+template <int TM, int TN>
+__device__ inline void load_c(double (&old)[TM][TN][4], int64_t M, int64_t N,
+                              const double* __restrict__ C, int64_t ldc, int64_t r0, int64_t c0) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        old[i][j][v] = C[min(r0 + 16 * i + 4 * v, M - 1) * ldc + min(c0 + 16 * j, N - 1)];
+}
+template <int TM, int TN>
+__device__ inline void store_c_pre(const f64x4 (&acc)[TM][TN], const double (&old)[TM][TN][4],
+                                   int64_t M, int64_t N, double alpha, double beta,
+                                   double* __restrict__ C, int64_t ldc, int64_t r0, int64_t c0,
+                                   bool lower) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + 16 * i + 4 * v, col = c0 + 16 * j;
+        if (row < M && col < N && (!lower || row >= col))
+          C[row * ldc + col] =
+              (beta == 0.0) ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * old[i][j][v];
+      }
+}
+
 __device__ inline void tri_decode(int64_t t, int64_t& i, int64_t& j) {
   int64_t ii = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
@@ -353,6 +386,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     };
 
     const int64_t nk = (kend > kbeg) ? (kend - kbeg + KS - 1) / KS : 0;
+    // 64-wide tiles (the factorisation's latency-bound updates) read C up front
+    constexpr bool PRE = (BM == 64) && !PARTIAL;
+    const int64_t cr0 = m0 + wm * WM + (lane >> 4), cc0 = n0 + wn * WN + (lane & 15);
+    double cold[PRE ? TM : 1][PRE ? TN : 1][4];
+    if (PRE && beta != 0.0) load_c(cold, M, N, C, ldc, cr0, cc0);
     if (nk > 0) dma(kbeg, sA0, sB0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -389,9 +427,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
               work[(tile * BM + rl) * BN + cl] = x;
             }
           }
+    } else if constexpr (PRE) {
+      store_c_pre(acc, cold, M, N, alpha, beta, C, ldc, cr0, cc0, MODE != GEMM_FULL);
     } else {
-      store_c(acc, M, N, alpha, beta, C, ldc, m0 + wm * WM + (lane >> 4),
-              n0 + wn * WN + (lane & 15), MODE != GEMM_FULL);
+      store_c(acc, M, N, alpha, beta, C, ldc, cr0, cc0, MODE != GEMM_FULL);
     }
     if (MODE != GEMM_SYRK_LOWER) break;
   }
