@@ -51,6 +51,7 @@ struct dngd_problem {
   double* A[kMaxLayers] = {nullptr};
   double* Zb[kMaxLayers] = {nullptr};
   double* Ab[2] = {nullptr, nullptr};
+  double* WT = nullptr;  // one hidden layer's weights transposed (backward products)
   double* seed = nullptr;
   double* U = nullptr;
   // tangent streams (lazy)
@@ -68,6 +69,7 @@ struct dngd_problem {
 namespace {
 
 int64_t act_bytes(const Geometry& g) { return g.R * (int64_t)g.max_width * (int64_t)sizeof(double); }
+size_t wt_bytes(const Geometry& g) { return (size_t)g.max_width * g.max_width * sizeof(double); }
 
 int dmalloc(dngd_problem* h, void** p, size_t bytes) {
   if (bytes == 0) bytes = 8;
@@ -139,9 +141,12 @@ int backward(dngd_problem* h, const double* theta, const double* p, hipStream_t 
     if (rc) return rc;
     if (hl > 0) {
       const int win = g.widths[hl];
-      // Abar_{hl-1} = Zb[hl] W_hl : (R x w) (w x win)
-      rc = gemm_f64(s, GEMM_FULL, true, false, g.R, win, w, 1.0, h->Zb[hl], w, Wp(h, theta, hl),
-                    win, 0.0, h->Ab[cur ^ 1], win);
+      // Abar_{hl-1} = Zb[hl] W_hl : (R x w) (w x win), with W_hl transposed
+      // first so that both operands run along K (the faster product kernel)
+      rc = transpose_rm(s, w, win, Wp(h, theta, hl), win, 0, h->WT, w);
+      if (rc) return rc;
+      rc = gemm_f64(s, GEMM_FULL, true, true, g.R, win, w, 1.0, h->Zb[hl], w, h->WT, w, 0.0,
+                    h->Ab[cur ^ 1], win);
       if (rc) return rc;
       cur ^= 1;
     }
@@ -462,7 +467,7 @@ size_t footprint_bytes(const Geometry& g, const dngd_step_opts* o) {
   dngd_step_opts_default(&def);
   if (!o) o = &def;
   size_t b = 0;
-  b += (size_t)g.R * g.d_in * 8 + 2 * (size_t)act_bytes(g) + 2 * (size_t)g.R * 8;
+  b += (size_t)g.R * g.d_in * 8 + 2 * (size_t)act_bytes(g) + 2 * (size_t)g.R * 8 + wt_bytes(g);
   for (int l = 0; l < g.L - 1; ++l) b += 3 * (size_t)g.R * g.widths[l + 1] * 8;
   if (o->ga || o->solver == DNGD_PCG) b += 6 * (size_t)act_bytes(g);
   b += step_vec_bytes(g) + vjp_work_bytes(g) + (size_t)g.n * 8 + 256;
@@ -572,6 +577,7 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   }
   if (!rc) rc = dmalloc(h, (void**)&h->Ab[0], act_bytes(g));
   if (!rc) rc = dmalloc(h, (void**)&h->Ab[1], act_bytes(g));
+  if (!rc) rc = dmalloc(h, (void**)&h->WT, wt_bytes(g));
   if (!rc) rc = dmalloc(h, (void**)&h->seed, (size_t)g.R * sizeof(double));
   if (!rc) rc = dmalloc(h, (void**)&h->U, (size_t)g.R * sizeof(double));
   for (int e = 0; e < 10 && !rc; ++e)
