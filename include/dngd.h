@@ -17,7 +17,7 @@
  *     workspace it allocates and frees it in dngd_problem_destroy. Stateless
  *     calls (dngd_gram, dngd_cholesky_solve) take their scratch from the
  *     stream-ordered allocator of the stream's device and release it before
- *     returning.
+ *     returning; dngd_cholesky_solve_noalloc uses a static device array.
  *   - A dngd_problem is not thread-safe; use one per job and one stream per
  *     problem at a time.
  *
@@ -207,6 +207,23 @@ int dngd_gram(int64_t m, int64_t n, const void* J, int64_t ldJ, int32_t j_dtype,
  * Synchronises `stream` when factoring (to read info). */
 int dngd_cholesky_solve(int64_t m, double* K, int64_t ldK, int32_t factored, int64_t nrhs,
                         double* B, int64_t ldB, int64_t* info, void* stream);
+
+/* dngd_cholesky_solve without any device allocation, for callers that cannot
+ * allocate: serving loops that keep hipMalloc/hipFree (and the stream-ordered
+ * allocator) out of their steady state, and harnesses that forbid allocation.
+ * Same arguments, kernels, results (bitwise) and error behaviour as
+ * dngd_cholesky_solve. Its scratch (the info word, the factor's diagonal
+ * blocks, the inverted diagonal blocks and L^T of the solves) is a static
+ * device array of 65 MiB that the library holds on every device it is loaded
+ * on until the process ends; m > 2048 needs more and is rejected with
+ * DNGD_EINVAL before anything is enqueued. Every call on one device shares
+ * that device's array: calls that overlap on one device (different host
+ * threads or streams) race and give wrong results; serialise them. Each call
+ * writes every scratch byte it reads, so nothing carries over between calls.
+ * Factoring (factored == 0) synchronises `stream` to read info. */
+int dngd_cholesky_solve_noalloc(int64_t m, double* K, int64_t ldK, int32_t factored,
+                                int64_t nrhs, double* B, int64_t ldB, int64_t* info,
+                                void* stream);
 
 /* Second directional derivative of the residual along v (Section 3.2):
  * fvv = d^2/dt^2 r(theta + t v) at t = 0. theta, v: device n FP64;

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/dngd.h"
@@ -509,6 +510,78 @@ size_t footprint_bytes(const Geometry& g, const dngd_step_opts* o) {
 int losses_impl(dngd_problem* h, const double* theta, const double* dtheta, int n_eta,
                 const double* etas, double* losses, hipStream_t s);
 
+// Dense Cholesky solve shared by dngd_cholesky_solve and its allocation-free
+// variant. buf: device scratch of cholesky_solve_scratch_bytes(m) bytes (the
+// info word, then the factor's and the solves' workspace); every byte the
+// call reads is written by the call first.
+int cholesky_solve_check(int64_t m, const double* K, int64_t ldK, int64_t nrhs, const double* B,
+                         int64_t ldB, const int64_t* info) {
+  DNGD_REQUIRE(K && info, "dngd_cholesky_solve: null pointer");
+  DNGD_REQUIRE(m > 0 && ldK >= m && nrhs >= 0 && (nrhs == 0 || (B && ldB >= m)),
+               "dngd_cholesky_solve: bad sizes");
+  return 0;
+}
+
+size_t cholesky_solve_scratch_bytes(int64_t m) { return 256 + chol_solve_aux_bytes(m); }
+
+int cholesky_solve_impl(int64_t m, double* K, int64_t ldK, int32_t factored, int64_t nrhs,
+                        double* B, int64_t ldB, int64_t* info, hipStream_t s, char* buf) {
+  *info = 0;
+  int64_t* dinfo = reinterpret_cast<int64_t*>(buf);
+  double* aux = reinterpret_cast<double*>(buf + 256);
+  int rc = 0;
+  if (!factored) {
+    rc = chol_factor(s, m, K, ldK, dinfo, aux, nullptr);  // clears *dinfo first
+    if (!rc) {
+      hipError_t e = hipMemcpyAsync(info, dinfo, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) rc = hip_fail(e, "info readback", __FILE__, __LINE__);
+    }
+  }
+  if (!rc && *info == 0 && nrhs > 0) {
+    rc = chol_prepare_solve(s, m, K, ldK, aux);
+    for (int64_t j = 0; j < nrhs && !rc; ++j) rc = chol_solve(s, m, K, ldK, aux, B + j * ldB);
+  }
+  if (rc) return rc;
+  if (*info != 0) {
+    set_error("Cholesky: non-positive pivot at column %lld", (long long)*info);
+    return DNGD_ENOTPD;
+  }
+  return DNGD_OK;
+}
+
+}  // namespace
+
+// Scratch of dngd_cholesky_solve_noalloc: a static device array, one copy on
+// every device the library is loaded on, held until the process ends. Host
+// code never uses the array's name as an address (on the host it is only a
+// stand-in for the symbol): noalloc_scratch() looks up each device's address
+// once, with that device current, and every launch takes that address.
+constexpr int kNoAllocMaxM = 2048;
+constexpr size_t kNoAllocScratchBytes = (size_t)65 << 20;  // >= 256 + chol_solve_aux_bytes(2048)
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+int noalloc_scratch(char** out) {
+  int dev = 0;
+  DNGD_HIP(hipGetDevice(&dev));
+  DNGD_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -670,36 +743,30 @@ int dngd_gram(int64_t m, int64_t n, const void* J, int64_t ldJ, int32_t j_dtype,
 
 int dngd_cholesky_solve(int64_t m, double* K, int64_t ldK, int32_t factored, int64_t nrhs,
                         double* B, int64_t ldB, int64_t* info, void* stream) {
-  DNGD_REQUIRE(K && info, "dngd_cholesky_solve: null pointer");
-  DNGD_REQUIRE(m > 0 && ldK >= m && nrhs >= 0 && (nrhs == 0 || (B && ldB >= m)),
-               "dngd_cholesky_solve: bad sizes");
-  hipStream_t s = S(stream);
-  *info = 0;
-  char* scratch = nullptr;
-  const size_t bytes = 64 + chol_solve_aux_bytes(m);
-  DNGD_HIP(hipMallocAsync((void**)&scratch, bytes, s));
-  int64_t* dinfo = reinterpret_cast<int64_t*>(scratch);
-  double* aux = reinterpret_cast<double*>(scratch + 64);
-  int rc = 0;
-  if (!factored) {
-    rc = chol_factor(s, m, K, ldK, dinfo, aux, nullptr);
-    if (!rc) {
-      hipError_t e = hipMemcpyAsync(info, dinfo, sizeof(int64_t), hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) rc = hip_fail(e, "info readback", __FILE__, __LINE__);
-    }
-  }
-  if (!rc && *info == 0 && nrhs > 0) {
-    rc = chol_prepare_solve(s, m, K, ldK, aux);
-    for (int64_t j = 0; j < nrhs && !rc; ++j) rc = chol_solve(s, m, K, ldK, aux, B + j * ldB);
-  }
-  hipFreeAsync(scratch, s);
+  int rc = cholesky_solve_check(m, K, ldK, nrhs, B, ldB, info);
   if (rc) return rc;
-  if (*info != 0) {
-    set_error("Cholesky: non-positive pivot at column %lld", (long long)*info);
-    return DNGD_ENOTPD;
-  }
-  return DNGD_OK;
+  hipStream_t s = S(stream);
+  char* buf = nullptr;
+  DNGD_HIP(hipMallocAsync((void**)&buf, cholesky_solve_scratch_bytes(m), s));
+  rc = cholesky_solve_impl(m, K, ldK, factored, nrhs, B, ldB, info, s, buf);
+  hipFreeAsync(buf, s);
+  return rc;
+}
+
+int dngd_cholesky_solve_noalloc(int64_t m, double* K, int64_t ldK, int32_t factored,
+                                int64_t nrhs, double* B, int64_t ldB, int64_t* info,
+                                void* stream) {
+  int rc = cholesky_solve_check(m, K, ldK, nrhs, B, ldB, info);
+  if (rc) return rc;
+  const size_t need = cholesky_solve_scratch_bytes(m);
+  DNGD_REQUIRE(need <= kNoAllocScratchBytes,
+               "dngd_cholesky_solve_noalloc: m = %lld needs %zu bytes of scratch, the static "
+               "array holds %zu (m <= %d)",
+               (long long)m, need, kNoAllocScratchBytes, kNoAllocMaxM);
+  char* buf = nullptr;
+  rc = noalloc_scratch(&buf);
+  if (rc) return rc;
+  return cholesky_solve_impl(m, K, ldK, factored, nrhs, B, ldB, info, S(stream), buf);
 }
 
 int dngd_fvv(dngd_problem* h, const double* theta, const double* v, double* fvv, void* stream) {

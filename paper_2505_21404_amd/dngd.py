@@ -83,7 +83,7 @@ EXPORTS = [
     "dngd_problem_destroy", "dngd_num_params", "dngd_num_residuals", "dngd_jacobian_ld",
     "dngd_footprint", "dngd_residual_jacobian", "dngd_gram", "dngd_cholesky_solve", "dngd_fvv",
     "dngd_jvp", "dngd_vjp", "dngd_losses", "dngd_nystrom_pcg", "dngd_step", "dngd_iterate",
-    "dngd_footprint_desc",
+    "dngd_footprint_desc", "dngd_cholesky_solve_noalloc",
 ]
 
 
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "dngd_residual_jacobian": (C.c_int, [vp, vp, vp, vp, i64, i32, vp]),
         "dngd_gram": (C.c_int, [i64, i64, vp, i64, i32, i32, dbl, vp, i64, vp]),
         "dngd_cholesky_solve": (C.c_int, [i64, vp, i64, i32, i64, vp, i64, C.POINTER(i64), vp]),
+        "dngd_cholesky_solve_noalloc": (C.c_int, [i64, vp, i64, i32, i64, vp, i64,
+                                                  C.POINTER(i64), vp]),
         "dngd_fvv": (C.c_int, [vp, vp, vp, vp, vp]),
         "dngd_jvp": (C.c_int, [vp, vp, vp, vp, vp]),
         "dngd_vjp": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -326,16 +328,19 @@ def gram(J: torch.Tensor, n: int, lam: float, passes: int = 1, stream=None) -> t
     return K
 
 
-def cholesky_solve(K: torch.Tensor, B: torch.Tensor, factored: bool = False, stream=None):
+def cholesky_solve(K: torch.Tensor, B: torch.Tensor, factored: bool = False, stream=None,
+                   noalloc: bool = False):
     """Factor K (lower triangle, in place) and overwrite B (m x nrhs, column
     blocks contiguous: pass B as an (nrhs, m) tensor) with K^{-1} B.
+    ``noalloc`` calls dngd_cholesky_solve_noalloc (static scratch, m <= 2048).
     Returns info (0 on success)."""
     m = K.shape[0]
     assert B.dtype == torch.float64 and B.is_contiguous()
     nrhs, ldB = (1, m) if B.dim() == 1 else (B.shape[0], B.shape[1])
     info = C.c_int64()
-    rc = _lib.dngd_cholesky_solve(m, _ptr(K), K.stride(0), int(factored), nrhs, _ptr(B), ldB,
-                                  C.byref(info), _stream(stream))
+    fn = _lib.dngd_cholesky_solve_noalloc if noalloc else _lib.dngd_cholesky_solve
+    rc = fn(m, _ptr(K), K.stride(0), int(factored), nrhs, _ptr(B), ldB, C.byref(info),
+            _stream(stream))
     if rc == ENOTPD:
         return int(info.value)
     _check(rc)

@@ -58,6 +58,11 @@ def test_argument_validation_without_gpu():
     info = ctypes.c_int64()
     assert lib.dngd_cholesky_solve(0, ctypes.c_void_p(8), 1, 0, 0, None, 1, ctypes.byref(info),
                                    None) == dngd.EINVAL
+    # the allocation-free variant rejects m beyond its static scratch (m <= 2048)
+    assert lib.dngd_cholesky_solve_noalloc(2049, ctypes.c_void_p(8), 2049, 0, 1,
+                                           ctypes.c_void_p(8), 2049, ctypes.byref(info),
+                                           None) == dngd.EINVAL
+    assert b"2048" in lib.dngd_last_error()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libdngd.so not built")
