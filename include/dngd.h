@@ -43,8 +43,7 @@ typedef enum {
   DNGD_ENOMEM = -2,   /* device allocation failed */
   DNGD_EHIP = -3,     /* a HIP runtime call failed */
   DNGD_ENOTPD = -4,   /* Cholesky met a non-positive pivot; info = 1-based column */
-  DNGD_ENAN = -5,     /* a non-finite value in the result */
-  DNGD_ETIMEOUT = -6  /* a kernel's bounded inter-workgroup wait expired; results invalid */
+  DNGD_ENAN = -5      /* a non-finite value in the result */
 } dngd_status;
 
 typedef enum { DNGD_F64 = 0, DNGD_F32 = 1 } dngd_dtype;

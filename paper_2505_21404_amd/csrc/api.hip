@@ -337,6 +337,21 @@ int carve_small(dngd_problem* h, Small& sm) {
 }
 
 
+// DNGD_ENAN unless ||r||^2 is finite (a non-finite theta, point or target);
+// synchronises s
+int check_finite_residual(const StepVecs& v, int64_t m, hipStream_t s) {
+  int rc = sumsq(s, m, v.r, v.scal + 30, v.red);
+  if (rc) return rc;
+  double rr = 0.0;
+  DNGD_HIP(hipMemcpyAsync(&rr, v.scal + 30, sizeof(double), hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
+  if (!std::isfinite(rr)) {
+    set_error("non-finite residual at theta (||r||^2 = %g)", rr);
+    return DNGD_ENAN;
+  }
+  return 0;
+}
+
 // The dense solvers factor K = A A^T + lambda I for an operator A (M x N,
 // row-major, FP32 or FP64): A = J for the dual step (M = m residuals, N = n
 // parameters, Section 4.1) and A = J^T for the primal step (M = n, N = m,
@@ -1169,6 +1184,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   if (o.solver == DNGD_PCG) {
     DNGD_REQUIRE(o.landmarks && o.n_landmarks >= 1 && o.n_landmarks <= g.m, "PCG needs landmarks");
     rc = forward(h, theta, v.r, s);
+    if (!rc) rc = check_finite_residual(v, g.m, s);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[1], s));
     Precond P;
@@ -1262,6 +1278,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   // ---------------- dense dual solver on the structured FP64 kernel (J never formed) ------
   if (o.solver == DNGD_STRUCTURED) {
     rc = forward(h, theta, v.r, s);
+    if (!rc) rc = check_finite_residual(v, g.m, s);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[1], s));
     rc = ensure(h, h->K, (size_t)g.m * g.m * 8);
@@ -1364,8 +1381,9 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   h->J_dtype = jd;
   void* J = h->J.p;
 
-  // residual + Jacobian (Section 2.2)
+  // residual + Jacobian (Section 2.2); ||r||^2 flags a non-finite theta or point
   rc = forward(h, theta, v.r, s);
+  if (!rc) rc = sumsq(s, g.m, v.r, v.scal + 30, v.red);
   if (!rc) rc = backward(h, theta, nullptr, s);
   if (!rc) rc = write_jacobian(h, J, ldJ, jd, v.rownorm2, s);
   if (rc) return rc;
@@ -1399,13 +1417,21 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   int passes = 1;
   if (jd == DNGD_F32) {
     passes = o.gram_passes;
-    // D = max_i ||A_i||^2: decides the bf16 split when passes == 0 (auto)
-    std::vector<double> rn(op.M);
-    DNGD_HIP(hipMemcpyAsync(rn.data(), diag, op.M * 8, hipMemcpyDeviceToHost, s));
+    // D = max_i ||A_i||^2 (reduced on the device): decides the bf16 split when
+    // passes == 0 (auto); it and ||r||^2 come back in one read
+    rc = vmax(s, op.M, diag, v.scal + 31, v.red);
+    if (rc) return rc;
+    double rd[2];
+    DNGD_HIP(hipMemcpyAsync(rd, v.scal + 30, sizeof(rd), hipMemcpyDeviceToHost, s));
     DNGD_HIP(hipStreamSynchronize(s));
-    double dmax = 0.0;
-    for (double x : rn) dmax = std::max(dmax, x);
-    st.max_row_norm2 = dmax;
+    const double dmax = std::max(rd[1], 0.0);
+    st.max_row_norm2 = rd[1];
+    if (!std::isfinite(rd[0]) || !std::isfinite(rd[1])) {
+      if (stats) *stats = st;
+      set_error("non-finite residual or Jacobian at theta (||r||^2 = %g, max ||J_i||^2 = %g)",
+                rd[0], rd[1]);
+      return DNGD_ENAN;
+    }
     if (passes == 0) {
       // bf16 unit roundoff 2^-8 times sqrt(D / lam) estimates the refinement
       // contraction of a 1-pass Gram; split when it would exceed 1/50. The
@@ -1550,6 +1576,10 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     for (int k = 0; k < ir && k < 8; ++k) st.ir_residual[k] = nr > 0 ? std::sqrt(sc[16 + k]) / nr : 0;
   }
   if (stats) *stats = st;
+  if (!std::isfinite(sc[30])) {
+    set_error("non-finite residual at theta (||r||^2 = %g)", sc[30]);
+    return DNGD_ENAN;
+  }
   if (info != 0) {
     set_error("Cholesky of K + lambda I: non-positive pivot at column %lld", (long long)info);
     return DNGD_ENOTPD;

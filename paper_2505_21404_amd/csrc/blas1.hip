@@ -152,6 +152,35 @@ __global__ __launch_bounds__(256) void sumsq_final_kernel(const double* __restri
   if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// max with NaN propagation: a NaN anywhere makes the result NaN
+__device__ inline double nanmax(double a, double b) {
+  if (a != a) return a;
+  if (b != b) return b;
+  return b > a ? b : a;
+}
+
+__global__ __launch_bounds__(256) void vmax_partial_kernel(int64_t n, const double* __restrict__ x,
+                                                           double* __restrict__ part) {
+  __shared__ double red[4];
+  double s = -HUGE_VAL;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)SS_BLOCKS * 256)
+    s = nanmax(s, x[i]);
+  for (int off = 32; off > 0; off >>= 1) s = nanmax(s, __shfl_xor(s, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void vmax_final_kernel(const double* __restrict__ part,
+                                                         double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = part[threadIdx.x];  // SS_BLOCKS == 256
+  for (int off = 32; off > 0; off >>= 1) s = nanmax(s, __shfl_xor(s, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
+}
+
 __global__ __launch_bounds__(256) void dot_partial_kernel(int64_t n, const double* __restrict__ x,
                                                           const double* __restrict__ y,
                                                           double* __restrict__ part) {
@@ -307,6 +336,14 @@ int sumsq(hipStream_t s, int64_t n, const double* x, double* out, double* work) 
   hipLaunchKernelGGL(sumsq_partial_kernel, dim3(SS_BLOCKS), dim3(256), 0, s, n, x, work);
   DNGD_LAUNCH_CHECK();
   hipLaunchKernelGGL(sumsq_final_kernel, dim3(1), dim3(256), 0, s, work, out);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int vmax(hipStream_t s, int64_t n, const double* x, double* out, double* work) {
+  hipLaunchKernelGGL(vmax_partial_kernel, dim3(SS_BLOCKS), dim3(256), 0, s, n, x, work);
+  DNGD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(vmax_final_kernel, dim3(1), dim3(256), 0, s, work, out);
   DNGD_LAUNCH_CHECK();
   return 0;
 }

@@ -177,6 +177,8 @@ int gemv_n_residual(hipStream_t s, int64_t m, int64_t n, const void* J, int64_t 
                     const double* t, const double* r, const double* x, double lam, double* out);
 // deterministic sum of squares of n values -> *out (device double)
 int sumsq(hipStream_t s, int64_t n, const double* x, double* out, double* work);
+// max of n values -> *out (device double); NaN if any value is NaN, -inf if n == 0
+int vmax(hipStream_t s, int64_t n, const double* x, double* out, double* work);
 int axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);  // y += a x
 int xpby(hipStream_t s, int64_t n, const double* x, double beta, double* y);  // y = x + beta y
 // deterministic dot product -> *out (device); work holds 256 doubles

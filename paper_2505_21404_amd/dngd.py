@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdngd.so")
 
-OK, ENOCONV, EINVAL, ENOMEM, EHIP, ENOTPD, ENAN, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
+OK, ENOCONV, EINVAL, ENOMEM, EHIP, ENOTPD, ENAN = 0, 1, -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 GRAM_F64 = 64   # gram_passes value: FP64-product Gram of an FP32 J
 POISSON, HEAT = 0, 1
@@ -24,7 +24,7 @@ PLAIN, MIXED = 0, 1
 DENSE, PCG, PRIMAL, DENSE_AUTO, STRUCTURED = 0, 1, 2, 3, 4
 
 _STATUS = {ENOCONV: "DNGD_ENOCONV", EINVAL: "DNGD_EINVAL", ENOMEM: "DNGD_ENOMEM", EHIP: "DNGD_EHIP",
-           ENOTPD: "DNGD_ENOTPD", ENAN: "DNGD_ENAN", ETIMEOUT: "DNGD_ETIMEOUT"}
+           ENOTPD: "DNGD_ENOTPD", ENAN: "DNGD_ENAN"}
 
 
 class DngdError(RuntimeError):

@@ -10,7 +10,10 @@ admitted jobs run concurrently, each on its own HIP stream driven by its own
 host thread (the library calls release the GIL), so their kernels overlap on
 the device. A finished job frees its memory and slot, which admits the next.
 
-Per-step latencies, admission waits and throughput are recorded; results do
+A job whose footprint exceeds the whole budget is rejected when it arrives
+(recorded as an error); the others are served. Per-step latencies (also split
+into each job's first step, which allocates the handle's workspace, and the
+steady state), admission waits and throughput are recorded; results do
 not depend on what else runs (every kernel is deterministic and a job touches
 only its own handle and stream).
 """
@@ -89,11 +92,15 @@ class Server:
         """Serve ``jobs``; with ``realtime`` a job becomes eligible at its
         arrival time, otherwise all are eligible at once (in arrival order)."""
         fps = {j.job_id: int(self._footprint(j)) for j in jobs}
-        for j in jobs:
-            if fps[j.job_id] > self.budget:
-                raise ValueError(f"job {j.job_id} needs {fps[j.job_id]} B > budget {self.budget} B")
-        pending = sorted(jobs, key=lambda j: (j.arrival, j.job_id))
         results: Dict[int, JobResult] = {}
+        # a job that can never fit is rejected when it arrives; the rest are served
+        rejected = [j for j in jobs if fps[j.job_id] > self.budget]
+        for j in rejected:
+            results[j.job_id] = JobResult(
+                j.job_id, j.arrival, j.arrival, j.arrival, fps[j.job_id],
+                error=f"rejected: footprint {fps[j.job_id]} B exceeds the budget {self.budget} B")
+        pending = sorted((j for j in jobs if fps[j.job_id] <= self.budget),
+                         key=lambda j: (j.arrival, j.job_id))
         in_use = 0
         active = 0
         threads = []
@@ -150,16 +157,23 @@ class Server:
 
 def report(results: Dict[int, JobResult], makespan: float, server: Server) -> Dict:
     lat = [x for r in results.values() for x in r.step_ms]
-    waits = [r.admitted - r.arrival for r in results.values()]
+    served = [r for r in results.values() if not (r.error or "").startswith("rejected")]
+    waits = [r.admitted - r.arrival for r in served]
+    first = [r.step_ms[0] for r in served if r.step_ms]
+    steady = [x for r in served for x in r.step_ms[1:]]
     steps = len(lat)
     return {
         "jobs": len(results),
+        "rejected": len(results) - len(served),
         "errors": {r.job_id: r.error for r in results.values() if r.error},
         "steps": steps,
         "makespan_s": makespan,
         "steps_per_s": steps / makespan if makespan > 0 else float("nan"),
         "p50_step_ms": percentile(lat, 0.50),
         "p99_step_ms": percentile(lat, 0.99),
+        "first_step_p50_ms": percentile(first, 0.50),
+        "steady_p50_step_ms": percentile(steady, 0.50),
+        "steady_p99_step_ms": percentile(steady, 0.99),
         "mean_step_ms": statistics.fmean(lat) if lat else float("nan"),
         "admission_wait_p50_s": percentile(waits, 0.50),
         "admission_wait_max_s": max(waits) if waits else float("nan"),

@@ -89,15 +89,30 @@ def test_config1_mixed_is_deterministic(c1):
 
 
 def test_config0_steps_match_oracle():
+    """Config 0 at its own damping (1e-8) and at 1e-6. Both sides are backward
+    stable, so the GPU's alpha must have a normwise backward error <= m u64
+    (the order a backward-stable Cholesky solve guarantees) against the oracle's K and r; the forward error of alpha and dtheta is then
+    bounded by the conditioning, c u64 cond(K + lam I), which is asserted beside
+    it (at 1e-6 that bound is below 1e-10)."""
     d = D()
     p = W.config(0)
     th = W.glorot_theta(p.widths, 0)
     prob = d.Problem.from_workload(p)
-    # tight check at moderate damping; the lam = 1e-8 case is conditioning-limited
-    for lam, tol in ((1e-6, 1e-10), (1e-8, 1e-7)):
+    u64 = np.finfo(np.float64).eps / 2
+    for lam in (1e-6, 1e-8):
         ref = S.dense_step(p, th, lam, ga=True)
-        say("case config0 plain step lam", lam)
-        dth, st = prob.step(th, lam, d.step_opts(precision=d.PLAIN, ga=True))
-        assert rel(dth.cpu().numpy(), ref.dtheta) <= tol
+        cond = np.linalg.cond(ref.K + lam * np.eye(p.m))
+        say("case config0 plain step lam", lam, "u64 * cond", u64 * cond)
+        alpha = torch.empty(p.m, dtype=torch.float64, device="cuda")
+        dth, st = prob.step(th, lam, d.step_opts(precision=d.PLAIN, ga=True, alpha_out=alpha))
+        a = alpha.cpu().numpy()
+        be = S.backward_error(ref.K, lam, a, ref.r)
+        ea, ed = rel(a, ref.alpha), rel(dth.cpu().numpy(), ref.dtheta)
+        say(f"  backward error {be:.2e}  alpha rel err {ea:.2e}  dtheta rel err {ed:.2e}")
+        assert be <= p.m * u64  # backward stability: O(m u64), 5.6e-14 at m = 500
+        assert ea <= max(1e-10, 10 * u64 * cond)
+        assert ed <= max(1e-10, 10 * u64 * cond)
+        if lam == 1e-6:
+            assert ed <= 1e-10
         assert st.ga_accepted == int(ref.accepted)
     prob.close()

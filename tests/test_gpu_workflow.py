@@ -56,22 +56,26 @@ def test_config0_training_20_steps():
     losses = [h["loss"] for h in hist] + [hist[-1]["loss_new"]]
     assert all(b <= a * (1 + 1e-12) for a, b in zip(losses, losses[1:]))
     u64 = np.finfo(np.float64).eps / 2
+    alpha = torch.empty(p.m, dtype=torch.float64, device="cuda")
     for k in (0, 7, 19):
-        ref = S.dense_step(p, thetas[k], 1e-8, ga=True)
-        e = rel(dirs[k], ref.dtheta)
-        # lambda = 1e-8 is conditioning-limited: both sides are backward
-        # stable, so they may differ by ~ u64 cond(K + lambda I)
-        cond = np.linalg.cond(ref.K + 1e-8 * np.eye(p.m))
-        say("step", k, "rel err vs oracle", e, "u64 * cond", u64 * cond)
-        assert e <= max(1e-10, 10 * u64 * cond)
-        assert hist[k]["step"]["ga_accepted"] == int(ref.accepted)
-        # at moderate damping the same iterate is checked tightly
-        ref6 = S.dense_step(p, thetas[k], 1e-6, ga=True)
-        d6, _ = prob.step(thetas[k], 1e-6, d.step_opts(precision=d.PLAIN, ga=True))
-        e6 = rel(d6.cpu().numpy(), ref6.dtheta)
-        cond6 = np.linalg.cond(ref6.K + 1e-6 * np.eye(p.m))
-        say("step", k, "lambda 1e-6 rel err", e6, "u64 * cond", u64 * cond6)
-        assert e6 <= max(1e-10, 10 * u64 * cond6)
+        for lam in (1e-8, 1e-6):
+            # both sides are backward stable: the GPU's alpha at this iterate
+            # has a normwise backward error <= m u64 against the oracle's K
+            # and r, and the forward error of the step is bounded by
+            # ~ u64 cond(K + lambda I) (conditioning-limited at 1e-8)
+            ref = S.dense_step(p, thetas[k], lam, ga=True)
+            cond = np.linalg.cond(ref.K + lam * np.eye(p.m))
+            dk, _ = prob.step(thetas[k], lam,
+                              d.step_opts(precision=d.PLAIN, ga=True, alpha_out=alpha))
+            be = S.backward_error(ref.K, lam, alpha.cpu().numpy(), ref.r)
+            e = rel(dirs[k] if lam == 1e-8 else dk.cpu().numpy(), ref.dtheta)
+            say(f"step {k} lambda {lam:g}: backward error {be:.2e}, rel err vs oracle {e:.2e},"
+                f" u64 * cond {u64 * cond:.2e}")
+            assert be <= p.m * u64  # backward stability: O(m u64), 5.6e-14 at m = 500
+            assert e <= max(1e-10, 10 * u64 * cond)
+            if lam == 1e-8:
+                assert rel(dk.cpu().numpy(), dirs[k]) == 0.0  # the iterate's own step
+                assert hist[k]["step"]["ga_accepted"] == int(ref.accepted)
         # the line search at this iterate against the oracle's losses
         eta, ls = S.line_search(p, thetas[k], dirs[k])
         assert abs(ls.min() - hist[k]["loss_new"]) <= 1e-10 * ls.min() + 1e-300

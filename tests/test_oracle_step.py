@@ -120,3 +120,63 @@ def test_primal_dense_step_equals_dual_step(widths, n_int, n_bdy, lam):
     assert rel(pr.a, du.a) <= 1e-8
     assert pr.accepted == du.accepted
     assert rel(pr.dtheta, du.dtheta) <= 1e-8
+
+
+def test_lm_lambda_is_the_smaller_of_loss_and_cap():
+    """Damping rule of the hyper-parameter tables, lam_k = min(L(theta_k), cap):
+    the cap binds above it and the loss below it (a max/min slip fails one)."""
+    assert S.lm_lambda(3.0, 1e-5) == 1e-5
+    assert S.lm_lambda(2e-7, 1e-5) == 2e-7
+    assert S.lm_lambda(1e-5, 1e-5) == 1e-5
+
+
+def test_backward_error_matches_its_defining_perturbation():
+    """The normwise backward error eta of x for A x = b (Rigal-Gaches) is the
+    smallest eps with (A + dA) x = b + db, ||dA|| <= eps ||A||, ||db|| <= eps ||b||.
+    The minimising perturbation is dA = c ||A|| r x^T / ||x||, db = -c ||b|| r with
+    r = b - A x and c = 1 / (||A|| ||x|| + ||b||); check both the equation and the
+    norms, plus a diagonal case by hand."""
+    rng = np.random.default_rng(7)
+    m = 40
+    B = rng.standard_normal((m, m))
+    K = B @ B.T
+    lam = 0.3
+    A = K + lam * np.eye(m)
+    b = rng.standard_normal(m)
+    x = np.linalg.solve(A, b) + 1e-3 * rng.standard_normal(m)
+    eta = S.backward_error(K, lam, x, b)
+    r = b - A @ x
+    nA, nx, nb = np.linalg.norm(A, 2), np.linalg.norm(x), np.linalg.norm(b)
+    c = 1.0 / (nA * nx + nb)
+    dA = c * nA * np.outer(r, x) / nx
+    db = -c * nb * r
+    assert np.linalg.norm((A + dA) @ x - (b + db)) <= 1e-13 * nb
+    assert np.isclose(np.linalg.norm(dA, 2), eta * nA, rtol=1e-12)
+    assert np.isclose(np.linalg.norm(db), eta * nb, rtol=1e-12)
+    # diag(1, 4), x = (1, 1), b = 0: ||A x|| = sqrt(17), ||A|| = 4, ||x|| = sqrt(2)
+    assert np.isclose(S.backward_error(np.diag([1.0, 4.0]), 0.0, np.ones(2), np.zeros(2)),
+                      np.sqrt(17.0) / (4.0 * np.sqrt(2.0)), rtol=1e-15)
+    # the exact solution has backward error at rounding level
+    assert S.backward_error(K, lam, np.linalg.solve(A, b), b) <= 1e-15
+
+
+def test_line_search_unique_minimiser_inside_the_grid():
+    """Along a direction supported on the output layer the residual is affine,
+    so L(theta + eta d) = 0.5 ||r0 + eta q||^2 with q = r(theta + d) - r(theta),
+    minimised at eta* = -r0.q / q.q. Scaling d so that eta* = 0.3 makes 0.25 the
+    grid's unique minimiser (|0.25 - 0.3| < |0.5 - 0.3|, and the quadratic is
+    symmetric about eta*); doubling d halves it to 0.125."""
+    p = W.config(0, scale=dict(widths=[2, 6, 1], n_int=30, n_bdy=10))
+    th = W.glorot_theta(p.widths, 3)
+    n = th.size
+    d = np.zeros(n)
+    d[n - 7:] = np.random.default_rng(4).standard_normal(7)  # W_2 (6) and b_2 (1)
+    r0 = N.residual(p, th)
+    q = N.residual(p, th + d) - r0
+    assert np.allclose(N.residual(p, th + 0.5 * d), r0 + 0.5 * q, rtol=0, atol=1e-13)
+    d = d * (-(r0 @ q) / (q @ q)) / 0.3  # now eta* = 0.3
+    eta, losses = S.line_search(p, th, d)
+    assert eta == 0.25
+    assert np.sum(losses == losses.min()) == 1
+    eta2, _ = S.line_search(p, th, 2.0 * d)
+    assert eta2 == 0.125

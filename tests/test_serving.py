@@ -71,11 +71,16 @@ def test_scheduler_queues_on_memory_and_overlaps_when_it_fits():
 
 
 def test_scheduler_rejects_job_larger_than_budget():
-    specs, fps = _specs([11], [0.0])
-    run_job, _ = _fake({0: 0.0})
+    """A job that can never fit is rejected at arrival; the others are served."""
+    specs, fps = _specs([11, 4, 12, 6], [0.0, 0.0, 0.01, 0.02])
+    run_job, live = _fake({j: 0.01 for j in fps})
     srv = SV.Server(budget_bytes=10, run_job=run_job, footprint=lambda s: fps[s.job_id])
-    with pytest.raises(ValueError):
-        srv.run(specs)
+    rep = srv.run(specs)
+    assert rep["jobs"] == 4 and rep["rejected"] == 2
+    assert sorted(rep["errors"]) == [0, 2]
+    assert all(e.startswith("rejected") for e in rep["errors"].values())
+    assert not rep["results"][0].step_ms and len(rep["results"][1].step_ms) == 2
+    assert rep["steps"] == 4 and srv.peak_bytes <= 10
 
 
 def test_footprint_query_is_host_only():
