@@ -27,6 +27,12 @@ import numpy as np
 
 POISSON = 0
 HEAT = 1
+NAVIER_STOKES = 2   # vector-valued residual classes: oracle/navier_stokes.py
+
+
+def _ns():
+    from . import navier_stokes
+    return navier_stokes
 
 
 # ----------------------------------------------------------------------------
@@ -163,6 +169,8 @@ def interior_operator(problem, u: Jet):
 
 def residual(problem, theta):
     """r(theta) in R^m, order interior, boundary, initial (Section 2.2)."""
+    if problem.pde == NAVIER_STOKES:
+        return _ns().residual(problem, theta)
     ci, cb, c0 = class_scales(problem)
     nl = nlap_of(problem)
     parts = []
@@ -223,14 +231,17 @@ def _tanh_jet_adjoint(z: Jet, abar: Jet) -> Jet:
 def _jacobian_class(theta, widths, x, nlap, seed_v, seed_g, seed_l):
     """Rows d r_i / d theta for one point class, where r_i is the linear
     functional seed_v*u.v + <seed_g, u.g> + seed_l*u.l of the output jet at x_i
-    (seed_* are per-point arrays). Returns (N, n)."""
+    (seed_* are per-point arrays: (N,), (N, d), (N,) for one output, or with a
+    trailing output axis (N, o), (N, d, o), (N, o) for o outputs). Returns (N, n)."""
     layers = unpack(theta, widths)
     _, tape = forward(theta, widths, x, nlap, keep=True)
     N = x.shape[0]
     d = x.shape[1]
-    # adjoint of the output jet (width 1)
-    zbar = Jet(seed_v[:, None].astype(theta.dtype), seed_g[:, :, None].astype(theta.dtype),
-               seed_l[:, None].astype(theta.dtype), nlap)
+    if seed_v.ndim == 1:
+        seed_v, seed_g, seed_l = seed_v[:, None], seed_g[:, :, None], seed_l[:, None]
+    # adjoint of the output jet
+    zbar = Jet(seed_v.astype(theta.dtype), seed_g.astype(theta.dtype),
+               seed_l.astype(theta.dtype), nlap)
     grads = [None] * len(layers)
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
@@ -250,6 +261,8 @@ def _jacobian_class(theta, widths, x, nlap, seed_v, seed_g, seed_l):
 def jacobian(problem, theta, chunk=512):
     """J = d r / d theta in R^{m x n}, rows in residual order, columns in the
     flat parameter layout."""
+    if problem.pde == NAVIER_STOKES:
+        return _ns().jacobian(problem, theta)
     ci, cb, c0 = class_scales(problem)
     nl = nlap_of(problem)
     d = problem.d_in
@@ -345,7 +358,12 @@ def _jet_fn_jet(dd, z: Jet) -> Jet:
 
 
 def fvv_output(theta, v, widths, x, nlap):
-    """Second t-derivative of the output jet along theta + t v.
+    """Second t-derivative of the output jet along theta + t v (see t_jets)."""
+    return t_jets(theta, v, widths, x, nlap)[2]
+
+
+def t_jets(theta, v, widths, x, nlap):
+    """The output jet and its first and second t-derivatives along theta + t v.
 
     Each layer carries the t-Taylor coefficients (as derivatives) z0, z1, z2 of
     its pre-activation, each a spatial jet. With W(t) = W + tV, b(t) = b + tc:
@@ -365,7 +383,7 @@ def fvv_output(theta, v, widths, x, nlap):
         z1 = a1.affine(W) + a0.affine(V, c)
         z2 = a2.affine(W) + a1.affine(V).scale(2.0)
         if li == L - 1:
-            return z2
+            return z0, z1, z2
         d = tanh_derivs(z0.v, 4)
         s_1 = _jet_fn_jet(d[1:4], z0)   # jet of tanh'(z0)
         s_2 = _jet_fn_jet(d[2:5], z0)   # jet of tanh''(z0)
@@ -377,6 +395,8 @@ def fvv_output(theta, v, widths, x, nlap):
 def fvv(problem, theta, v):
     """f_vv in R^m: the residual's second directional derivative along v.
     Targets f, g drop out (they do not depend on theta)."""
+    if problem.pde == NAVIER_STOKES:
+        return _ns().fvv(problem, theta, v)
     ci, cb, c0 = class_scales(problem)
     nl = nlap_of(problem)
     parts = []

@@ -26,6 +26,7 @@ import numpy as np
 
 POISSON = 0
 HEAT = 1
+NAVIER_STOKES = 2
 
 
 @dataclasses.dataclass
@@ -51,6 +52,8 @@ class Problem:
     amplitude: float = 1.0
     name: str = ""
     solution: str = ""  # key into exact_solution()
+    d_int: int = 1      # residual components per interior point (3 for Navier-Stokes)
+    d_bdy: int = 1      # residual components per boundary point
 
     @property
     def d_in(self) -> int:
@@ -70,7 +73,8 @@ class Problem:
 
     @property
     def m(self) -> int:
-        return self.n_int + self.n_bdy + self.n_init
+        """Residual-space size sum_gamma N_gamma d_gamma."""
+        return self.n_int * self.d_int + self.n_bdy * self.d_bdy + self.n_init
 
     @property
     def n_params(self) -> int:
@@ -148,7 +152,64 @@ def exact_solution(key: str, x: np.ndarray, kappa: float = 0.0, amplitude: float
     if key == "heat_sinsin":  # u = A exp(-2 pi^2 kappa t) sin(pi x) sin(pi y)
         return (amplitude * np.exp(-2.0 * np.pi ** 2 * kappa * x[:, 2])
                 * np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]))
+    if key == "kovasznay":  # (u, v, p) of Kovasznay flow, nu = kappa
+        return kovasznay_fields(x, kappa)
     raise KeyError(key)
+
+
+KOVASZNAY_BOX = ((-0.5, 1.0), (-0.5, 1.5))
+
+
+def kovasznay_fields(x: np.ndarray, nu: float) -> np.ndarray:
+    """Kovasznay's closed-form steady Navier-Stokes solution (u, v, p) at the
+    points x (N, 2) for viscosity nu: with l = 1/(2 nu) - sqrt(1/(4 nu^2) + 4 pi^2),
+    u = 1 - e^{l x} cos(2 pi y), v = l/(2 pi) e^{l x} sin(2 pi y),
+    p = (1 - e^{2 l x}) / 2."""
+    lam = 0.5 / nu - math.sqrt(0.25 / nu ** 2 + 4.0 * math.pi ** 2)
+    ex = np.exp(lam * x[:, 0])
+    c, sn = np.cos(2.0 * np.pi * x[:, 1]), np.sin(2.0 * np.pi * x[:, 1])
+    return np.stack([1.0 - ex * c, lam / (2.0 * np.pi) * ex * sn, 0.5 * (1.0 - ex * ex)], axis=1)
+
+
+def _rect_interior(rng, n, box):
+    (x0, x1), (y0, y1) = box
+    return np.stack([rng.uniform(x0, x1, n), rng.uniform(y0, y1, n)], axis=1)
+
+
+def _rect_boundary(rng, n, box):
+    """Uniform in arc length on the rectangle's perimeter."""
+    (x0, x1), (y0, y1) = box
+    w, h = x1 - x0, y1 - y0
+    s = rng.uniform(0.0, 2.0 * (w + h), n)
+    out = np.empty((n, 2))
+    for i, t in enumerate(s):
+        if t < w:
+            out[i] = (x0 + t, y0)
+        elif t < w + h:
+            out[i] = (x1, y0 + (t - w))
+        elif t < 2 * w + h:
+            out[i] = (x1 - (t - w - h), y1)
+        else:
+            out[i] = (x0, y1 - (t - 2 * w - h))
+    return out
+
+
+def kovasznay(seed: int = 0, widths=(2, 50, 50, 50, 50, 3), n_int: int = 400, n_bdy: int = 400,
+              nu: float = 1.0 / 40.0) -> Problem:
+    """Kovasznay flow at Re = 1/nu = 40 on [-0.5, 1.0] x [-0.5, 1.5]
+    (Section 5.3 and its hyper-parameter table): a [2, 50 x 4, 3] tanh MLP for
+    (u, v, p), N_int interior and N_bdy boundary points drawn uniformly (area and
+    arc length). Interior targets f = 0 for the three equations; boundary values
+    of u, v and p from the closed-form solution. m = 3 N_int + 3 N_bdy."""
+    assert widths[0] == 2 and widths[-1] == 3
+    rng = np.random.default_rng(seed + 1)
+    xi = _rect_interior(rng, n_int, KOVASZNAY_BOX)
+    xb = _rect_boundary(rng, n_bdy, KOVASZNAY_BOX)
+    return Problem(
+        pde=NAVIER_STOKES, widths=list(widths), x_int=xi, x_bdy=xb, x_init=np.zeros((0, 2)),
+        f_int=np.zeros((n_int, 3)), g_bdy=kovasznay_fields(xb, nu), g_init=np.zeros(0),
+        kappa=nu, name=f"kovasznay_re{round(1.0 / nu)}_m{3 * (n_int + n_bdy)}",
+        solution="kovasznay", d_int=3, d_bdy=3)
 
 
 def _source(key: str, x: np.ndarray, amplitude: float = 1.0):
@@ -188,6 +249,8 @@ def heat_problem(widths, n_int, n_bdy, n_init, kappa, seed, amplitude=1.0, name=
 def eval_points(problem: Problem, n: int = 10_000, seed: int = 0):
     """Fresh uniform points in the (space-time) domain for relative L2 error."""
     rng = np.random.default_rng(seed + 2)
+    if problem.pde == NAVIER_STOKES:
+        return _rect_interior(rng, n, KOVASZNAY_BOX)
     return rng.uniform(0.0, 1.0, size=(n, problem.d_in))
 
 
