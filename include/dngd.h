@@ -24,7 +24,9 @@
  * Parameter layout (theta, dtheta, gradients): per affine layer l = 1..L,
  * W_l row-major [out][in], then b_l[out]; n = sum_l (w_l * w_{l-1} + w_l).
  * Residual layout: interior points, then boundary points, then initial
- * points; m = n_int + n_bdy + n_init (one scalar residual per point).
+ * points; m = sum over the classes of N_gamma d_gamma, where d_gamma is the
+ * number of residual components per point (1 for Poisson and heat, 3 for
+ * both Navier-Stokes classes); a point's components are consecutive.
  */
 #ifndef DNGD_H
 #define DNGD_H
@@ -47,7 +49,7 @@ typedef enum {
 } dngd_status;
 
 typedef enum { DNGD_F64 = 0, DNGD_F32 = 1 } dngd_dtype;
-typedef enum { DNGD_POISSON = 0, DNGD_HEAT = 1 } dngd_pde;
+typedef enum { DNGD_POISSON = 0, DNGD_HEAT = 1, DNGD_NAVIER_STOKES = 2 } dngd_pde;
 typedef enum { DNGD_PLAIN = 0, DNGD_MIXED = 1 } dngd_precision;
 /* Solvers of the step's linear systems.
  *   DNGD_DENSE       dual: Cholesky of the m x m kernel J J^T + lambda I (Section 4.1)
@@ -78,19 +80,31 @@ typedef enum {
  *   initial   r_k = N_init^{-1/2} (u(x_k) - g_k)   (heat only).
  * u is a tanh MLP with widths[0] = d_in inputs and widths[L] = 1 output.
  * Heat inputs are ordered (x_1..x_{d_in-1}, t); the Laplacian sums over the
- * spatial coordinates. The point arrays are copied at creation. */
+ * spatial coordinates.
+ * DNGD_NAVIER_STOKES (vector-valued classes; the steady incompressible
+ * equations of Section 5.3 with viscosity nu = kappa): the MLP maps (x, y)
+ * (widths[0] = 2) to (u, v, p) (widths[L] = 3). An interior point has three
+ * residuals, N_int^{-1/2} times
+ *     u u_x + v u_y + p_x - nu lap u - f_i0     (x-momentum)
+ *     u v_x + v v_y + p_y - nu lap v - f_i1     (y-momentum)
+ *     u_x + v_y - f_i2                          (continuity),
+ * a boundary point three, N_bdy^{-1/2} (u - g_j0, v - g_j1, p - g_j2); f_int
+ * is n_int x 3 and g_bdy n_bdy x 3 (row-major); there are no initial points.
+ * Only the dense solvers (DNGD_DENSE, DNGD_PRIMAL, DNGD_DENSE_AUTO) accept it.
+ * The point arrays are copied at creation. */
 typedef struct {
   int32_t pde;            /* dngd_pde */
   int32_t n_layers;       /* L >= 1 affine layers */
-  const int32_t* widths;  /* host, L+1 entries; 1 <= widths[0] <= 8, widths[L] == 1,
+  const int32_t* widths;  /* host, L+1 entries; 1 <= widths[0] <= 8, widths[L] == 1
+                             (Navier-Stokes: widths[0] == 2, widths[L] == 3),
                              hidden widths in [1, 4096] */
-  double kappa;           /* heat diffusivity (ignored for Poisson) */
+  double kappa;           /* heat diffusivity, Navier-Stokes viscosity (ignored for Poisson) */
   int64_t n_int, n_bdy, n_init;  /* n_init must be 0 for Poisson */
   const double* x_int;    /* device, n_int  x d_in, row-major */
   const double* x_bdy;    /* device, n_bdy  x d_in */
   const double* x_init;   /* device, n_init x d_in (may be NULL if n_init == 0) */
-  const double* f_int;    /* device, n_int  interior source f */
-  const double* g_bdy;    /* device, n_bdy  boundary value g */
+  const double* f_int;    /* device, n_int  interior source f (Navier-Stokes: n_int x 3) */
+  const double* g_bdy;    /* device, n_bdy  boundary value g (Navier-Stokes: n_bdy x 3) */
   const double* g_init;   /* device, n_init initial value */
 } dngd_problem_desc;
 

@@ -53,8 +53,9 @@ struct dngd_problem {
   double* Zb[kMaxLayers] = {nullptr};
   double* Ab[2] = {nullptr, nullptr};
   double* WT = nullptr;  // one hidden layer's weights transposed (backward products)
-  double* seed = nullptr;
-  double* U = nullptr;
+  double* seed = nullptr;  // R x d_out reverse-pass seeds on the output jets
+  double* U = nullptr;     // R x d_out output jets of the last forward pass
+  double *U1 = nullptr, *U2 = nullptr;  // their t-derivatives (Navier-Stokes tangents)
   // tangent streams (lazy)
   double *Z1 = nullptr, *Z2 = nullptr, *A1[2] = {nullptr, nullptr}, *A2[2] = {nullptr, nullptr};
   // step / solver workspace (lazy, grown on demand)
@@ -120,21 +121,24 @@ int forward(dngd_problem* h, const double* theta, double* r, hipStream_t s) {
     if (rc) return rc;
   }
   const int l = g.L - 1;
-  rc = net_rowdot(s, g.R, g.widths[l], act_in(h, l), Wp(h, theta, l), 0.0, nullptr, nullptr, h->U);
+  rc = net_rowdot(s, g.R, g.widths[l], g.d_out, act_in(h, l), Wp(h, theta, l), 0.0, nullptr,
+                  nullptr, h->U);
   if (rc) return rc;
   if (r) rc = net_residual(s, h->rm, h->U, Bp(h, theta, l), h->f_int, h->g_bdy, h->g_init, r);
   return rc;
 }
 
-// Backward pass from per-residual weights p (null = Jacobian seeds): fills
-// seed and Zb[h] (adjoints of every hidden pre-activation).
-int backward(dngd_problem* h, const double* theta, const double* p, hipStream_t s) {
+// Backward pass from per-residual weights p (null = the Jacobian rows of
+// residual component comp of every point): fills seed and Zb[h] (adjoints of
+// every hidden pre-activation). Requires forward() at theta.
+int backward(dngd_problem* h, const double* theta, const double* p, hipStream_t s, int comp = 0) {
   const Geometry& g = h->g;
-  int rc = net_seeds(s, h->rm, p, h->seed);
+  int rc = net_seeds(s, h->rm, h->U, Bp(h, theta, g.L - 1), p, comp, h->seed);
   if (rc) return rc;
   if (g.L == 1) return 0;
   int cur = 0;
-  rc = net_outer_seed(s, g.R, g.widths[g.L - 1], h->seed, Wp(h, theta, g.L - 1), h->Ab[cur]);
+  rc = net_outer_seed(s, g.R, g.widths[g.L - 1], g.d_out, h->seed, Wp(h, theta, g.L - 1),
+                      h->Ab[cur]);
   if (rc) return rc;
   for (int hl = g.L - 2; hl >= 0; --hl) {
     const int w = g.widths[hl + 1];
@@ -156,7 +160,8 @@ int backward(dngd_problem* h, const double* theta, const double* p, hipStream_t 
 }
 
 int write_jacobian(dngd_problem* h, void* J, int64_t ldJ, int j_dtype, double* rownorm2,
-                   hipStream_t s, const int64_t* pidx = nullptr, int64_t nrows = 0) {
+                   hipStream_t s, const int64_t* pidx = nullptr, int64_t nrows = 0,
+                   int comp = 0) {
   const Geometry& g = h->g;
   const double* A[kMaxLayers];
   const double* Zb[kMaxLayers];
@@ -164,7 +169,22 @@ int write_jacobian(dngd_problem* h, void* J, int64_t ldJ, int j_dtype, double* r
     A[l] = act_in(h, l);
     Zb[l] = (l < g.L - 1) ? h->Zb[l] : h->seed;
   }
-  return net_jacobian_rows(s, g, h->rm, A, Zb, h->seed, J, ldJ, j_dtype, rownorm2, pidx, nrows);
+  return net_jacobian_rows(s, g, h->rm, A, Zb, h->seed, J, ldJ, j_dtype, rownorm2, pidx, nrows,
+                           comp);
+}
+
+// Every row of J (and its squared norm): one backward pass per residual
+// component of a point (the d x d blocks of vector-valued classes), each
+// writing its component's rows. Requires forward() at theta.
+int jacobian_all(dngd_problem* h, const double* theta, void* J, int64_t ldJ, int j_dtype,
+                 double* rownorm2, hipStream_t s) {
+  const int ncomp = std::max(h->g.r_int, h->g.r_bdy);
+  for (int c = 0; c < ncomp; ++c) {
+    int rc = backward(h, theta, nullptr, s, c);
+    if (!rc) rc = write_jacobian(h, J, ldJ, j_dtype, rownorm2, s, nullptr, 0, c);
+    if (rc) return rc;
+  }
+  return 0;
 }
 
 int ensure_tangent(dngd_problem* h) {
@@ -177,6 +197,10 @@ int ensure_tangent(dngd_problem* h) {
   rc |= dmalloc(h, (void**)&h->A1[1], b);
   rc |= dmalloc(h, (void**)&h->A2[0], b);
   rc |= dmalloc(h, (void**)&h->A2[1], b);
+  if (h->g.pde == kNavierStokes) {
+    rc |= dmalloc(h, (void**)&h->U1, (size_t)h->g.R * h->g.d_out * sizeof(double));
+    rc |= dmalloc(h, (void**)&h->U2, (size_t)h->g.R * h->g.d_out * sizeof(double));
+  }
   return rc ? DNGD_ENOMEM : 0;
 }
 
@@ -225,9 +249,24 @@ int tangent(dngd_problem* h, const double* theta, const double* dir, int order, 
   }
   const int l = g.L - 1;
   const int win = g.widths[l];
+  if (g.pde == kNavierStokes) {
+    // the operator is nonlinear in the outputs: keep U (the forward's output
+    // jets) and form U1 = a1 W^T + a0 V^T, U2 = a2 W^T + 2 a1 V^T beside it
+    rc = net_rowdot(s, g.R, win, g.d_out, act_in(h, l), Wp(h, dir, l), a1p ? 1.0 : 0.0, a1p,
+                    Wp(h, theta, l), h->U1);
+    if (rc) return rc;
+    if (order >= 2) {
+      rc = a1p ? net_rowdot(s, g.R, win, g.d_out, a2p, Wp(h, theta, l), 2.0, a1p, Wp(h, dir, l),
+                            h->U2)
+               : fill(s, g.R * g.d_out, 0.0, h->U2);
+      if (rc) return rc;
+    }
+    return net_ns_tangent(s, h->rm, h->U, Bp(h, theta, l), h->U1, Bp(h, dir, l), h->U2, order,
+                          out);
+  }
   if (order == 1) {
     // u1 = a1 W^T + a0 V^T (+ c on the value channel)
-    rc = net_rowdot(s, g.R, win, act_in(h, l), Wp(h, dir, l), a1p ? 1.0 : 0.0, a1p,
+    rc = net_rowdot(s, g.R, win, 1, act_in(h, l), Wp(h, dir, l), a1p ? 1.0 : 0.0, a1p,
                     Wp(h, theta, l), h->U);
     if (rc) return rc;
     return net_linear_residual(s, h->rm, h->U, Bp(h, dir, l), out);
@@ -236,7 +275,7 @@ int tangent(dngd_problem* h, const double* theta, const double* dir, int order, 
     return fill(s, g.m, 0.0, out);
   }
   // u2 = a2 W^T + 2 a1 V^T (no bias term)
-  rc = net_rowdot(s, g.R, win, a2p, Wp(h, theta, l), 2.0, a1p, Wp(h, dir, l), h->U);
+  rc = net_rowdot(s, g.R, win, 1, a2p, Wp(h, theta, l), 2.0, a1p, Wp(h, dir, l), h->U);
   if (rc) return rc;
   return net_linear_residual(s, h->rm, h->U, nullptr, out);
 }
@@ -407,11 +446,18 @@ struct Precond {
 // Checks a problem description; need_data == false skips the array pointers
 // (footprint queries before any data is on the device).
 int validate_desc(const dngd_problem_desc* d, bool need_data) {
-  DNGD_REQUIRE(d->pde == DNGD_POISSON || d->pde == DNGD_HEAT, "unknown pde %d", d->pde);
+  DNGD_REQUIRE(d->pde == DNGD_POISSON || d->pde == DNGD_HEAT || d->pde == DNGD_NAVIER_STOKES,
+               "unknown pde %d", d->pde);
   DNGD_REQUIRE(d->n_layers >= 1 && d->n_layers <= kMaxLayers, "n_layers out of range");
   DNGD_REQUIRE(d->widths != nullptr, "widths is null");
   DNGD_REQUIRE(d->widths[0] >= 1 && d->widths[0] <= kMaxDin, "d_in must be in [1, %d]", kMaxDin);
-  DNGD_REQUIRE(d->widths[d->n_layers] == 1, "the network must have one output");
+  if (d->pde == DNGD_NAVIER_STOKES) {
+    DNGD_REQUIRE(d->widths[0] == 2 && d->widths[d->n_layers] == 3,
+                 "Navier-Stokes: the network maps (x, y) to (u, v, p)");
+    DNGD_REQUIRE(d->n_init == 0, "Navier-Stokes: no initial points");
+  } else {
+    DNGD_REQUIRE(d->widths[d->n_layers] == 1, "the network must have one output");
+  }
   for (int l = 1; l < d->n_layers; ++l)
     DNGD_REQUIRE(d->widths[l] >= 1 && d->widths[l] <= kMaxWidth, "hidden width out of range");
   DNGD_REQUIRE(d->n_int >= 0 && d->n_bdy >= 0 && d->n_init >= 0, "negative point count");
@@ -443,7 +489,10 @@ void make_geometry(const dngd_problem_desc* d, Geometry& g) {
   g.n_int = d->n_int;
   g.n_bdy = d->n_bdy;
   g.n_init = d->n_init;
-  g.m = d->n_int + d->n_bdy + d->n_init;
+  g.d_out = d->widths[g.L];
+  g.r_int = (g.pde == DNGD_NAVIER_STOKES) ? 3 : 1;
+  g.r_bdy = (g.pde == DNGD_NAVIER_STOKES) ? 3 : 1;
+  g.m = d->n_int * g.r_int + d->n_bdy * g.r_bdy + d->n_init;
   g.d_in = d->widths[0];
   g.nlap = (g.pde == DNGD_HEAT) ? g.d_in - 1 : g.d_in;
   g.C_int = g.d_in + 2;
@@ -483,9 +532,11 @@ size_t footprint_bytes(const Geometry& g, const dngd_step_opts* o) {
   dngd_step_opts_default(&def);
   if (!o) o = &def;
   size_t b = 0;
-  b += (size_t)g.R * g.d_in * 8 + 2 * (size_t)act_bytes(g) + 2 * (size_t)g.R * 8 + wt_bytes(g);
+  b += (size_t)g.R * g.d_in * 8 + 2 * (size_t)act_bytes(g) + 2 * (size_t)g.R * g.d_out * 8 +
+       wt_bytes(g);
   for (int l = 0; l < g.L - 1; ++l) b += 3 * (size_t)g.R * g.widths[l + 1] * 8;
   if (o->ga || o->solver == DNGD_PCG) b += 6 * (size_t)act_bytes(g);
+  if (o->ga && g.pde == DNGD_NAVIER_STOKES) b += 2 * (size_t)g.R * g.d_out * 8;
   b += step_vec_bytes(g) + vjp_work_bytes(g) + (size_t)g.n * 8 + 256;
   if (o->solver == DNGD_STRUCTURED) {
     // K, solve workspace, point offsets and the two chunk products (no J)
@@ -649,8 +700,8 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   dup(&h->x_int, d->x_int, g.n_int * g.d_in);
   dup(&h->x_bdy, d->x_bdy, g.n_bdy * g.d_in);
   dup(&h->x_init, d->x_init, g.n_init * g.d_in);
-  dup(&h->f_int, d->f_int, g.n_int);
-  dup(&h->g_bdy, d->g_bdy, g.n_bdy);
+  dup(&h->f_int, d->f_int, g.n_int * g.r_int);
+  dup(&h->g_bdy, d->g_bdy, g.n_bdy * g.r_bdy);
   dup(&h->g_init, d->g_init, g.n_init);
   if (!rc) {
     hipError_t e = hipStreamSynchronize(nullptr);
@@ -666,8 +717,8 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   if (!rc) rc = dmalloc(h, (void**)&h->Ab[0], act_bytes(g));
   if (!rc) rc = dmalloc(h, (void**)&h->Ab[1], act_bytes(g));
   if (!rc) rc = dmalloc(h, (void**)&h->WT, wt_bytes(g));
-  if (!rc) rc = dmalloc(h, (void**)&h->seed, (size_t)g.R * sizeof(double));
-  if (!rc) rc = dmalloc(h, (void**)&h->U, (size_t)g.R * sizeof(double));
+  if (!rc) rc = dmalloc(h, (void**)&h->seed, (size_t)g.R * g.d_out * sizeof(double));
+  if (!rc) rc = dmalloc(h, (void**)&h->U, (size_t)g.R * g.d_out * sizeof(double));
   for (int e = 0; e < 10 && !rc; ++e)
     if (hipEventCreate(&h->ev[e]) != hipSuccess) rc = DNGD_EHIP;
   for (int e = 0; e < 2 && !rc; ++e)
@@ -714,7 +765,8 @@ int dngd_footprint_desc(const dngd_problem_desc* d, const dngd_step_opts* o, siz
   if (rc) return rc;
   Geometry g;
   make_geometry(d, g);
-  *bytes = footprint_bytes(g, o) + (size_t)(g.n_int * (g.d_in + 1) + g.n_bdy * (g.d_in + 1) +
+  *bytes = footprint_bytes(g, o) + (size_t)(g.n_int * (g.d_in + g.r_int) +
+                                            g.n_bdy * (g.d_in + g.r_bdy) +
                                             g.n_init * (g.d_in + 1)) * sizeof(double);
   return DNGD_OK;
 }
@@ -730,9 +782,7 @@ int dngd_residual_jacobian(dngd_problem* h, const double* theta, double* r, void
   int rc = forward(h, theta, r, s);
   if (rc) return rc;
   if (!J) return DNGD_OK;
-  rc = backward(h, theta, nullptr, s);
-  if (rc) return rc;
-  return write_jacobian(h, J, ldJ, j_dtype, nullptr, s);
+  return jacobian_all(h, theta, J, ldJ, j_dtype, nullptr, s);
 }
 
 int dngd_gram(int64_t m, int64_t n, const void* J, int64_t ldJ, int32_t j_dtype, int32_t passes,
@@ -1130,6 +1180,8 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda, const 
                      dngd_step_stats* stats, void* stream) {
   DNGD_REQUIRE(h && theta && landmarks && b && x, "dngd_nystrom_pcg: null argument");
   DNGD_REQUIRE(ell >= 1 && ell <= h->g.m, "dngd_nystrom_pcg: ell out of range");
+  DNGD_REQUIRE(h->g.pde != DNGD_NAVIER_STOKES,
+               "dngd_nystrom_pcg: scalar residual classes only (one residual per point)");
   DNGD_REQUIRE(lambda > 0.0 && std::isfinite(lambda), "dngd_nystrom_pcg: lambda must be > 0");
   DNGD_REQUIRE(tol >= 0.0 && maxit >= 0, "dngd_nystrom_pcg: bad tol/maxit");
   hipStream_t s = S(stream);
@@ -1171,6 +1223,10 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
                    o.gram_passes == 4 || o.gram_passes == DNGD_GRAM_F64,
                "bad gram_passes");
   const Geometry& g = h->g;
+  DNGD_REQUIRE(g.pde != DNGD_NAVIER_STOKES || o.solver == DNGD_DENSE || o.solver == DNGD_PRIMAL ||
+                   o.solver == DNGD_DENSE_AUTO,
+               "vector-valued residuals: dense solvers only (DNGD_DENSE, DNGD_PRIMAL, "
+               "DNGD_DENSE_AUTO)");
   hipStream_t s = S(stream);
   StepVecs v;
   Small sm;
@@ -1384,8 +1440,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   // residual + Jacobian (Section 2.2); ||r||^2 flags a non-finite theta or point
   rc = forward(h, theta, v.r, s);
   if (!rc) rc = sumsq(s, g.m, v.r, v.scal + 30, v.red);
-  if (!rc) rc = backward(h, theta, nullptr, s);
-  if (!rc) rc = write_jacobian(h, J, ldJ, jd, v.rownorm2, s);
+  if (!rc) rc = jacobian_all(h, theta, J, ldJ, jd, v.rownorm2, s);
   if (rc) return rc;
 
   // the operator of K = A A^T + lam I and the first system K x = b:

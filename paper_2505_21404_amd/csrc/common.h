@@ -66,7 +66,12 @@ struct Geometry {
   double kappa = 0.0;
   double c_int = 0.0, c_bdy = 0.0, c_init = 0.0;  // N^{-1/2} class scales
   int max_width = 0;
+  int d_out = 1;             // network outputs (widths[L])
+  int r_int = 1, r_bdy = 1;  // residual components per interior / boundary point
 };
+
+// pde value of the steady incompressible Navier-Stokes family (dngd.h)
+constexpr int kNavierStokes = 2;
 
 // Device-side description of where a point's rows are and how its residual
 // is formed from the output jet. Passed by value to kernels.
@@ -77,7 +82,10 @@ struct RowMap {
   int d_in;
   int nlap;
   int pde;
-  double kappa, c_int, c_bdy, c_init;
+  double kappa, c_int, c_bdy, c_init;  // kappa: heat diffusivity or Navier-Stokes viscosity
+  int d_out;                  // network outputs
+  int r_int, r_bdy;           // residual components per interior / boundary point
+  int64_t res_bdy0, res_init0;  // first residual index of the boundary / initial class
 };
 
 RowMap row_map(const Geometry& g);
@@ -212,20 +220,28 @@ int net_input_layer(hipStream_t s, const RowMap& rm, const double* x_int, const 
 int net_bias_act(hipStream_t s, const RowMap& rm, int w, const double* b, double* Z, double* A);
 int net_act_adjoint(hipStream_t s, const RowMap& rm, int w, const double* Z, const double* Abar,
                     double* Zbar);
-int net_rowdot(hipStream_t s, int64_t R, int w, const double* X, const double* wv, double beta,
-               const double* Y, const double* wv2, double* out);
+// out[row * nout + o] = X[row] . wv[o*w..] + beta * Y[row] . wv2[o*w..]
+int net_rowdot(hipStream_t s, int64_t R, int w, int nout, const double* X, const double* wv,
+               double beta, const double* Y, const double* wv2, double* out);
 int net_residual(hipStream_t s, const RowMap& rm, const double* U, const double* bias,
                  const double* f_int, const double* g_bdy, const double* g_init, double* r);
 int net_linear_residual(hipStream_t s, const RowMap& rm, const double* U, const double* bias,
                         double* out);
-int net_seeds(hipStream_t s, const RowMap& rm, const double* p, double* seed);
-int net_outer_seed(hipStream_t s, int64_t R, int w, const double* seed, const double* wL,
-                   double* Abar);
-// pidx == null: all m rows; else row q of J is point pidx[q] (q < nrows)
+// reverse-pass seeds (R x d_out): d/dU of sum_k w_k r_k with w = p (null: the
+// Jacobian's, component comp of every point); U, bias: the forward's output jets
+int net_seeds(hipStream_t s, const RowMap& rm, const double* U, const double* bias,
+              const double* p, int comp, double* seed);
+int net_outer_seed(hipStream_t s, int64_t R, int w, int nout, const double* seed,
+                   const double* wL, double* Abar);
+// Navier-Stokes residual t-derivatives (order 1: J dir, order 2: f_vv)
+int net_ns_tangent(hipStream_t s, const RowMap& rm, const double* U0, const double* b0,
+                   const double* U1, const double* c1, const double* U2, int order, double* out);
+// pidx == null: the rows of residual component comp of every point (every row
+// for one-component classes); else row q of J is point pidx[q] (q < nrows)
 int net_jacobian_rows(hipStream_t s, const Geometry& g, const RowMap& rm, const double* const* A,
                       const double* const* Zbar, const double* seed, void* J, int64_t ldJ,
                       int j_dtype, double* rownorm2, const int64_t* pidx = nullptr,
-                      int64_t nrows = 0);
+                      int64_t nrows = 0, int comp = 0);
 int net_tangent_act(hipStream_t s, const RowMap& rm, int w, const double* b1, const double* Z0,
                     double* Z1, double* Z2, double* A1, double* A2, int order);
 // Nystrom landmark columns without J (net.hip)

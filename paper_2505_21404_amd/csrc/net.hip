@@ -37,6 +37,16 @@ __device__ inline void point_rows(const RowMap& rm, int64_t p, int64_t& base, in
   }
 }
 
+// residual index of component comp of point p (-1 if the point's class has
+// fewer components): classes in order interior, boundary, initial, each
+// point-major (a point's components are consecutive)
+__device__ inline int64_t residual_row(const RowMap& rm, int64_t p, int comp) {
+  if (p < rm.n_int) return comp < rm.r_int ? p * rm.r_int + comp : -1;
+  if (p < rm.n_int + rm.n_bdy)
+    return comp < rm.r_bdy ? rm.res_bdy0 + (p - rm.n_int) * rm.r_bdy + comp : -1;
+  return comp == 0 ? rm.res_init0 + (p - rm.n_int - rm.n_bdy) : -1;
+}
+
 __global__ void input_layer_kernel(RowMap rm, const double* __restrict__ xi,
                                    const double* __restrict__ xb, const double* __restrict__ x0,
                                    double* __restrict__ A0) {
@@ -126,8 +136,10 @@ __global__ __launch_bounds__(256) void act_adjoint_kernel(RowMap rm, int w,
   zb[(int64_t)(1 + d) * w] = s.s1 * abl;
 }
 
-// out[row] = X[row] . wv + beta * Y[row] . wv2   (one wave per row)
-__global__ __launch_bounds__(256) void rowdot_kernel(int64_t R, int w, const double* __restrict__ X,
+// out[row * nout + o] = X[row] . wv_o + beta * Y[row] . wv2_o for the nout rows
+// wv_o = wv + o * w of the output layer's weights (one wave per jet row)
+__global__ __launch_bounds__(256) void rowdot_kernel(int64_t R, int w, int nout,
+                                                     const double* __restrict__ X,
                                                      const double* __restrict__ wv, double beta,
                                                      const double* __restrict__ Y,
                                                      const double* __restrict__ wv2,
@@ -135,13 +147,17 @@ __global__ __launch_bounds__(256) void rowdot_kernel(int64_t R, int w, const dou
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= R) return;
-  double s = 0.0;
-  for (int k = lane; k < w; k += 64) {
-    s += X[row * w + k] * wv[k];
-    if (Y) s += beta * Y[row * w + k] * wv2[k];
+  for (int o = 0; o < nout; ++o) {
+    const double* w1 = wv + (int64_t)o * w;
+    const double* w2 = Y ? wv2 + (int64_t)o * w : nullptr;
+    double s = 0.0;
+    for (int k = lane; k < w; k += 64) {
+      s += X[row * w + k] * w1[k];
+      if (Y) s += beta * Y[row * w + k] * w2[k];
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) out[row * nout + o] = s;
   }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (lane == 0) out[row] = s;
 }
 
 // interior operator on an output jet: -lap u (Poisson) or u_t - kappa lap u (heat)
@@ -197,11 +213,150 @@ __global__ void seeds_kernel(RowMap rm, const double* __restrict__ pv, double* _
   }
 }
 
-__global__ void outer_seed_kernel(int64_t R, int w, const double* __restrict__ seed,
+// Abar of the last hidden layer: Ab[row][j] = sum_o seed[row][o] W_L[o][j]
+__global__ void outer_seed_kernel(int64_t R, int w, int nout, const double* __restrict__ seed,
                                   const double* __restrict__ wL, double* __restrict__ Ab) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= R * w) return;
-  Ab[idx] = seed[idx / w] * wL[idx % w];
+  const int64_t row = idx / w;
+  const int j = (int)(idx % w);
+  double a = 0.0;
+  for (int o = 0; o < nout; ++o) a += seed[row * nout + o] * wL[(int64_t)o * w + j];
+  Ab[idx] = a;
+}
+
+// ---------------------------------------------------------------------------
+// Steady incompressible Navier-Stokes residuals (vector-valued classes). The
+// network outputs (u, v, p); an interior point's four jet rows (value, d/dx,
+// d/dy, Laplacian) each hold the three outputs, and its three residuals are
+//   x-momentum  u u_x + v u_y + p_x - nu lap u
+//   y-momentum  u v_x + v v_y + p_y - nu lap v
+//   continuity  u_x + v_y
+// (nu = rm.kappa). A boundary point's three residuals are its outputs against
+// the prescribed values. Residual rows are point-major within a class.
+
+struct NSCh {
+  double u, v, p, ux, uy, vx, vy, px, py, lu, lv;
+};
+
+// the operator's inputs at an interior point; bias (may be null) enters the values
+__device__ inline NSCh ns_channels(const double* __restrict__ U, int64_t base,
+                                   const double* __restrict__ bias) {
+  const double* r = U + base * 3;
+  NSCh c;
+  c.u = r[0] + (bias ? bias[0] : 0.0);
+  c.v = r[1] + (bias ? bias[1] : 0.0);
+  c.p = r[2] + (bias ? bias[2] : 0.0);
+  c.ux = r[3];
+  c.vx = r[4];
+  c.px = r[5];
+  c.uy = r[6];
+  c.vy = r[7];
+  c.py = r[8];
+  c.lu = r[9];
+  c.lv = r[10];
+  return c;
+}
+
+// derivative of the operator at a in the direction b
+__device__ inline void ns_linear(const NSCh& a, const NSCh& b, double nu, double out[3]) {
+  out[0] = a.u * b.ux + b.u * a.ux + a.v * b.uy + b.v * a.uy + b.px - nu * b.lu;
+  out[1] = a.u * b.vx + b.u * a.vx + a.v * b.vy + b.v * a.vy + b.py - nu * b.lv;
+  out[2] = b.ux + b.vy;
+}
+
+__global__ void ns_residual_kernel(RowMap rm, const double* __restrict__ U,
+                                   const double* __restrict__ bias, const double* __restrict__ f,
+                                   const double* __restrict__ g, double* __restrict__ r) {
+  const int64_t npts = rm.n_int + rm.n_bdy;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const double nu = rm.kappa;
+  if (p < rm.n_int) {
+    const NSCh c = ns_channels(U, p * rm.C_int, bias);
+    const double* fp = f ? f + p * 3 : nullptr;
+    r[p * 3 + 0] = rm.c_int * (c.u * c.ux + c.v * c.uy + c.px - nu * c.lu - (fp ? fp[0] : 0.0));
+    r[p * 3 + 1] = rm.c_int * (c.u * c.vx + c.v * c.vy + c.py - nu * c.lv - (fp ? fp[1] : 0.0));
+    r[p * 3 + 2] = rm.c_int * (c.ux + c.vy - (fp ? fp[2] : 0.0));
+  } else {
+    const int64_t pb = p - rm.n_int;
+    const double* u = U + (rm.R_int + pb) * 3;
+    for (int o = 0; o < 3; ++o)
+      r[rm.res_bdy0 + pb * 3 + o] =
+          rm.c_bdy * (u[o] + (bias ? bias[o] : 0.0) - (g ? g[pb * 3 + o] : 0.0));
+  }
+}
+
+// t-derivatives of the residual along theta + t dir from the output jets'
+// t-derivatives U0 (+ b0), U1 (+ c1), U2: order 1 gives J dir = DN(U0)[U1];
+// order 2 gives f_vv = DN(U0)[U2] + 2 B(U1, U1), B the operator's quadratic part
+__global__ void ns_tangent_kernel(RowMap rm, const double* __restrict__ U0,
+                                  const double* __restrict__ b0, const double* __restrict__ U1,
+                                  const double* __restrict__ c1, const double* __restrict__ U2,
+                                  int order, double* __restrict__ out) {
+  const int64_t npts = rm.n_int + rm.n_bdy;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const double nu = rm.kappa;
+  if (p < rm.n_int) {
+    const int64_t base = p * rm.C_int;
+    const NSCh a = ns_channels(U0, base, b0);
+    const NSCh b = ns_channels(U1, base, c1);
+    double o3[3];
+    if (order == 1) {
+      ns_linear(a, b, nu, o3);
+    } else {
+      const NSCh d = ns_channels(U2, base, nullptr);
+      ns_linear(a, d, nu, o3);
+      o3[0] += 2.0 * (b.u * b.ux + b.v * b.uy);
+      o3[1] += 2.0 * (b.u * b.vx + b.v * b.vy);
+    }
+    for (int k = 0; k < 3; ++k) out[p * 3 + k] = rm.c_int * o3[k];
+  } else {
+    const int64_t pb = p - rm.n_int;
+    const int64_t row = (rm.R_int + pb) * 3;
+    for (int o = 0; o < 3; ++o) {
+      const double x = (order == 1) ? U1[row + o] + (c1 ? c1[o] : 0.0) : U2[row + o];
+      out[rm.res_bdy0 + pb * 3 + o] = rm.c_bdy * x;
+    }
+  }
+}
+
+// Reverse-pass seeds: d/dU of sum_k w_k r_k for each point's residuals, with
+// w = pw (the weights of a vector-Jacobian product) or w_k = [k == comp] (one
+// Jacobian row per point). seed is R x 3 like U.
+__global__ void ns_seeds_kernel(RowMap rm, const double* __restrict__ U,
+                                const double* __restrict__ bias, const double* __restrict__ pw,
+                                int comp, double* __restrict__ seed) {
+  const int64_t npts = rm.n_int + rm.n_bdy;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const double nu = rm.kappa;
+  if (p < rm.n_int) {
+    const int64_t base = p * rm.C_int;
+    const NSCh a = ns_channels(U, base, bias);
+    double w[3];
+    for (int k = 0; k < 3; ++k)
+      w[k] = rm.c_int * (pw ? pw[p * 3 + k] : (k == comp ? 1.0 : 0.0));
+    double* s0 = seed + base * 3;  // value row, then d/dx, d/dy, Laplacian rows
+    s0[0] = w[0] * a.ux + w[1] * a.vx;
+    s0[1] = w[0] * a.uy + w[1] * a.vy;
+    s0[2] = 0.0;
+    s0[3] = w[0] * a.u + w[2];
+    s0[4] = w[1] * a.u;
+    s0[5] = w[0];
+    s0[6] = w[0] * a.v;
+    s0[7] = w[1] * a.v + w[2];
+    s0[8] = w[1];
+    s0[9] = -nu * w[0];
+    s0[10] = -nu * w[1];
+    s0[11] = 0.0;
+  } else {
+    const int64_t pb = p - rm.n_int;
+    double* s0 = seed + (rm.R_int + pb) * 3;
+    for (int o = 0; o < 3; ++o)
+      s0[o] = rm.c_bdy * (pw ? pw[rm.res_bdy0 + pb * 3 + o] : (o == comp ? 1.0 : 0.0));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -237,13 +392,21 @@ template <typename T>
 __global__ __launch_bounds__(256) void jacobian_rows_kernel(RowMap rm, JacLayers jl, T* __restrict__ J,
                                                             int64_t ldJ, int64_t n,
                                                             double* __restrict__ rownorm2,
-                                                            const int64_t* __restrict__ pidx) {
+                                                            const int64_t* __restrict__ pidx,
+                                                            int comp) {
   __shared__ double red[4];
   const int64_t p = pidx ? pidx[blockIdx.x] : (int64_t)blockIdx.x;
+  // the J row of residual component `comp` of point p (row q of a gathered
+  // set when pidx is given); points without that component have no row
+  int64_t jrow = blockIdx.x;
+  if (!pidx) {
+    jrow = residual_row(rm, p, comp);
+    if (jrow < 0) return;  // uniform over the workgroup
+  }
   int64_t base;
   int C;
   point_rows(rm, p, base, C);
-  T* row = J + (int64_t)blockIdx.x * ldJ;
+  T* row = J + jrow * ldJ;
   const int t = threadIdx.x;
   double ss = 0.0;
   // the point's adjoints of a chunk of JOC outputs, staged in LDS (every
@@ -323,7 +486,7 @@ __global__ __launch_bounds__(256) void jacobian_rows_kernel(RowMap rm, JacLayers
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
     if ((t & 63) == 0) red[t >> 6] = ss;
     __syncthreads();
-    if (t == 0) rownorm2[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (t == 0) rownorm2[jrow] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
 
@@ -515,6 +678,11 @@ RowMap row_map(const Geometry& g) {
   r.c_int = g.c_int;
   r.c_bdy = g.c_bdy;
   r.c_init = g.c_init;
+  r.d_out = g.widths[g.L];
+  r.r_int = g.r_int;
+  r.r_bdy = g.r_bdy;
+  r.res_bdy0 = g.n_int * g.r_int;
+  r.res_init0 = r.res_bdy0 + g.n_bdy * g.r_bdy;
   return r;
 }
 
@@ -545,10 +713,10 @@ int net_act_adjoint(hipStream_t s, const RowMap& rm, int w, const double* Z, con
   return 0;
 }
 
-int net_rowdot(hipStream_t s, int64_t R, int w, const double* X, const double* wv, double beta,
-               const double* Y, const double* wv2, double* out) {
-  hipLaunchKernelGGL(rowdot_kernel, dim3(blocks_for(R, 4)), dim3(256), 0, s, R, w, X, wv, beta, Y,
-                     wv2, out);
+int net_rowdot(hipStream_t s, int64_t R, int w, int nout, const double* X, const double* wv,
+               double beta, const double* Y, const double* wv2, double* out) {
+  hipLaunchKernelGGL(rowdot_kernel, dim3(blocks_for(R, 4)), dim3(256), 0, s, R, w, nout, X, wv,
+                     beta, Y, wv2, out);
   DNGD_LAUNCH_CHECK();
   return 0;
 }
@@ -556,6 +724,12 @@ int net_rowdot(hipStream_t s, int64_t R, int w, const double* X, const double* w
 int net_residual(hipStream_t s, const RowMap& rm, const double* U, const double* bias,
                  const double* f, const double* g, const double* g0, double* r) {
   const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  if (rm.pde == kNavierStokes) {
+    hipLaunchKernelGGL(ns_residual_kernel, dim3(blocks_for(npts)), dim3(256), 0, s, rm, U, bias, f,
+                       g, r);
+    DNGD_LAUNCH_CHECK();
+    return 0;
+  }
   hipLaunchKernelGGL(residual_kernel, dim3(blocks_for(npts)), dim3(256), 0, s, rm, U, bias, f, g,
                      g0, r);
   DNGD_LAUNCH_CHECK();
@@ -567,24 +741,32 @@ int net_linear_residual(hipStream_t s, const RowMap& rm, const double* U, const 
   return net_residual(s, rm, U, bias, nullptr, nullptr, nullptr, out);
 }
 
-int net_seeds(hipStream_t s, const RowMap& rm, const double* p, double* seed) {
+int net_seeds(hipStream_t s, const RowMap& rm, const double* U, const double* bias,
+              const double* p, int comp, double* seed) {
   const int64_t npts = rm.n_int + rm.n_bdy + rm.n_init;
+  if (rm.pde == kNavierStokes) {
+    hipLaunchKernelGGL(ns_seeds_kernel, dim3(blocks_for(npts)), dim3(256), 0, s, rm, U, bias, p,
+                       comp, seed);
+    DNGD_LAUNCH_CHECK();
+    return 0;
+  }
   hipLaunchKernelGGL(seeds_kernel, dim3(blocks_for(npts)), dim3(256), 0, s, rm, p, seed);
   DNGD_LAUNCH_CHECK();
   return 0;
 }
 
-int net_outer_seed(hipStream_t s, int64_t R, int w, const double* seed, const double* wL,
-                   double* Ab) {
-  hipLaunchKernelGGL(outer_seed_kernel, dim3(blocks_for(R * w)), dim3(256), 0, s, R, w, seed, wL,
-                     Ab);
+int net_outer_seed(hipStream_t s, int64_t R, int w, int nout, const double* seed,
+                   const double* wL, double* Ab) {
+  hipLaunchKernelGGL(outer_seed_kernel, dim3(blocks_for(R * w)), dim3(256), 0, s, R, w, nout, seed,
+                     wL, Ab);
   DNGD_LAUNCH_CHECK();
   return 0;
 }
 
 int net_jacobian_rows(hipStream_t s, const Geometry& g, const RowMap& rm, const double* const* A,
                       const double* const* Zb, const double* seed, void* J, int64_t ldJ,
-                      int j_dtype, double* rownorm2, const int64_t* pidx, int64_t nrows) {
+                      int j_dtype, double* rownorm2, const int64_t* pidx, int64_t nrows,
+                      int comp) {
   JacLayers jl;
   jl.L = g.L;
   for (int l = 0; l < g.L; ++l) {
@@ -595,14 +777,23 @@ int net_jacobian_rows(hipStream_t s, const Geometry& g, const RowMap& rm, const 
     jl.woff[l] = g.w_off[l];
     jl.boff[l] = g.b_off[l];
   }
-  dim3 grid((unsigned)(pidx ? nrows : g.m));
+  dim3 grid((unsigned)(pidx ? nrows : g.n_int + g.n_bdy + g.n_init));
   if (grid.x == 0) return 0;
   if (j_dtype == 0)
     hipLaunchKernelGGL(jacobian_rows_kernel<double>, grid, dim3(256), 0, s, rm, jl,
-                       static_cast<double*>(J), ldJ, g.n, rownorm2, pidx);
+                       static_cast<double*>(J), ldJ, g.n, rownorm2, pidx, comp);
   else
     hipLaunchKernelGGL(jacobian_rows_kernel<float>, grid, dim3(256), 0, s, rm, jl,
-                       static_cast<float*>(J), ldJ, g.n, rownorm2, pidx);
+                       static_cast<float*>(J), ldJ, g.n, rownorm2, pidx, comp);
+  DNGD_LAUNCH_CHECK();
+  return 0;
+}
+
+int net_ns_tangent(hipStream_t s, const RowMap& rm, const double* U0, const double* b0,
+                   const double* U1, const double* c1, const double* U2, int order, double* out) {
+  const int64_t npts = rm.n_int + rm.n_bdy;
+  hipLaunchKernelGGL(ns_tangent_kernel, dim3(blocks_for(npts)), dim3(256), 0, s, rm, U0, b0, U1, c1,
+                     U2, order, out);
   DNGD_LAUNCH_CHECK();
   return 0;
 }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdngd.so")
 OK, ENOCONV, EINVAL, ENOMEM, EHIP, ENOTPD, ENAN = 0, 1, -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 GRAM_F64 = 64   # gram_passes value: FP64-product Gram of an FP32 J
-POISSON, HEAT = 0, 1
+POISSON, HEAT, NAVIER_STOKES = 0, 1, 2
 PLAIN, MIXED = 0, 1
 DENSE, PCG, PRIMAL, DENSE_AUTO, STRUCTURED = 0, 1, 2, 3, 4
 
