@@ -142,6 +142,15 @@ typedef struct {
      any step with GA) */
   double* alpha_out;
   double* fvv_out;
+  /* Nystrom preconditioner (solver == DNGD_PCG) */
+  int64_t nystrom_chunk_rows;  /* jet rows per chunk of the landmark-column products
+                                  (0 = sized for about 8 GB of products per chunk) */
+  int32_t nystrom_reuse;       /* 0: build from `landmarks` every step (default); R > 0:
+                                  reuse the factors of this handle's last PCG step for up
+                                  to R further steps (landmarks are then ignored; only the
+                                  l x l system is refactored when lambda changes) -- the
+                                  preconditioner is built once and reused (Section 4) */
+  int32_t reserved_opts;
 } dngd_step_opts;
 
 /* gram_passes / dngd_gram passes value: FP64-product Gram of an FP32 J */
@@ -162,6 +171,9 @@ typedef struct {
   int32_t pcg_iterations_ga;  /* PCG with GA: iterations of the second (f_vv) solve */
   int32_t primal;             /* 1 if the step solved the primal n x n system */
   int32_t reserved2;
+  double nystrom_shift;       /* PCG: delta added to K_II before its factorisation */
+  int32_t nystrom_reused;     /* PCG: 1 if the step reused earlier Nystrom factors */
+  int32_t reserved3;
 } dngd_step_stats;
 
 const char* dngd_last_error(void);

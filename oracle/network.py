@@ -228,34 +228,65 @@ def _tanh_jet_adjoint(z: Jet, abar: Jet) -> Jet:
     return Jet(vbar, gbar, lbar, nl)
 
 
-def _jacobian_class(theta, widths, x, nlap, seed_v, seed_g, seed_l):
-    """Rows d r_i / d theta for one point class, where r_i is the linear
-    functional seed_v*u.v + <seed_g, u.g> + seed_l*u.l of the output jet at x_i
-    (seed_* are per-point arrays: (N,), (N, d), (N,) for one output, or with a
-    trailing output axis (N, o), (N, d, o), (N, o) for o outputs). Returns (N, n)."""
+def _tape_class(theta, widths, x, nlap, seed_v, seed_g, seed_l):
+    """Reverse pass over the jets of one point class: for every affine layer l,
+    its input jet a_{l-1} and the adjoint zbar_l of its output jet, where the
+    output jet's adjoint is the seed. A row of J is then, per layer,
+    W_l-bar = sum over channels of zbar_l (x) a_{l-1} and b_l-bar = zbar_l.v.
+    Seeds are per-point arrays: (N,), (N, d), (N,) for one output, or with a
+    trailing output axis (N, o), (N, d, o), (N, o) for o outputs."""
     layers = unpack(theta, widths)
     _, tape = forward(theta, widths, x, nlap, keep=True)
-    N = x.shape[0]
-    d = x.shape[1]
     if seed_v.ndim == 1:
         seed_v, seed_g, seed_l = seed_v[:, None], seed_g[:, :, None], seed_l[:, None]
     # adjoint of the output jet
     zbar = Jet(seed_v.astype(theta.dtype), seed_g.astype(theta.dtype),
                seed_l.astype(theta.dtype), nlap)
-    grads = [None] * len(layers)
+    out = [None] * len(layers)
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
-        a_prev = tape[li][1]
-        # z = a_prev W^T + b on every channel  =>  Wbar_i = sum_ch zbar_ch (x) a_prev_ch
-        Wbar = (np.einsum("no,ni->noi", zbar.v, a_prev.v)
-                + np.einsum("ndo,ndi->noi", zbar.g, a_prev.g)
-                + np.einsum("no,ni->noi", zbar.l, a_prev.l))
-        grads[li] = (Wbar.reshape(N, -1), zbar.v.copy())
+        out[li] = (tape[li][1], zbar)
         if li == 0:
             break
         abar = Jet(zbar.v @ W, zbar.g @ W, zbar.l @ W, nlap)
         zbar = _tanh_jet_adjoint(tape[li][0], abar)
-    return np.concatenate([np.concatenate([gW, gb], axis=1) for gW, gb in grads], axis=1)
+    return out
+
+
+def _layer_rows(a_prev: Jet, zbar: Jet, o0=0, o1=None):
+    """J's columns of W_l rows o0..o1 (row-major [out][in]) and of b_l[o0:o1]
+    for the points of one class: z = a_prev W^T + b on every channel, so
+    W-bar[o][i] = sum_ch zbar_ch[o] a_prev_ch[i] and b-bar = zbar.v."""
+    zv, zg, zl = zbar.v[:, o0:o1], zbar.g[:, :, o0:o1], zbar.l[:, o0:o1]
+    Wbar = (np.einsum("no,ni->noi", zv, a_prev.v)
+            + np.einsum("ndo,ndi->noi", zg, a_prev.g)
+            + np.einsum("no,ni->noi", zl, a_prev.l))
+    return Wbar.reshape(Wbar.shape[0], -1), zv.copy()
+
+
+def _jacobian_class(theta, widths, x, nlap, seed_v, seed_g, seed_l):
+    """Rows d r_i / d theta for one point class, where r_i is the linear
+    functional seed_v*u.v + <seed_g, u.g> + seed_l*u.l of the output jet at x_i
+    (seed shapes as in _tape_class). Returns (N, n)."""
+    tape = _tape_class(theta, widths, x, nlap, seed_v, seed_g, seed_l)
+    return np.concatenate([np.concatenate(_layer_rows(a, z), axis=1) for a, z in tape], axis=1)
+
+
+def _class_seeds(problem, c, N):
+    """Output-jet seeds of the residuals of class c (0 interior, 1 boundary,
+    2 initial) at N points, scalar residual families: r_i is c_gamma times a
+    linear functional of the output jet (Section 2.2)."""
+    ci, cb, c0 = class_scales(problem)
+    d = problem.d_in
+    sv, sg, sl = np.zeros(N), np.zeros((N, d)), np.zeros(N)
+    if c == 0 and problem.pde == POISSON:
+        sl[:] = -ci
+    elif c == 0:
+        sg[:, d - 1] = ci
+        sl[:] = -ci * problem.kappa
+    else:
+        sv[:] = cb if c == 1 else c0
+    return sv, sg, sl
 
 
 def jacobian(problem, theta, chunk=512):
@@ -263,31 +294,68 @@ def jacobian(problem, theta, chunk=512):
     flat parameter layout."""
     if problem.pde == NAVIER_STOKES:
         return _ns().jacobian(problem, theta)
-    ci, cb, c0 = class_scales(problem)
     nl = nlap_of(problem)
-    d = problem.d_in
     rows = []
-
-    def run(x, sv, sg, sl):
-        for s in range(0, x.shape[0], chunk):
-            e = slice(s, s + chunk)
+    for c, (N, x) in enumerate(((problem.n_int, problem.x_int), (problem.n_bdy, problem.x_bdy),
+                                (problem.n_init, problem.x_init))):
+        if not N:
+            continue
+        sv, sg, sl = _class_seeds(problem, c, N)
+        for s0 in range(0, N, chunk):
+            e = slice(s0, s0 + chunk)
             rows.append(_jacobian_class(theta, problem.widths, x[e], nl, sv[e], sg[e], sl[e]))
-
-    if problem.n_int:
-        N = problem.n_int
-        sv = np.zeros(N)
-        sg = np.zeros((N, d))
-        sl = np.zeros(N)
-        if problem.pde == POISSON:
-            sl[:] = -ci
-        else:
-            sg[:, d - 1] = ci
-            sl[:] = -ci * problem.kappa
-        run(problem.x_int, sv, sg, sl)
-    for N, x, c in ((problem.n_bdy, problem.x_bdy, cb), (problem.n_init, problem.x_init, c0)):
-        if N:
-            run(x, np.full(N, c), np.zeros((N, d)), np.zeros(N))
     return np.concatenate(rows, axis=0)
+
+
+# ----------------------------------------------------------------------------
+# Jacobians too large to form (FP64 J of the heat workload is 207 GB): the
+# same reverse pass, kept per layer for all residuals, gives column blocks of J
+# and the product J^T p without the whole matrix.
+
+
+def layer_tapes(problem, theta, weights=None):
+    """Per class, the reverse pass's (a_{l-1}, zbar_l) of every layer
+    (``_tape_class``), scalar residual families. With ``weights`` (m) the seeds
+    of residual i are multiplied by weights[i] (the adjoints of J^T weights)."""
+    nl = nlap_of(problem)
+    out, off = [], 0
+    for c, (N, x) in enumerate(((problem.n_int, problem.x_int), (problem.n_bdy, problem.x_bdy),
+                                (problem.n_init, problem.x_init))):
+        if not N:
+            continue
+        sv, sg, sl = _class_seeds(problem, c, N)
+        if weights is not None:
+            w = weights[off:off + N]
+            sv, sg, sl = sv * w, sg * w[:, None], sl * w
+        out.append(_tape_class(theta, problem.widths, x, nl, sv, sg, sl))
+        off += N
+    return out
+
+
+def jacobian_block(tapes, l, o0, o1):
+    """Columns of J for W_l rows o0..o1 (contiguous in theta) and for
+    b_l[o0:o1] (contiguous), all m rows: (m x (o1-o0) w_{l-1}, m x (o1-o0))."""
+    parts = [_layer_rows(t[l][0], t[l][1], o0, o1) for t in tapes]
+    return (np.concatenate([p[0] for p in parts], axis=0),
+            np.concatenate([p[1] for p in parts], axis=0))
+
+
+def vjp(problem, theta, p):
+    """J^T p without forming J: the reverse pass with residual i's seed scaled
+    by p_i, its weight gradients summed over the points (Section 2.2, where
+    the loss gradient is J^T r)."""
+    if problem.pde == NAVIER_STOKES:
+        return jacobian(problem, theta).T @ p
+    tapes = layer_tapes(problem, theta, weights=p)
+    grads = []
+    for l in range(len(problem.widths) - 1):
+        Wg, bg = 0.0, 0.0
+        for t in tapes:
+            a, z = t[l]
+            Wg = Wg + z.v.T @ a.v + np.einsum("ndo,ndi->oi", z.g, a.g) + z.l.T @ a.l
+            bg = bg + z.v.sum(axis=0)
+        grads.append(np.concatenate([np.ravel(Wg), bg]))
+    return np.concatenate(grads)
 
 
 def _class_of(problem, idx):
@@ -325,24 +393,14 @@ def residual_rows(problem, theta, idx):
 
 def jacobian_rows(problem, theta, idx):
     """Rows idx of J, each from its own point (seeds as in ``jacobian``)."""
-    ci, cb, c0 = class_scales(problem)
     nl = nlap_of(problem)
-    d = problem.d_in
     cls, pt = _class_of(problem, idx)
     out = np.empty((len(cls), n_params(problem.widths)))
-    for c, scale in ((0, ci), (1, cb), (2, c0)):
+    for c in (0, 1, 2):
         sel = np.nonzero(cls == c)[0]
         if not len(sel):
             continue
-        N = len(sel)
-        sv, sg, sl = np.zeros(N), np.zeros((N, d)), np.zeros(N)
-        if c == 0 and problem.pde == POISSON:
-            sl[:] = -scale
-        elif c == 0:
-            sg[:, d - 1] = scale
-            sl[:] = -scale * problem.kappa
-        else:
-            sv[:] = scale
+        sv, sg, sl = _class_seeds(problem, c, len(sel))
         out[sel] = _jacobian_class(theta, problem.widths, _class_points(problem, c)[pt[sel]], nl,
                                    sv, sg, sl)
     return out

@@ -3,20 +3,20 @@ system (FP64 CPU).
 
 Test infrastructure only (see ``oracle/__init__.py``).
 
-Nystrom construction (Section 4.2 and its appendix algorithm): with landmark
-index set I (passed in; how it is drawn is the caller's business),
-    K_II = Q Lambda_Q Q^T          (keep the positive eigenpairs, rank r)
-    U~_I = Q,  U~_C = K_CI Q Lambda_Q^{-1}
-    M = U~ Lambda_Q^{1/2} = V Sigma W^T (thin SVD)
-    U = V,  Lambda^ = Sigma^2
-Spectral preconditioner (Section 3.3):
-    P^{-1} = U (Lambda^ + lam I)^{-1} U^T + (I - U U^T) / lam
-PCG (appendix algorithm) is run on the alpha form of the dual system,
-(K + lam I) alpha = r, and the step is dtheta = -J^T alpha.
+Section 3.3 approximates the residual Gramian K from its landmark columns
+K_{:,I} (index set I, passed in; how it is drawn is the caller's business) by
+the Nystrom approximation K^ = K_{:,I} K_II^+ K_{I,:}, written here as that
+product with the pseudo-inverse of K_II (eigenvalues at or below a positivity
+threshold dropped), and takes K^'s nonzero eigenpairs (U, Lambda^). The
+spectral preconditioner is then
+    P^{-1} = U (Lambda^ + lam I)^{-1} U^T + (I - U U^T) / lam,
+which equals (K^ + lam I)^{-1}. PCG (appendix algorithm) runs on the alpha
+form of the dual system, (K + lam I) alpha = r, and the step is dtheta = -J^T alpha.
 """
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg as sla
 
 
 def positive_threshold(Kii, ell_factor=None):
@@ -27,21 +27,32 @@ def positive_threshold(Kii, ell_factor=None):
     return ell * np.finfo(np.float64).eps * 0.5 * lmax
 
 
-def nystrom(K_cols, I):
-    """(U, Lambda^) from the m x ell block K[:, I] and the landmark indices."""
-    m, ell = K_cols.shape
+def nystrom_approx(K_cols, I, delta=None):
+    """(K^, rank) with K^ = K_{:,I} K_II^+ K_{I,:} from the m x ell block
+    K[:, I]. K_II^+ is the pseudo-inverse keeping the eigenvalues above
+    ``positive_threshold``; with ``delta`` it is (K_II + delta I)^{-1} instead
+    (the shifted form a Cholesky-based construction uses), evaluated as M M^T
+    with M = K_{:,I} L^{-T}, L L^T = K_II + delta I (the product with the
+    explicit inverse loses ~ ||K|| / delta digits when K_II is singular)."""
     Kii = K_cols[I, :]
     Kii = 0.5 * (Kii + Kii.T)
-    lam_q, Q = np.linalg.eigh(Kii)
-    keep = lam_q > positive_threshold(Kii)
-    lam_q, Q = lam_q[keep], Q[:, keep]
-    C = np.setdiff1d(np.arange(m), I)
-    Ut = np.zeros((m, Q.shape[1]))
-    Ut[I, :] = Q
-    Ut[C, :] = K_cols[C, :] @ Q / lam_q
-    M = Ut * np.sqrt(lam_q)
-    V, S, _ = np.linalg.svd(M, full_matrices=False)
-    return V, S ** 2
+    if delta is None:
+        lam_q, Q = np.linalg.eigh(Kii)
+        keep = lam_q > positive_threshold(Kii)
+        inv = (Q[:, keep] / lam_q[keep]) @ Q[:, keep].T
+        return K_cols @ inv @ K_cols.T, int(keep.sum())
+    L = np.linalg.cholesky(Kii + delta * np.eye(len(I)))
+    M = sla.solve_triangular(L, K_cols.T, lower=True).T
+    return M @ M.T, len(I)
+
+
+def nystrom(K_cols, I):
+    """(U, Lambda^): the eigenpairs of K^ with its `rank` largest eigenvalues
+    (the others are zero up to rounding), U with orthonormal columns."""
+    Khat, rank = nystrom_approx(K_cols, I)
+    w, V = np.linalg.eigh(0.5 * (Khat + Khat.T))
+    order = np.argsort(w)[::-1][:rank]
+    return V[:, order], w[order]
 
 
 def precond_apply(U, lam_hat, lam, x):

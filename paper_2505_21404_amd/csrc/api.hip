@@ -34,6 +34,18 @@ using namespace dngd;
 // ---------------------------------------------------------------------------
 // problem handle
 
+// Nystrom preconditioner in Woodbury form (see dngd_nystrom_pcg)
+struct Precond {
+  double* Mt = nullptr;  // ell x m   (L_I^{-1} K_{I,:})
+  double* G = nullptr;   // ell x ell (lambda I + Mt Mt^T, Cholesky factor)
+  double* tl = nullptr;    // ell scratch vector
+  double* Gaux = nullptr;  // solve workspace for chol(G)
+  int64_t ldM = 0;
+  double delta = 0;
+  int64_t ell = 0;
+  double lambda = 0;
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -66,6 +78,10 @@ struct dngd_problem {
   // side stream and events of the factorisation's look-ahead
   hipStream_t side = nullptr;
   hipEvent_t cev[2] = {nullptr, nullptr};
+  // Nystrom preconditioner of the last PCG step (in K's buffer), its age in
+  // steps; -1 when K's buffer holds something else
+  Precond pc;
+  int pc_age = -1;
 };
 
 namespace {
@@ -431,17 +447,6 @@ int dense_solve(dngd_problem* h, const DenseOp& op, const StepVecs& v, const dou
   return 0;
 }
 
-// Nystrom preconditioner in Woodbury form (see dngd_nystrom_pcg)
-struct Precond {
-  double* Mt = nullptr;  // ell x m   (L_I^{-1} K_{I,:})
-  double* G = nullptr;   // ell x ell (lambda I + Mt Mt^T, Cholesky factor)
-  double* tl = nullptr;    // ell scratch vector
-  double* Gaux = nullptr;  // solve workspace for chol(G)
-  int64_t ldM = 0;
-  double delta = 0;
-  int64_t ell = 0;
-  double lambda = 0;
-};
 
 // Checks a problem description; need_data == false skips the array pointers
 // (footprint queries before any data is on the device).
@@ -952,8 +957,33 @@ int structured_gram(dngd_problem* h, const double* theta, double lambda, double*
   return add_diag(s, g.m, K, ldK, lambda);
 }
 
+// G = lam I + Mt Mt^T, factorised and prepared for solves (the Woodbury
+// form's small system; redone alone when only lambda changes)
+int pcg_factor_G(dngd_problem* h, Precond& P, double lambda, hipStream_t s) {
+  const Geometry& g = h->g;
+  StepVecs v;
+  int rc = carve_vecs(h, v);
+  if (rc) return rc;
+  const int64_t ell = P.ell;
+  const size_t gw = gram_workspace_bytes(ell, g.m, DNGD_F64, 1, nullptr);
+  rc = ensure(h, h->gram_work, gw);
+  if (rc) return rc;
+  rc = gram_launch(s, ell, g.m, P.Mt, P.ldM, DNGD_F64, 1, lambda, P.G, ell, h->gram_work.p, gw);
+  if (rc) return rc;
+  rc = chol_factor(s, ell, P.G, ell, reinterpret_cast<int64_t*>(v.scal), P.Gaux, nullptr);
+  if (rc) return rc;
+  int64_t hinfo = 1;
+  DNGD_HIP(hipMemcpyAsync(&hinfo, v.scal, 8, hipMemcpyDeviceToHost, s));
+  DNGD_HIP(hipStreamSynchronize(s));
+  DNGD_REQUIRE(hinfo == 0, "Nystrom: lam I + M^T M not positive definite");
+  P.lambda = lambda;
+  return chol_prepare_solve(s, ell, P.G, ell, P.Gaux);
+}
+
+// chunk_rows: jet rows per chunk of the landmark-column products (0 = sized
+// for about 8 GB of products)
 int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t* I, int64_t ell,
-              Precond& P, hipStream_t s) {
+              Precond& P, hipStream_t s, int64_t chunk_rows = 0) {
   const Geometry& g = h->g;
   // landmark indices: validated on the host before any kernel reads them
   std::vector<int64_t> hI(ell);
@@ -974,7 +1004,8 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
   }
   const int64_t RI = qoff[ell];
   const int64_t ldM = round_up(g.m, 4);
-  const int64_t RC = nystrom_chunk_rows(g, RI);
+  const int64_t RC = chunk_rows > 0 ? std::max<int64_t>(chunk_rows, g.C_int)
+                                    : nystrom_chunk_rows(g, RI);
   // work (h->J): landmark row lists, gathered G_I and H_I, chunk products Gp, Hp
   const size_t bRows = (size_t)(RI + ell + 1) * 8, bGath = 2 * (size_t)RI * g.max_width * 8;
   const size_t bProd = 2 * (size_t)RC * RI * 8;
@@ -1064,18 +1095,7 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
   // Mt = L_I^{-1} K_{I,:}
   rc = trsm_lower_left(s, ell, LI, ell, g.m, P.Mt, ldM);
   if (rc) return rc;
-  // G = lam I + Mt Mt^T, factorised
-  const size_t gw = gram_workspace_bytes(ell, g.m, DNGD_F64, 1, nullptr);
-  rc = ensure(h, h->gram_work, gw);
-  if (rc) return rc;
-  rc = gram_launch(s, ell, g.m, P.Mt, ldM, DNGD_F64, 1, lambda, P.G, ell, h->gram_work.p, gw);
-  if (rc) return rc;
-  rc = chol_factor(s, ell, P.G, ell, reinterpret_cast<int64_t*>(v.scal), P.Gaux, nullptr);
-  if (rc) return rc;
-  DNGD_HIP(hipMemcpyAsync(&hinfo, v.scal, 8, hipMemcpyDeviceToHost, s));
-  DNGD_HIP(hipStreamSynchronize(s));
-  DNGD_REQUIRE(hinfo == 0, "Nystrom: lam I + M^T M not positive definite");
-  return chol_prepare_solve(s, ell, P.G, ell, P.Gaux);
+  return pcg_factor_G(h, P, lambda, s);
 }
 
 // z = P^{-1} x
@@ -1191,6 +1211,7 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda, const 
   if (!rc) rc = carve_small(h, sm);
   if (!rc) rc = forward(h, theta, nullptr, s);
   if (rc) return rc;
+  h->pc_age = -1;  // K's buffer is rebuilt here
   Precond P;
   rc = pcg_build(h, theta, lambda, landmarks, ell, P, s);
   if (rc) return rc;
@@ -1203,6 +1224,8 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda, const 
     stats->pcg_iterations = its;
     stats->pcg_converged = (st == DNGD_OK);
     stats->pcg_rel_residual = rel;
+    stats->nystrom_shift = P.delta;
+    stats->nystrom_reused = 0;
   }
   return st;
 }
@@ -1219,6 +1242,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
                    o.solver == DNGD_DENSE_AUTO || o.solver == DNGD_STRUCTURED,
                "bad solver");
   DNGD_REQUIRE(o.ir_sweeps >= 0 && o.ir_sweeps <= 8, "ir_sweeps must be in [0, 8]");
+  DNGD_REQUIRE(o.nystrom_chunk_rows >= 0 && o.nystrom_reuse >= 0, "bad Nystrom options");
   DNGD_REQUIRE(o.gram_passes == 0 || o.gram_passes == 1 || o.gram_passes == 3 ||
                    o.gram_passes == 4 || o.gram_passes == DNGD_GRAM_F64,
                "bad gram_passes");
@@ -1243,9 +1267,24 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     if (!rc) rc = check_finite_residual(v, g.m, s);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[1], s));
-    Precond P;
-    rc = pcg_build(h, theta, lambda, o.landmarks, o.n_landmarks, P, s);
+    // the Nystrom factors of an earlier PCG step on this handle are reused for
+    // up to nystrom_reuse further steps (only G is refactored when lambda
+    // changes); otherwise they are rebuilt from this step's landmarks
+    const bool reuse = o.nystrom_reuse > 0 && h->pc_age >= 0 && h->pc_age < o.nystrom_reuse &&
+                       h->pc.ell == o.n_landmarks;
+    if (reuse) {
+      if (h->pc.lambda != lambda) rc = pcg_factor_G(h, h->pc, lambda, s);
+      ++h->pc_age;
+    } else {
+      h->pc_age = -1;
+      rc = pcg_build(h, theta, lambda, o.landmarks, o.n_landmarks, h->pc, s,
+                     o.nystrom_chunk_rows);
+      if (!rc) h->pc_age = 0;
+    }
     if (rc) return rc;
+    const Precond& P = h->pc;
+    st.nystrom_shift = P.delta;
+    st.nystrom_reused = reuse ? 1 : 0;
     DNGD_HIP(hipEventRecord(h->ev[2], s));
     // the dual solution alpha goes to v.fvv (pcg_solve works in s, tmpm, rownorm2, alpha)
     int its = 0;
@@ -1337,6 +1376,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     if (!rc) rc = check_finite_residual(v, g.m, s);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[1], s));
+    h->pc_age = -1;  // K's buffer no longer holds a Nystrom preconditioner
     rc = ensure(h, h->K, (size_t)g.m * g.m * 8);
     if (!rc) rc = ensure(h, h->solve_aux, chol_solve_aux_bytes(g.m));
     if (rc) return rc;
@@ -1497,6 +1537,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
       else passes = 4;
     }
   }
+  h->pc_age = -1;  // K's buffer no longer holds a Nystrom preconditioner
   rc = ensure(h, h->K, (size_t)op.M * op.M * 8);
   if (!rc) rc = ensure(h, h->solve_aux, chol_solve_aux_bytes(op.M));
   if (rc) return rc;

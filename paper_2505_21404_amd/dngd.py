@@ -46,7 +46,9 @@ class StepOpts(C.Structure):
                 ("ir_sweeps", C.c_int32), ("gram_passes", C.c_int32), ("no_lookahead", C.c_int32),
                 ("eps_norm", C.c_double), ("n_landmarks", C.c_int64), ("landmarks", C.c_void_p),
                 ("pcg_tol", C.c_double), ("pcg_maxit", C.c_int64), ("ir_tol", C.c_double),
-                ("alpha_out", C.c_void_p), ("fvv_out", C.c_void_p)]
+                ("alpha_out", C.c_void_p), ("fvv_out", C.c_void_p),
+                ("nystrom_chunk_rows", C.c_int64), ("nystrom_reuse", C.c_int32),
+                ("reserved_opts", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -59,7 +61,8 @@ class StepStats(C.Structure):
                 ("max_row_norm2", C.c_double), ("pcg_rel_residual", C.c_double),
                 ("ms_gram_kernel", C.c_double), ("gram_attempts", C.c_int32),
                 ("pcg_iterations_ga", C.c_int32), ("primal", C.c_int32),
-                ("reserved2", C.c_int32)]
+                ("reserved2", C.c_int32), ("nystrom_shift", C.c_double),
+                ("nystrom_reused", C.c_int32), ("reserved3", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ir_residual"}
@@ -155,7 +158,8 @@ def version() -> str:
 def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0, eps_norm=0.0,
               landmarks: Optional[torch.Tensor] = None, pcg_tol=1e-6, pcg_maxit=500,
               ir_tol: Optional[float] = None, alpha_out: Optional[torch.Tensor] = None,
-              fvv_out: Optional[torch.Tensor] = None) -> StepOpts:
+              fvv_out: Optional[torch.Tensor] = None, nystrom_chunk_rows: int = 0,
+              nystrom_reuse: int = 0) -> StepOpts:
     o = StepOpts()
     _lib.dngd_step_opts_default(C.byref(o))
     o.precision, o.solver, o.ga = precision, solver, int(bool(ga))
@@ -165,6 +169,7 @@ def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0
         o.landmarks = landmarks.data_ptr()
         o._landmarks_ref = landmarks   # the options hold a device pointer into it
     o.pcg_tol, o.pcg_maxit = pcg_tol, pcg_maxit
+    o.nystrom_chunk_rows, o.nystrom_reuse = int(nystrom_chunk_rows), int(nystrom_reuse)
     if ir_tol is not None:
         o.ir_tol = ir_tol
     for name, t in (("alpha_out", alpha_out), ("fvv_out", fvv_out)):

@@ -21,9 +21,10 @@ int main(void) {
   printf("dngd_iter_stats size %zu\n", sizeof(dngd_iter_stats));
   printf("dngd_problem_desc size %zu\n", sizeof(dngd_problem_desc));
   P(dngd_step_opts, eps_norm) P(dngd_step_opts, landmarks) P(dngd_step_opts, ir_tol)
-  P(dngd_step_opts, fvv_out)
+  P(dngd_step_opts, fvv_out) P(dngd_step_opts, nystrom_chunk_rows) P(dngd_step_opts, nystrom_reuse)
   P(dngd_step_stats, ga_accepted) P(dngd_step_stats, ir_residual)
   P(dngd_step_stats, ms_gram_kernel) P(dngd_step_stats, gram_attempts)
+  P(dngd_step_stats, nystrom_shift) P(dngd_step_stats, nystrom_reused)
   P(dngd_iter_stats, eta_index) P(dngd_iter_stats, step)
   P(dngd_problem_desc, kappa) P(dngd_problem_desc, x_int) P(dngd_problem_desc, g_init)
   return 0;

@@ -2,11 +2,14 @@
 m = 8192 with 6144 interior, 1024 boundary, 1024 initial points; FP32 J of
 103 GB materialised), mixed-precision step with GA.
 
-The oracle cannot form this J or K on the host, so the checks are on outputs
-it computes point by point (r and f_vv on sampled residuals, each from its own
-point) and on properties that hold at any size: the dual solution satisfies
-(J J^T + lambda I) alpha = r when the products are taken in FP64 by the
-matrix-free kernel-vector product (Definition 3.6), and v = -J^T alpha."""
+The step is compared with the oracle's step stored in
+tests/golden/config2_step.npz (written by tests/golden/make_golden.py, which
+forms K from column blocks of the FP64 J on the host): dtheta within the mixed
+bar 1e-4, the GA decision, alpha and f_vv. Also checked: r and f_vv on sampled
+residuals, each from its own point, and properties that hold at any size (the
+dual solution satisfies (J J^T + lambda I) alpha = r when the products are
+taken in FP64 by the matrix-free kernel-vector product, Definition 3.6)."""
+import os
 import time
 
 import numpy as np
@@ -17,6 +20,7 @@ from oracle import network as N
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "config2_step.npz")
 
 
 def say(*a):
@@ -87,4 +91,20 @@ def test_config2_full_size_mixed_step():
     say("f_vv rows vs oracle", e_f)
     assert e_f <= 1e-5
     assert np.all(np.isfinite(dth.cpu().numpy()))
+
+    # against the oracle's step (Theorem 3.2 recovery, dense dual solve)
+    g = np.load(GOLD)
+    assert abs(lam - float(g["lam"])) <= 1e-14 * lam
+    assert rel(r_np, g["r"]) <= 1e-12
+    e_dth = rel(dth.cpu().numpy(), g["dtheta32"])
+    e_alpha = rel(alpha.cpu().numpy(), g["alpha"])
+    e_fvv = rel(fvv.cpu().numpy(), g["fvv"])
+    say(f"vs oracle step: dtheta {e_dth:.2e}, alpha {e_alpha:.2e}, f_vv {e_fvv:.2e}, "
+        f"|v| {st.vnorm:.6g} (oracle {float(g['vnorm']):.6g}), |a| {st.anorm:.6g} "
+        f"(oracle {float(g['anorm']):.6g}), accepted {st.ga_accepted} (oracle "
+        f"{int(g['accepted'])})")
+    assert st.ga_accepted == int(g["accepted"])
+    assert e_dth <= 1e-4
+    # f_vv is quadratic in v: its relative error is about twice v's
+    assert e_fvv <= 1e-4
     prob.close()

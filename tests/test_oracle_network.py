@@ -298,3 +298,32 @@ def test_row_subsets_match_full_oracle(kind):
     assert np.array_equal(N.residual_rows(p, th, idx), N.residual(p, th)[idx])
     assert np.allclose(N.jacobian_rows(p, th, idx), N.jacobian(p, th)[idx], rtol=0, atol=1e-14)
     assert np.allclose(N.fvv_rows(p, th, v, idx), N.fvv(p, th, v)[idx], rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind", ["poisson", "heat"])
+def test_jacobian_blocks_and_vjp_match_the_jacobian(kind):
+    """The streamed forms used where J cannot be held (column blocks of J per
+    layer, J^T p from the weighted reverse pass) against J itself (pinned by
+    complex step above), on Poisson and heat nets."""
+    if kind == "poisson":
+        p = W.config(0, scale=dict(widths=[2, 7, 6, 1], n_int=20, n_bdy=9))
+    else:
+        p = W.heat_problem([3, 6, 5, 1], 15, 6, 4, 0.1, 0)
+    th = W.glorot_theta(p.widths, 2)
+    J = N.jacobian(p, th)
+    tapes = N.layer_tapes(p, th)
+    Jb = np.full_like(J, np.nan)
+    off = 0
+    for l in range(len(p.widths) - 1):
+        win, wout = p.widths[l], p.widths[l + 1]
+        for o0 in range(0, wout, 2):
+            o1 = min(wout, o0 + 2)
+            Wc, bc = N.jacobian_block(tapes, l, o0, o1)
+            Jb[:, off + o0 * win: off + o1 * win] = Wc
+            Jb[:, off + wout * win + o0: off + wout * win + o1] = bc
+        off += wout * win + wout
+    assert off == th.size
+    assert np.max(np.abs(Jb - J)) <= 1e-15 * np.max(np.abs(J))
+    pv = W.random_direction(p.m, 3)
+    g = N.vjp(p, th, pv)
+    assert np.linalg.norm(g - J.T @ pv) <= 1e-13 * np.linalg.norm(J.T @ pv)

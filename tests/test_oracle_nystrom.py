@@ -86,3 +86,29 @@ def test_pcg_maxit_and_breakdown_flags():
     # indefinite operator -> <p, Ap> <= 0 stops the iteration
     y, its, ok, _ = NY.pcg(lambda v: -v, b, lambda v: v, 1e-10, 10)
     assert not ok and its == 0
+
+
+def test_nystrom_is_exact_when_landmarks_span_the_range():
+    """If K has rank r and K_II has the same rank, the Nystrom approximation
+    reproduces K exactly (its columns span K's range), and P^{-1} = (K + lam I)^{-1}."""
+    rng = np.random.default_rng(3)
+    m, r = 90, 12
+    B = rng.standard_normal((m, r))
+    K = B @ B.T
+    I = np.sort(rng.choice(m, 20, replace=False))
+    Khat, rank = NY.nystrom_approx(K[:, I], I)
+    assert rank == r
+    assert np.abs(Khat - K).max() <= 1e-10 * np.abs(K).max()
+    U, lh = NY.nystrom(K[:, I], I)
+    assert U.shape == (m, r) and np.all(lh > 0)
+    lam = 1e-2
+    x = rng.standard_normal(m)
+    z = NY.precond_apply(U, lh, lam, x)
+    assert np.linalg.norm((K + lam * np.eye(m)) @ z - x) <= 1e-9 * np.linalg.norm(x)
+    # with fewer landmarks than the rank, K_II is nonsingular and the shifted
+    # form tends to the pseudo-inverse form as the shift vanishes
+    I2 = I[:10]
+    K0, rank2 = NY.nystrom_approx(K[:, I2], I2)
+    Kd, _ = NY.nystrom_approx(K[:, I2], I2, delta=1e-10 * np.abs(K).max())
+    assert rank2 == 10
+    assert np.abs(Kd - K0).max() <= 1e-7 * np.abs(K).max()
