@@ -49,10 +49,17 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling: 3 device copies of 1 GiB (calibrates the HBM byte counters)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream run")
-    ap.add_argument("--serving-jobs", type=int, default=64)
-    ap.add_argument("--serving-steps", type=int, default=10,
+    ap.add_argument("--serving-jobs", type=int, default=8,
+                    help="jobs of the serving stream (its first N; the stream has 64)")
+    ap.add_argument("--serving-steps", type=int, default=200,
                     help="iterations per serving job (the stream's jobs ask for 200)")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-budget-gb", type=float, default=0.0,
+                    help="serving memory budget in GB (default: 80%% of free device memory)")
+    ap.add_argument("--serving-lookahead", action="store_true",
+                    help="serving jobs factor with the look-ahead (default off)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="instead: only the serving stream, one JSON line")
     ap.add_argument("--pcg", action="store_true",
                     help="instead: one Nystrom-PCG step on the 5-D Poisson MLP 5-2048x4-1, m=50000")
     ap.add_argument("--pcg-landmarks", type=int, default=2000)
@@ -143,15 +150,25 @@ def cpu_baseline(seed_theta, lam):
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gram_bf16_kernel_poisson5d_m5000.traffic.txt")
 
 
-def serving_run(n_jobs, steps, slots, torch):
+def serving_run(n_jobs, steps, slots, torch, budget_gb=0.0, lookahead=False):
     """The serving stream (Poisson arrivals at 4 jobs/s, uneven m and widths)
     with ``steps`` iterations per job, admitted by footprint into 80% of the
-    free device memory."""
+    free device memory (or ``budget_gb`` GB)."""
     import workloads as W
     from paper_2505_21404_amd import serving as SV
     specs = SV.specs_from_workloads(W.serving_jobs(n_jobs=n_jobs, rate=4.0, steps=steps))
     free, _ = torch.cuda.mem_get_info()
-    srv = SV.Server(budget_bytes=int(0.8 * free), max_slots=slots)
+    budget = int(budget_gb * 2 ** 30) if budget_gb > 0 else int(0.8 * free)
+    fp, rj = SV.gpu_executor(lookahead=lookahead)
+    t0 = time.perf_counter()
+
+    def run_job(spec, res):  # the executor, plus a progress line per finished job
+        rj(spec, res)
+        progress(f"serving job {spec.job_id} done at {time.perf_counter() - t0:.1f} s "
+                 f"(m {spec.problem.m}, {len(res.step_ms)} steps, median "
+                 f"{statistics.median(res.step_ms):.1f} ms)")
+
+    srv = SV.Server(budget_bytes=budget, max_slots=slots, run_job=run_job, footprint=fp)
     rep = srv.run(specs, realtime=True)
     out = {k: v for k, v in rep.items() if k not in ("results", "errors")}
     out["errors"] = len(rep["errors"])
@@ -159,6 +176,7 @@ def serving_run(n_jobs, steps, slots, torch):
     out["steps_per_job"] = steps
     out["slots"] = slots
     out["budget_bytes"] = srv.budget
+    out["lookahead"] = lookahead
     return out
 
 
@@ -345,6 +363,16 @@ def main():
     if a.structured >= 0:
         print(json.dumps(structured_run(a.structured, torch)), flush=True)
         return 0
+    if a.serving_only:
+        rep = serving_run(a.serving_jobs, a.serving_steps, a.serving_slots, torch,
+                          a.serving_budget_gb, a.serving_lookahead)
+        print(json.dumps({"metric": "serving stream: steps/s, p50/p99 step ms",
+                          "value": rep["steps_per_s"], "unit": "steps/s", "n_gpus": 1,
+                          "higher_is_better": True, "data": "synthetic",
+                          "config": {"workload": "serving_stream_poisson_heat",
+                                     "jobs": a.serving_jobs, "steps_per_job": a.serving_steps,
+                                     "slots": a.serving_slots}, "serving": rep}), flush=True)
+        return 0
     import workloads as W
     from paper_2505_21404_amd import dngd as D
 
@@ -448,7 +476,8 @@ def main():
 
     if not a.no_serving:
         progress("serving stream ...")
-        out["serving"] = serving_run(a.serving_jobs, a.serving_steps, a.serving_slots, torch)
+        out["serving"] = serving_run(a.serving_jobs, a.serving_steps, a.serving_slots, torch,
+                                     a.serving_budget_gb, a.serving_lookahead)
         progress("serving done")
 
     if not a.no_cpu:

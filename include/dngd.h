@@ -14,7 +14,9 @@
  *     default stream. Work is enqueued on it; unless a call is documented
  *     as synchronising, it returns before the work finishes.
  *   - The caller owns every buffer it passes in. A dngd_problem owns the
- *     workspace it allocates and frees it in dngd_problem_destroy. Stateless
+ *     workspace it allocates (from the stream-ordered allocator, on the
+ *     stream of the call that first needs it) and frees it in
+ *     dngd_problem_destroy. Stateless
  *     calls (dngd_gram, dngd_cholesky_solve) take their scratch from the
  *     stream-ordered allocator of the stream's device and release it before
  *     returning; dngd_cholesky_solve_noalloc uses a static device array.
@@ -186,6 +188,9 @@ void dngd_step_opts_default(dngd_step_opts* opts);
  * complete when the call returns (the caller may free its arrays); work the
  * caller enqueued to produce them must be finished before the call. */
 int dngd_problem_create(const dngd_problem_desc* desc, dngd_problem** out);
+/* Waits for the handle's own work (the stream of its last call and its
+ * internal stream), not for the whole device, then releases its memory.
+ * Work the caller enqueued with the handle on other streams must be finished. */
 int dngd_problem_destroy(dngd_problem* h);
 
 int64_t dngd_num_params(const dngd_problem* h);     /* n */

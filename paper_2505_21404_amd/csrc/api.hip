@@ -82,6 +82,13 @@ struct dngd_problem {
   // steps; -1 when K's buffer holds something else
   Precond pc;
   int pc_age = -1;
+  // Device memory comes from the stream-ordered allocator on the stream of
+  // the call in progress (astream), so that growing a buffer mid-job or
+  // destroying a handle never waits for the whole device (other jobs'
+  // queued work); last_use is recorded on each call's stream.
+  hipStream_t astream = nullptr;
+  hipEvent_t last_use = nullptr;
+  bool last_use_valid = false;
 };
 
 namespace {
@@ -91,10 +98,10 @@ size_t wt_bytes(const Geometry& g) { return (size_t)g.max_width * g.max_width * 
 
 int dmalloc(dngd_problem* h, void** p, size_t bytes) {
   if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(p, bytes);
+  hipError_t e = hipMallocAsync(p, bytes, h->astream);
   if (e != hipSuccess) {
     *p = nullptr;
-    return hip_fail(e, "hipMalloc", __FILE__, __LINE__);
+    return hip_fail(e, "hipMallocAsync", __FILE__, __LINE__);
   }
   h->owned.push_back(*p);
   return 0;
@@ -105,7 +112,7 @@ int ensure(dngd_problem* h, DevBuf& b, size_t bytes) {
   if (b.p) {
     for (auto& q : h->owned)
       if (q == b.p) q = nullptr;
-    DNGD_HIP(hipFree(b.p));
+    DNGD_HIP(hipFreeAsync(b.p, h->astream));  // after the work already queued on the stream
     b.p = nullptr;
     b.bytes = 0;
   }
@@ -116,6 +123,18 @@ int ensure(dngd_problem* h, DevBuf& b, size_t bytes) {
 }
 
 hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+// Every entry point that takes a handle and a stream opens one: allocations
+// of the call go to that stream, and the stream's last use of the handle is
+// recorded for dngd_problem_destroy.
+struct CallScope {
+  dngd_problem* h;
+  hipStream_t s;
+  CallScope(dngd_problem* h_, hipStream_t s_) : h(h_), s(s_) { h->astream = s; }
+  ~CallScope() {
+    if (h->last_use && hipEventRecord(h->last_use, s) == hipSuccess) h->last_use_valid = true;
+  }
+};
 
 const double* Wp(const dngd_problem* h, const double* th, int l) { return th + h->g.w_off[l]; }
 const double* Bp(const dngd_problem* h, const double* th, int l) { return th + h->g.b_off[l]; }
@@ -690,6 +709,15 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
 
   int rc = 0;
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+    h->side = nullptr;
+    rc = DNGD_EHIP;
+  }
+  if (!rc && hipEventCreateWithFlags(&h->last_use, hipEventDisableTiming) != hipSuccess) {
+    h->last_use = nullptr;
+    rc = DNGD_EHIP;
+  }
+  h->astream = h->side;  // creation's allocations and copies run on the side stream
   // A device-to-device hipMemcpy does not wait for the copy before it
   // returns, and the caller may free or reuse the source arrays as soon as
   // this call returns: enqueue the copies, then wait for them.
@@ -698,7 +726,7 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
     rc = dmalloc(h, (void**)dst, (size_t)std::max<int64_t>(cnt, 1) * sizeof(double));
     if (!rc && cnt > 0) {
       hipError_t e = hipMemcpyAsync(*dst, src, (size_t)cnt * sizeof(double), hipMemcpyDefault,
-                                    nullptr);
+                                    h->side);
       if (e != hipSuccess) rc = hip_fail(e, "hipMemcpyAsync", __FILE__, __LINE__);
     }
   };
@@ -709,7 +737,7 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
   dup(&h->g_bdy, d->g_bdy, g.n_bdy * g.r_bdy);
   dup(&h->g_init, d->g_init, g.n_init);
   if (!rc) {
-    hipError_t e = hipStreamSynchronize(nullptr);
+    hipError_t e = hipStreamSynchronize(h->side);
     if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
   }
   if (!rc) rc = dmalloc(h, (void**)&h->A0, (size_t)g.R * g.d_in * sizeof(double));
@@ -728,9 +756,9 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
     if (hipEventCreate(&h->ev[e]) != hipSuccess) rc = DNGD_EHIP;
   for (int e = 0; e < 2 && !rc; ++e)
     if (hipEventCreateWithFlags(&h->cev[e], hipEventDisableTiming) != hipSuccess) rc = DNGD_EHIP;
-  if (!rc && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
-    h->side = nullptr;
-    rc = DNGD_EHIP;
+  if (!rc) {  // the activation buffers are allocated once creation returns
+    hipError_t e = hipStreamSynchronize(h->side);
+    if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
   }
   if (rc) {
     dngd_problem_destroy(h);
@@ -742,9 +770,14 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
 
 int dngd_problem_destroy(dngd_problem* h) {
   if (!h) return DNGD_OK;
-  hipDeviceSynchronize();
+  // wait for this handle's own work only (its last call's stream and the
+  // side stream), then return its memory to the stream-ordered pool
+  if (h->last_use_valid) hipEventSynchronize(h->last_use);
+  if (h->side) hipStreamSynchronize(h->side);
   for (void* p : h->owned)
-    if (p) hipFree(p);
+    if (p) hipFreeAsync(p, h->side);
+  if (h->side) hipStreamSynchronize(h->side);
+  if (h->last_use) hipEventDestroy(h->last_use);
   for (auto& e : h->ev)
     if (e) hipEventDestroy(e);
   for (auto& e : h->cev)
@@ -784,6 +817,7 @@ int dngd_residual_jacobian(dngd_problem* h, const double* theta, double* r, void
     DNGD_REQUIRE(ldJ >= h->g.n && ldJ % 4 == 0, "ldJ must be >= n and a multiple of 4");
   }
   hipStream_t s = S(stream);
+  CallScope scope(h, s);
   int rc = forward(h, theta, r, s);
   if (rc) return rc;
   if (!J) return DNGD_OK;
@@ -842,6 +876,7 @@ int dngd_cholesky_solve_noalloc(int64_t m, double* K, int64_t ldK, int32_t facto
 int dngd_fvv(dngd_problem* h, const double* theta, const double* v, double* fvv, void* stream) {
   DNGD_REQUIRE(h && theta && v && fvv, "dngd_fvv: null argument");
   hipStream_t s = S(stream);
+  CallScope scope(h, s);
   int rc = forward(h, theta, nullptr, s);
   if (rc) return rc;
   return tangent(h, theta, v, 2, fvv, s);
@@ -850,6 +885,7 @@ int dngd_fvv(dngd_problem* h, const double* theta, const double* v, double* fvv,
 int dngd_jvp(dngd_problem* h, const double* theta, const double* u, double* w, void* stream) {
   DNGD_REQUIRE(h && theta && u && w, "dngd_jvp: null argument");
   hipStream_t s = S(stream);
+  CallScope scope(h, s);
   int rc = forward(h, theta, nullptr, s);
   if (rc) return rc;
   return tangent(h, theta, u, 1, w, s);
@@ -858,6 +894,7 @@ int dngd_jvp(dngd_problem* h, const double* theta, const double* u, double* w, v
 int dngd_vjp(dngd_problem* h, const double* theta, const double* p, double* gout, void* stream) {
   DNGD_REQUIRE(h && theta && p && gout, "dngd_vjp: null argument");
   hipStream_t s = S(stream);
+  CallScope scope(h, s);
   int rc = forward(h, theta, nullptr, s);
   if (rc) return rc;
   return vjp(h, theta, p, gout, s);
@@ -867,6 +904,7 @@ int dngd_losses(dngd_problem* h, const double* theta, const double* dtheta, int3
                 const double* etas, double* losses, void* stream) {
   DNGD_REQUIRE(h && theta && dtheta && etas && losses && n_eta > 0 && n_eta <= 48,
                "dngd_losses: bad argument");
+  CallScope scope(h, S(stream));
   return losses_impl(h, theta, dtheta, n_eta, etas, losses, S(stream));
 }
 
@@ -1205,6 +1243,7 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda, const 
   DNGD_REQUIRE(lambda > 0.0 && std::isfinite(lambda), "dngd_nystrom_pcg: lambda must be > 0");
   DNGD_REQUIRE(tol >= 0.0 && maxit >= 0, "dngd_nystrom_pcg: bad tol/maxit");
   hipStream_t s = S(stream);
+  CallScope scope(h, s);
   StepVecs v;
   Small sm;
   int rc = carve_vecs(h, v);
@@ -1252,6 +1291,7 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
                "vector-valued residuals: dense solvers only (DNGD_DENSE, DNGD_PRIMAL, "
                "DNGD_DENSE_AUTO)");
   hipStream_t s = S(stream);
+  CallScope scope(h, s);
   StepVecs v;
   Small sm;
   int rc = carve_vecs(h, v);
@@ -1701,6 +1741,7 @@ int dngd_iterate(dngd_problem* h, double* theta, double lambda_cap, double lambd
     DNGD_REQUIRE(std::isfinite(etas[k]), "dngd_iterate: non-finite step length");
   const Geometry& g = h->g;
   hipStream_t s = S(stream);
+  CallScope scope(h, s);
   int rc = ensure(h, h->iter, (size_t)g.n * sizeof(double));
   if (rc) return rc;
   double* dth = static_cast<double*>(h->iter.p);

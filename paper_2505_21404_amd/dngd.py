@@ -159,7 +159,7 @@ def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0
               landmarks: Optional[torch.Tensor] = None, pcg_tol=1e-6, pcg_maxit=500,
               ir_tol: Optional[float] = None, alpha_out: Optional[torch.Tensor] = None,
               fvv_out: Optional[torch.Tensor] = None, nystrom_chunk_rows: int = 0,
-              nystrom_reuse: int = 0) -> StepOpts:
+              nystrom_reuse: int = 0, no_lookahead: bool = False) -> StepOpts:
     o = StepOpts()
     _lib.dngd_step_opts_default(C.byref(o))
     o.precision, o.solver, o.ga = precision, solver, int(bool(ga))
@@ -170,6 +170,7 @@ def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0
         o._landmarks_ref = landmarks   # the options hold a device pointer into it
     o.pcg_tol, o.pcg_maxit = pcg_tol, pcg_maxit
     o.nystrom_chunk_rows, o.nystrom_reuse = int(nystrom_chunk_rows), int(nystrom_reuse)
+    o.no_lookahead = int(bool(no_lookahead))
     if ir_tol is not None:
         o.ir_tol = ir_tol
     for name, t in (("alpha_out", alpha_out), ("fvv_out", fvv_out)):

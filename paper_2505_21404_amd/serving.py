@@ -161,6 +161,9 @@ def report(results: Dict[int, JobResult], makespan: float, server: Server) -> Di
     waits = [r.admitted - r.arrival for r in served]
     first = [r.step_ms[0] for r in served if r.step_ms]
     steady = [x for r in served for x in r.step_ms[1:]]
+    # each step against its own job's median: the tail that interference adds,
+    # apart from the spread of job sizes
+    norm = [x / statistics.median(r.step_ms) for r in served if r.step_ms for x in r.step_ms]
     steps = len(lat)
     return {
         "jobs": len(results),
@@ -174,6 +177,7 @@ def report(results: Dict[int, JobResult], makespan: float, server: Server) -> Di
         "first_step_p50_ms": percentile(first, 0.50),
         "steady_p50_step_ms": percentile(steady, 0.50),
         "steady_p99_step_ms": percentile(steady, 0.99),
+        "p99_over_job_median": percentile(norm, 0.99),
         "mean_step_ms": statistics.fmean(lat) if lat else float("nan"),
         "admission_wait_p50_s": percentile(waits, 0.50),
         "admission_wait_max_s": max(waits) if waits else float("nan"),
@@ -190,15 +194,21 @@ def specs_from_workloads(jobs, lam_cap_poisson: float = 1e-5, lam_cap_heat: floa
                     lam_cap_heat if j.problem.pde == 1 else lam_cap_poisson) for j in jobs]
 
 
-def gpu_executor(device: str = "cuda", opts_fn: Optional[Callable] = None):
+def gpu_executor(device: str = "cuda", opts_fn: Optional[Callable] = None,
+                 lookahead: bool = False):
     """(footprint, run_job) backed by libdngd: each job gets its own handle,
-    its own torch stream and the mixed-precision dense step with GA."""
+    its own torch stream and the mixed-precision dense step with GA. The
+    factorisation's look-ahead (a trailing update that reserves whole CUs
+    beside the panels) is meant for a device with one job; with several
+    resident jobs it is off unless ``lookahead``."""
     import torch
 
     from . import dngd as D
 
     def make_opts(spec):
-        return opts_fn(spec) if opts_fn else D.step_opts(precision=D.MIXED, ga=True)
+        if opts_fn:
+            return opts_fn(spec)
+        return D.step_opts(precision=D.MIXED, ga=True, no_lookahead=not lookahead)
 
     def footprint(spec: JobSpec) -> int:
         p = spec.problem
@@ -227,9 +237,10 @@ def gpu_executor(device: str = "cuda", opts_fn: Optional[Callable] = None):
     return footprint, run_job
 
 
-def run_alone(spec: JobSpec, device: str = "cuda", opts_fn: Optional[Callable] = None):
+def run_alone(spec: JobSpec, device: str = "cuda", opts_fn: Optional[Callable] = None,
+              lookahead: bool = False):
     """The same job on an idle device (reference for the mix)."""
-    _, run_job = gpu_executor(device, opts_fn)
+    _, run_job = gpu_executor(device, opts_fn, lookahead)
     res = JobResult(spec.job_id, spec.arrival, 0.0, 0.0, 0)
     run_job(spec, res)
     return res
