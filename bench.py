@@ -69,6 +69,14 @@ def parse():
                     help="with --pcg: also run this many optimiser iterations (PCG steps + line search)")
     ap.add_argument("--pcg-ga", action="store_true",
                     help="with --pcg: geodesic acceleration (second PCG solve for f_vv)")
+    ap.add_argument("--pcg-reuse", type=int, default=0,
+                    help="with --pcg-iters: reuse the Nystrom factors for up to R further steps")
+    ap.add_argument("--config0", action="store_true",
+                    help="instead: the plain FP64 dense step with GA on the 2-D Poisson workload "
+                         "(MLP 2-32-32-1, m = 500, lambda = 1e-8)")
+    ap.add_argument("--kovasznay", action="store_true",
+                    help="instead: the dense step on the Kovasznay flow (vector-valued residuals, "
+                         "[2,50x4,3], 400 + 400 points, m = 2400): mixed and plain, GA")
     ap.add_argument("--landmark-study", type=str, default="", metavar="L1,L2,...",
                     help="instead: --pcg runs with --pcg-iters optimiser iterations (default 6) "
                          "for each landmark count; PCG iterations per step over training")
@@ -258,6 +266,34 @@ def regime_map(torch, ms=(300, 1300, 3300, 6300), ks=(0, 1, 2, 4), steps=3):
             "auto_picks_faster": f"{agree}/{len(rows)}"}
 
 
+def kovasznay_run(torch, steps=20, warmup=3):
+    """Dense D-NGD step with GA on the Kovasznay flow (steady Navier-Stokes,
+    vector-valued residual classes): [2, 50 x 4, 3] tanh MLP, 400 interior and
+    400 boundary points (m = 2400, n = 7953), lambda = min(L, 1e-5)."""
+    import workloads as W
+    from paper_2505_21404_amd import dngd as D
+    p = W.kovasznay()
+    th = torch.tensor(W.glorot_theta(p.widths, 0), device="cuda")
+    prob = D.Problem.from_workload(p)
+    r = prob.residual(th)
+    lam = min(0.5 * float((r * r).sum()), 1e-5)
+    out = {"metric": "dense D-NGD step, Kovasznay flow (vector-valued residuals)",
+           "unit": "steps/s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": p.name, "m": prob.m, "n": prob.n, "lambda": lam}}
+    for name, o in (("mixed", D.step_opts(precision=D.MIXED, ga=True)),
+                    ("plain", D.step_opts(precision=D.PLAIN, ga=True)),
+                    ("primal_plain", D.step_opts(precision=D.PLAIN, solver=D.PRIMAL, ga=True))):
+        tot, walls, stats, _ = timed_steps(prob, th, lam, o, steps, warmup, torch)
+        out[name] = {"steps_per_s": steps / tot, "p50_step_ms": statistics.median(walls),
+                     "gram_passes": stats[-1]["gram_passes_used"],
+                     "phase_ms_median": {k: statistics.median(x[k] for x in stats) for k in (
+                         "ms_residual_jacobian", "ms_gram", "ms_factor", "ms_solve_v", "ms_fvv",
+                         "ms_solve_a")}}
+        progress(f"kovasznay {name}: {out[name]['p50_step_ms']:.2f} ms/step")
+    prob.close()
+    return out
+
+
 def pcg_run(a, torch):
     """One matrix-free Nystrom-PCG step (GA with --pcg-ga) on the large 5-D Poisson
     workload: n = 12.6M parameters, m = 50,000 residuals (45,000 interior,
@@ -311,7 +347,7 @@ def pcg_run(a, torch):
         for k in range(a.pcg_iters):
             Ik = torch.tensor(W.landmarks(p.m, a.pcg_landmarks, 0, step=k), device="cuda")
             ok = D.step_opts(solver=D.PCG, ga=a.pcg_ga, landmarks=Ik, pcg_tol=a.pcg_tol,
-                             pcg_maxit=a.pcg_maxit)
+                             pcg_maxit=a.pcg_maxit, nystrom_reuse=a.pcg_reuse)
             t0 = time.perf_counter()
             it = prob.iterate(th, etas, lam_cap=W.LAMBDA_CAP[3], opts=ok)
             hist.append({"loss": it.loss, "lam": it.lam, "eta": it.eta,
@@ -319,6 +355,8 @@ def pcg_run(a, torch):
                          "pcg_iterations_ga": it.step.pcg_iterations_ga,
                          "ga_accepted": it.step.ga_accepted,
                          "pcg_rel_residual": it.step.pcg_rel_residual,
+                         "nystrom_reused": it.step.nystrom_reused,
+                         "s_nystrom_build": it.step.ms_factor / 1e3,
                          "s_step": it.step.ms_total / 1e3, "s_line_search": it.ms_line_search / 1e3,
                          "s_iteration": time.perf_counter() - t0})
             progress(f"PCG iteration {k}: loss {it.loss:.4g} pcg its {it.step.pcg_iterations}")
@@ -356,6 +394,34 @@ def main():
         return 0
     if a.pcg:
         print(json.dumps(pcg_run(a, torch)), flush=True)
+        return 0
+    if a.kovasznay:
+        print(json.dumps(kovasznay_run(torch)), flush=True)
+        return 0
+    if a.config0:
+        import workloads as W
+        from paper_2505_21404_amd import dngd as D
+        p = W.config(0)
+        th = torch.tensor(W.glorot_theta(p.widths, 0), device="cuda")
+        prob = D.Problem.from_workload(p)
+        o = D.step_opts(precision=D.PLAIN, ga=True)
+        tot, walls, stats, _ = timed_steps(prob, th, W.LAMBDA[0], o, a.steps, a.warmup, torch)
+        etas = [2.0 ** -k for k in range(31)]
+        ls = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            prob.iterate(th.clone(), etas, fixed_lambda=W.LAMBDA[0], opts=o)
+            ls.append((time.perf_counter() - t0) * 1e3)
+        print(json.dumps({"metric": "D-NGD plain FP64 steps/s, 2-D Poisson", "unit": "steps/s",
+                          "value": a.steps / tot, "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": W.CONFIG_NAMES[0], "m": prob.m, "n": prob.n,
+                                     "lambda": W.LAMBDA[0]},
+                          "p50_step_ms": statistics.median(walls), "p99_step_ms": p99(walls),
+                          "optimizer_iteration_ms": statistics.median(ls),
+                          "phase_ms_median": {k: statistics.median(x[k] for x in stats) for k in (
+                              "ms_residual_jacobian", "ms_gram", "ms_factor", "ms_solve_v",
+                              "ms_fvv", "ms_solve_a")}}), flush=True)
+        prob.close()
         return 0
     if a.regime_map:
         print(json.dumps(regime_map(torch)), flush=True)
