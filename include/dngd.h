@@ -172,7 +172,11 @@ typedef struct {
   int32_t gram_attempts;      /* Gram + factorisation attempts (> 1 after an escalation) */
   int32_t pcg_iterations_ga;  /* PCG with GA: iterations of the second (f_vv) solve */
   int32_t primal;             /* 1 if the step solved the primal n x n system */
-  int32_t reserved2;
+  int32_t ga_early_reject;    /* mixed dense dual step with GA: 1 if the correction was
+                                 rejected for certain after the first refinement sweep of its
+                                 solve (||a0|| - ||s0|| / (2 sqrt(lambda)) already fails the
+                                 test; dtheta = v) and its remaining sweeps were skipped;
+                                 anorm is then ||a0|| */
   double nystrom_shift;       /* PCG: delta added to K_II before its factorisation */
   int32_t nystrom_reused;     /* PCG: 1 if the step reused earlier Nystrom factors */
   int32_t reserved3;

@@ -441,6 +441,23 @@ struct DenseOp {
 // x = (K + lam I)^{-1} rhs with the factor in h->K, then ir_sweeps sweeps of
 // refinement against the exact operator: s = rhs - (A (A^T x) + lam x), computed
 // with FP32/FP64 A and FP64 accumulation; ||s||^2 of sweep k -> ir_out[k].
+// One refinement sweep's residual: tN = A^T x, sM = rhs - (A tN + lam x).
+int refine_residual(const DenseOp& op, const StepVecs& v, const double* rhs, const double* x,
+                    double lambda, hipStream_t s) {
+  int rc = gemv_t(s, op.M, op.N, op.A, op.ldA, op.jd, x, 1.0, op.tN, v.gemv_work);
+  if (rc) return rc;
+  return gemv_n_residual(s, op.M, op.N, op.A, op.ldA, op.jd, op.tN, rhs, x, lambda, op.sM);
+}
+
+// x += (K + lam I)^{-1} sM (the correction of a sweep, with the factor in h->K)
+int refine_correct(dngd_problem* h, const DenseOp& op, double* x, hipStream_t s) {
+  double* K = static_cast<double*>(h->K.p);
+  const double* aux = static_cast<const double*>(h->solve_aux.p);
+  int rc = chol_solve(s, op.M, K, h->ldK, aux, op.sM);
+  if (rc) return rc;
+  return axpy(s, op.M, 1.0, op.sM, x);
+}
+
 int dense_solve(dngd_problem* h, const DenseOp& op, const StepVecs& v, const double* rhs,
                 double* x, double lambda, int ir_sweeps, double* ir_out, hipStream_t s) {
   double* K = static_cast<double*>(h->K.p);
@@ -450,17 +467,13 @@ int dense_solve(dngd_problem* h, const DenseOp& op, const StepVecs& v, const dou
   rc = chol_solve(s, op.M, K, h->ldK, aux, x);
   if (rc) return rc;
   for (int k = 0; k < ir_sweeps; ++k) {
-    rc = gemv_t(s, op.M, op.N, op.A, op.ldA, op.jd, x, 1.0, op.tN, v.gemv_work);
-    if (rc) return rc;
-    rc = gemv_n_residual(s, op.M, op.N, op.A, op.ldA, op.jd, op.tN, rhs, x, lambda, op.sM);
+    rc = refine_residual(op, v, rhs, x, lambda, s);
     if (rc) return rc;
     if (ir_out && k < 8) {
       rc = sumsq(s, op.M, op.sM, ir_out + k, v.red);
       if (rc) return rc;
     }
-    rc = chol_solve(s, op.M, K, h->ldK, aux, op.sM);
-    if (rc) return rc;
-    rc = axpy(s, op.M, 1.0, op.sM, x);
+    rc = refine_correct(h, op, x, s);
     if (rc) return rc;
   }
   return 0;
@@ -1655,18 +1668,59 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     if (!rc && o.fvv_out) rc = copy(s, g.m, v.fvv, o.fvv_out);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[5], s));
+    bool combined = false;  // dtheta and the GA flag already written
     if (primal) {
       rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.fvv, 1.0, v.t, v.gemv_work);
       if (!rc) rc = dense_solve(h, op, v, v.t, v.px, lambda, ir, nullptr, s);
       if (!rc) rc = fill(s, g.n, 0.0, v.a);
       if (!rc) rc = axpy(s, g.n, -1.0, v.px, v.a);
+    } else if (ir > 0) {
+      combined = true;
+      const double* aux = static_cast<const double*>(h->solve_aux.p);
+      // beta in stages. With beta0 the unrefined solve, t = J^T beta0 (so
+      // a0 = -t) and s0 = f_vv - (J t + lam beta0) -- the first refinement
+      // sweep's residual -- the refined a satisfies
+      //   ||a - a0|| = ||J^T (K + lam I)^{-1} s0|| <= ||s0|| / (2 sqrt(lam))
+      // (max over singular values of sigma / (sigma^2 + lam)). When even
+      // ||a0|| minus that bound fails the acceptance test, the correction is
+      // rejected for certain: the rest of its refinement is skipped and
+      // dtheta = v, as the full computation would give.
+      rc = copy(s, g.m, v.fvv, v.beta);
+      if (!rc) rc = chol_solve(s, g.m, K, g.m, aux, v.beta);
+      if (!rc) rc = refine_residual(op, v, v.fvv, v.beta, lambda, s);
+      if (!rc) rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
+      if (!rc) rc = sumsq(s, g.n, op.tN, v.scal + 1, v.red);
+      if (!rc) rc = sumsq(s, g.m, op.sM, v.scal + 2, v.red);
+      if (rc) return rc;
+      double nr[3];
+      DNGD_HIP(hipMemcpyAsync(nr, v.scal, sizeof(nr), hipMemcpyDeviceToHost, s));
+      DNGD_HIP(hipStreamSynchronize(s));
+      const double nv = std::sqrt(nr[0]);
+      const double a_low = std::sqrt(nr[1]) - std::sqrt(nr[2]) / (2.0 * std::sqrt(lambda));
+      if (nv > o.eps_norm && 2.0 * a_low > 0.5 * nv) {
+        st.ga_early_reject = 1;  // scal[1] holds ||a0||^2: the combine rejects, dtheta = v
+        rc = ga_combine(s, g.n, v.v, v.a, v.scal, o.eps_norm, dtheta, sm.ga_flag);
+        if (rc) return rc;
+      } else {
+        rc = refine_correct(h, op, v.beta, s);
+        for (int k = 1; k < ir && !rc; ++k) {
+          rc = refine_residual(op, v, v.fvv, v.beta, lambda, s);
+          if (!rc) rc = refine_correct(h, op, v.beta, s);
+        }
+        if (!rc) rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.beta, -1.0, v.a, v.gemv_work);
+        if (!rc) rc = sumsq(s, g.n, v.a, v.scal + 1, v.red);
+        if (!rc) rc = ga_combine(s, g.n, v.v, v.a, v.scal, o.eps_norm, dtheta, sm.ga_flag);
+        if (rc) return rc;
+      }
     } else {
       rc = dense_solve(h, op, v, v.fvv, v.beta, lambda, ir, nullptr, s);
       if (!rc) rc = gemv_t(s, g.m, g.n, J, ldJ, jd, v.beta, -1.0, v.a, v.gemv_work);
     }
-    if (!rc) rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
-    if (!rc) rc = sumsq(s, g.n, v.a, v.scal + 1, v.red);
-    if (!rc) rc = ga_combine(s, g.n, v.v, v.a, v.scal, o.eps_norm, dtheta, sm.ga_flag);
+    if (!combined) {
+      if (!rc) rc = sumsq(s, g.n, v.v, v.scal + 0, v.red);
+      if (!rc) rc = sumsq(s, g.n, v.a, v.scal + 1, v.red);
+      if (!rc) rc = ga_combine(s, g.n, v.v, v.a, v.scal, o.eps_norm, dtheta, sm.ga_flag);
+    }
     if (rc) return rc;
   } else {
     DNGD_HIP(hipEventRecord(h->ev[5], s));

@@ -61,7 +61,7 @@ class StepStats(C.Structure):
                 ("max_row_norm2", C.c_double), ("pcg_rel_residual", C.c_double),
                 ("ms_gram_kernel", C.c_double), ("gram_attempts", C.c_int32),
                 ("pcg_iterations_ga", C.c_int32), ("primal", C.c_int32),
-                ("reserved2", C.c_int32), ("nystrom_shift", C.c_double),
+                ("ga_early_reject", C.c_int32), ("nystrom_shift", C.c_double),
                 ("nystrom_reused", C.c_int32), ("reserved3", C.c_int32)]
 
     def as_dict(self):

@@ -104,6 +104,7 @@ def test_config2_full_size_mixed_step():
         f"(oracle {float(g['anorm']):.6g}), accepted {st.ga_accepted} (oracle "
         f"{int(g['accepted'])})")
     assert st.ga_accepted == int(g["accepted"])
+    assert st.ga_early_reject == 0  # accepted: the f_vv solve was refined in full
     assert e_dth <= 1e-4
     # f_vv is quadratic in v: its relative error is about twice v's
     assert e_fvv <= 1e-4

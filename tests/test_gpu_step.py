@@ -79,6 +79,23 @@ def test_config1_mixed_step(c1):
     assert e <= 1e-4
 
 
+def test_config1_mixed_ga_rejected_early(c1):
+    """At the Glorot start the correction fails the acceptance test by a wide
+    margin: after the first refinement sweep of the f_vv solve the rejection is
+    certain (||a0|| - ||s0|| / (2 sqrt(lambda)) already fails), the remaining
+    sweeps are skipped, and the step is bitwise the step without GA."""
+    d, p, th, prob, g = c1
+    lam = float(g["lam"])
+    a, st = prob.step(th, lam, d.step_opts(precision=d.MIXED, ga=True))
+    b, st0 = prob.step(th, lam, d.step_opts(precision=d.MIXED, ga=False))
+    say("early reject", st.ga_early_reject, "|a0|", st.anorm, "|v|", st.vnorm,
+        "oracle |a|", float(np.linalg.norm(g["a"])))
+    assert st.ga_early_reject == 1 and st.ga_accepted == 0 == int(g["accepted"])
+    assert torch.equal(a, b)
+    # the estimate is the oracle's |a| to about the refinement residual
+    assert abs(st.anorm - np.linalg.norm(g["a"])) <= 1e-2 * np.linalg.norm(g["a"])
+
+
 def test_config1_mixed_is_deterministic(c1):
     d, p, th, prob, g = c1
     lam = float(g["lam"])
