@@ -69,6 +69,11 @@ def parse():
                     help="with --pcg: also run this many optimiser iterations (PCG steps + line search)")
     ap.add_argument("--pcg-ga", action="store_true",
                     help="with --pcg: geodesic acceleration (second PCG solve for f_vv)")
+    ap.add_argument("--pcg-kvp", choices=["f64", "bf16"], default="f64",
+                    help="with --pcg: kernel-vector products in FP64 or with bf16 GEMM operands "
+                         "(FP32 accumulation, FP64 true residuals)")
+    ap.add_argument("--kvp", type=int, default=-1, metavar="CFG",
+                    help="instead: time the kernel-vector product (FP64 and bf16) on workload CFG")
     ap.add_argument("--pcg-reuse", type=int, default=0,
                     help="with --pcg-iters: reuse the Nystrom factors for up to R further steps")
     ap.add_argument("--config0", action="store_true",
@@ -309,8 +314,9 @@ def pcg_run(a, torch):
     lam = min(L0, W.LAMBDA_CAP[3])
     I = torch.tensor(W.landmarks(p.m, a.pcg_landmarks, 0), device="cuda")
     alpha = torch.empty(prob.m, dtype=torch.float64, device="cuda")
+    kvp_dtype = D.BF16 if a.pcg_kvp == "bf16" else D.F64
     opts = D.step_opts(solver=D.PCG, ga=a.pcg_ga, landmarks=I, pcg_tol=a.pcg_tol,
-                       pcg_maxit=a.pcg_maxit, alpha_out=alpha)
+                       pcg_maxit=a.pcg_maxit, alpha_out=alpha, pcg_kvp=kvp_dtype)
     progress(f"PCG step: n={prob.n} m={prob.m} landmarks={a.pcg_landmarks}")
     t0 = time.perf_counter()
     dth, st = prob.step(th, lam, opts)
@@ -329,7 +335,9 @@ def pcg_run(a, torch):
         "config": {"workload": "poisson5d_mlp5-2048x4-1_m50000_pcg" + ("_ga" if a.pcg_ga else ""),
                    "n": prob.n, "m": prob.m,
                    "landmarks": a.pcg_landmarks, "tol": a.pcg_tol, "maxit": a.pcg_maxit,
-                   "lambda": lam},
+                   "lambda": lam, "kvp": a.pcg_kvp},
+        "pcg_kvp_f64": st.pcg_kvp_f64, "pcg_replacements": st.pcg_replacements,
+        "pcg_escalated": st.pcg_escalated,
         "pcg_iterations": st.pcg_iterations, "pcg_converged": bool(st.pcg_converged),
         "pcg_rel_residual": st.pcg_rel_residual, "true_rel_residual": true_res,
         "ms_forward": st.ms_residual_jacobian, "ms_nystrom_build": st.ms_factor,
@@ -347,7 +355,8 @@ def pcg_run(a, torch):
         for k in range(a.pcg_iters):
             Ik = torch.tensor(W.landmarks(p.m, a.pcg_landmarks, 0, step=k), device="cuda")
             ok = D.step_opts(solver=D.PCG, ga=a.pcg_ga, landmarks=Ik, pcg_tol=a.pcg_tol,
-                             pcg_maxit=a.pcg_maxit, nystrom_reuse=a.pcg_reuse)
+                             pcg_maxit=a.pcg_maxit, nystrom_reuse=a.pcg_reuse,
+                             pcg_kvp=kvp_dtype)
             t0 = time.perf_counter()
             it = prob.iterate(th, etas, lam_cap=W.LAMBDA_CAP[3], opts=ok)
             hist.append({"loss": it.loss, "lam": it.lam, "eta": it.eta,
@@ -355,6 +364,8 @@ def pcg_run(a, torch):
                          "pcg_iterations_ga": it.step.pcg_iterations_ga,
                          "ga_accepted": it.step.ga_accepted,
                          "pcg_rel_residual": it.step.pcg_rel_residual,
+                         "pcg_kvp_f64": it.step.pcg_kvp_f64,
+                         "pcg_escalated": it.step.pcg_escalated,
                          "nystrom_reused": it.step.nystrom_reused,
                          "s_nystrom_build": it.step.ms_factor / 1e3,
                          "s_step": it.step.ms_total / 1e3, "s_line_search": it.ms_line_search / 1e3,
@@ -363,6 +374,47 @@ def pcg_run(a, torch):
         out["iterations"] = hist
     prob.close()
     return out
+
+
+def kvp_run(cfg, a, torch):
+    """The kernel-vector product w = J (J^T p) + lam p (Definition 3.6) on
+    workload cfg, FP64 and bf16 products: wall ms per dngd_kvp call (forward
+    pass included; bf16 also includes the per-step bf16/FP32 copies) and the
+    forward pass alone, medians over --steps calls after --warmup."""
+    import numpy as np
+    import workloads as W
+    from paper_2505_21404_amd import dngd as D
+    p = W.config(cfg)
+    th = torch.tensor(W.glorot_theta(p.widths, 0), device="cuda")
+    prob = D.Problem.from_workload(p)
+    pv = torch.tensor(W.random_direction(p.m, 1), device="cuda")
+    lam = W.LAMBDA_CAP[cfg]
+
+    def timed(fn):
+        ts = []
+        for k in range(a.warmup + a.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            if k >= a.warmup:
+                ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts)), out
+
+    progress(f"kvp: workload {cfg}, n={prob.n} m={prob.m}")
+    t_fwd, r = timed(lambda: prob.residual(th))
+    t64, w64 = timed(lambda: prob.kvp(th, lam, pv, D.F64))
+    progress("kvp: FP64 products timed")
+    t16, w16 = timed(lambda: prob.kvp(th, lam, pv, D.BF16))
+    progress("kvp: bf16 products timed")
+    err = float(((w16 - w64).norm() / w64.norm()).item())
+    prob.close()
+    return {"metric": "kernel-vector product ms (dngd_kvp, forward pass included)",
+            "unit": "ms", "value": t16, "higher_is_better": False, "n_gpus": 1,
+            "config": {"workload": p.name, "n": int(prob.n), "m": int(prob.m), "lambda": lam},
+            "ms_forward_only": t_fwd, "ms_kvp_f64": t64, "ms_kvp_bf16": t16,
+            "ms_product_f64": t64 - t_fwd, "ms_product_bf16_incl_copies": t16 - t_fwd,
+            "bf16_vs_f64_rel_err": err}
 
 
 def main():
@@ -392,6 +444,9 @@ def main():
                                      "tol": a.pcg_tol, "iterations": a.pcg_iters},
                           "rows": rows}), flush=True)
         return 0
+    if a.kvp >= 0:
+        print(json.dumps(kvp_run(a.kvp, a, torch)), flush=True)
+        return
     if a.pcg:
         print(json.dumps(pcg_run(a, torch)), flush=True)
         return 0

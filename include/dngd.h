@@ -50,7 +50,7 @@ typedef enum {
   DNGD_ENAN = -5      /* a non-finite value in the result */
 } dngd_status;
 
-typedef enum { DNGD_F64 = 0, DNGD_F32 = 1 } dngd_dtype;
+typedef enum { DNGD_F64 = 0, DNGD_F32 = 1, DNGD_BF16 = 2 } dngd_dtype;
 typedef enum { DNGD_POISSON = 0, DNGD_HEAT = 1, DNGD_NAVIER_STOKES = 2 } dngd_pde;
 typedef enum { DNGD_PLAIN = 0, DNGD_MIXED = 1 } dngd_precision;
 /* Solvers of the step's linear systems.
@@ -152,7 +152,16 @@ typedef struct {
                                   to R further steps (landmarks are then ignored; only the
                                   l x l system is refactored when lambda changes) -- the
                                   preconditioner is built once and reused (Section 4) */
-  int32_t reserved_opts;
+  int32_t pcg_kvp;             /* PCG kernel-vector products: DNGD_F64 (default) or
+                                  DNGD_BF16 (bf16 GEMM operands, FP32 accumulation; see
+                                  dngd_kvp). With DNGD_BF16 convergence is still decided
+                                  on the FP64 true residual ||b - A y|| <= tol ||b||:
+                                  each time the recursive residual reaches tol (or has
+                                  fallen 2^10-fold since the last replacement) the true
+                                  residual is formed with the FP64 product and replaces
+                                  it; once a replacement finds the true residual reduced
+                                  less than 8-fold, the remaining iterations use FP64
+                                  products. Scalar residual classes, L >= 2. */
 } dngd_step_opts;
 
 /* gram_passes / dngd_gram passes value: FP64-product Gram of an FP32 J */
@@ -179,7 +188,11 @@ typedef struct {
                                  anorm is then ||a0|| */
   double nystrom_shift;       /* PCG: delta added to K_II before its factorisation */
   int32_t nystrom_reused;     /* PCG: 1 if the step reused earlier Nystrom factors */
-  int32_t reserved3;
+  int32_t pcg_kvp_f64;        /* PCG: FP64 kernel-vector products (iterations and true
+                                 residuals; both solves with GA) */
+  int32_t pcg_replacements;   /* PCG with bf16 products: recursive residuals replaced by
+                                 FP64 true residuals (both solves) */
+  int32_t pcg_escalated;      /* PCG with bf16 products: 1 if a solve switched to FP64 products */
 } dngd_step_stats;
 
 const char* dngd_last_error(void);
@@ -269,6 +282,17 @@ int dngd_fvv(dngd_problem* h, const double* theta, const double* v, double* fvv,
  * u, g: device n FP64; w, p: device m FP64. Neither J nor K is formed. */
 int dngd_jvp(dngd_problem* h, const double* theta, const double* u, double* w, void* stream);
 int dngd_vjp(dngd_problem* h, const double* theta, const double* p, double* g, void* stream);
+
+/* Kernel-vector product (Definition 3.6): w = J (J^T p) + lambda p,
+ * matrix-free (a reverse pass, then a forward tangent pass), J at theta.
+ * dtype DNGD_F64: FP64 products. DNGD_BF16: every per-layer product takes
+ * bf16 operands with FP32 accumulation on the matrix cores and the tanh jet
+ * rules run in FP32 (error of order 2^-8 ||J||^2 ||p||); scalar residual
+ * classes and networks with at least one hidden layer only (else
+ * DNGD_EINVAL). Activations are kept from the forward pass, not recomputed.
+ * theta: device n FP64; p, w: device m FP64, w must not alias p. */
+int dngd_kvp(dngd_problem* h, const double* theta, double lambda, const double* p, double* w,
+             int32_t dtype, void* stream);
 
 /* Line-search losses (D-NGD workflow): losses[k] = 0.5 ||r(theta + eta_k dtheta)||^2.
  * etas, losses: host arrays of n_eta. Synchronises `stream`. */

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdngd.so")
-SOURCES = ["api.hip", "net.hip", "gemm_f64.hip", "gram.hip", "chol.hip", "blas1.hip"]
+SOURCES = ["api.hip", "net.hip", "gemm_f64.hip", "gram.hip", "chol.hip", "blas1.hip",
+           "gemm_bf16.hip", "lowp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DNGD_OFFLOAD_ARCH", "gfx950")

@@ -72,6 +72,7 @@ struct dngd_problem {
   double *Z1 = nullptr, *Z2 = nullptr, *A1[2] = {nullptr, nullptr}, *A2[2] = {nullptr, nullptr};
   // step / solver workspace (lazy, grown on demand)
   DevBuf J, Jt, K, vecs, work, gram_work, solve_aux, small, iter;
+  DevBuf lp;  // buffers of the bf16 kernel-vector product (LowpBufs carves them)
   int J_dtype = -1;
   int64_t ldJ = 0, ldK = 0;
   hipEvent_t ev[10] = {nullptr};
@@ -343,6 +344,146 @@ int vjp(dngd_problem* h, const double* theta, const double* p, double* gout, hip
 }
 
 // ---------------------------------------------------------------------------
+// bf16 kernel-vector product (Definition 3.6 with bf16 GEMM operands and FP32
+// accumulation). Per step (theta fixed), after forward(): FP32 copies of the
+// hidden pre-activation jets (the jet rules run in FP32), bf16 copies of
+// every layer's input activations, row-major (tangent products) and
+// transposed with a value-row marker (weight and bias gradients), and bf16
+// copies of the hidden weights and their transposes. Per product: the
+// adjoint and tangent streams in FP32 (GEMM outputs) and bf16 (GEMM inputs).
+// Row lengths of bf16 matrices are rounded up to 32 with zero padding; the
+// transposed matrices have Rp = R rounded up to 32 columns.
+
+int64_t ldw(int w) { return round_up(w, 32); }
+
+struct LowpBufs {
+  int64_t Rp = 0;
+  float* Zf[kMaxLayers] = {nullptr};      // l = 0..L-2: R x w_{l+1}
+  uint16_t* Hb[kMaxLayers] = {nullptr};   // l = 0..L-1: R x ldw(w_l)
+  uint16_t* HbT[kMaxLayers] = {nullptr};  // l = 0..L-1: (w_l + 1) x Rp
+  uint16_t* Wb[kMaxLayers] = {nullptr};   // l = 1..L-2: w_{l+1} x ldw(w_l)
+  uint16_t* WTb[kMaxLayers] = {nullptr};  // l = 1..L-2: w_l x ldw(w_{l+1})
+  uint16_t* Vb[kMaxLayers] = {nullptr};   // l = 0..L-2: direction blocks, w_{l+1} x ldw(w_l)
+  uint16_t* seedT = nullptr;              // Rp
+  uint16_t* Zb = nullptr;                 // R x ldw(max width)
+  uint16_t* ZbT = nullptr;                // max width x Rp
+  float* F = nullptr;                     // R x max width (adjoints, then tangents)
+  uint16_t* A1 = nullptr;                 // R x ldw(max width)
+  float* part = nullptr;                  // split-K partials of the weight gradients
+  size_t part_bytes = 0;
+};
+
+// Carves the buffers from base (null: only sizes them); returns the bytes.
+size_t lp_layout(const Geometry& g, LowpBufs& b, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* q = base ? base + off : nullptr;
+    off += round_up((int64_t)bytes, 256);
+    return q;
+  };
+  const int64_t R = g.R;
+  b.Rp = round_up(R, 32);
+  const int64_t wp = ldw(g.max_width);
+  for (int l = 0; l < g.L; ++l) {
+    const int win = g.widths[l], wout = g.widths[l + 1];
+    if (l < g.L - 1) b.Zf[l] = reinterpret_cast<float*>(take((size_t)R * wout * 4));
+    b.Hb[l] = reinterpret_cast<uint16_t*>(take((size_t)R * ldw(win) * 2));
+    b.HbT[l] = reinterpret_cast<uint16_t*>(take((size_t)(win + 1) * b.Rp * 2));
+    if (l >= 1 && l < g.L - 1) {
+      b.Wb[l] = reinterpret_cast<uint16_t*>(take((size_t)wout * ldw(win) * 2));
+      b.WTb[l] = reinterpret_cast<uint16_t*>(take((size_t)win * ldw(wout) * 2));
+    }
+    if (l < g.L - 1) b.Vb[l] = reinterpret_cast<uint16_t*>(take((size_t)wout * ldw(win) * 2));
+  }
+  b.seedT = reinterpret_cast<uint16_t*>(take((size_t)b.Rp * 2));
+  b.Zb = reinterpret_cast<uint16_t*>(take((size_t)R * wp * 2));
+  b.ZbT = reinterpret_cast<uint16_t*>(take((size_t)g.max_width * b.Rp * 2));
+  b.F = reinterpret_cast<float*>(take((size_t)R * g.max_width * 4));
+  b.A1 = reinterpret_cast<uint16_t*>(take((size_t)R * wp * 2));
+  size_t pb = 0;
+  for (int l = 0; l < g.L; ++l)
+    pb = std::max(pb, gemm_bf16_split_work_bytes(g.widths[l + 1], g.widths[l] + 1, b.Rp));
+  b.part_bytes = pb;
+  b.part = reinterpret_cast<float*>(take(pb));
+  return off;
+}
+
+// The per-step copies (requires forward() at theta; scalar residual classes,
+// L >= 2).
+int lp_prepare(dngd_problem* h, const double* theta, LowpBufs& b, hipStream_t s) {
+  const Geometry& g = h->g;
+  DNGD_REQUIRE(g.L >= 2 && g.d_out == 1,
+               "bf16 products: networks with a hidden layer and one output only");
+  LowpBufs probe;
+  int rc = ensure(h, h->lp, lp_layout(g, probe, nullptr));
+  if (rc) return rc;
+  lp_layout(g, b, static_cast<char*>(h->lp.p));
+  for (int l = 0; l < g.L; ++l) {
+    const int win = g.widths[l], wout = g.widths[l + 1];
+    if (l < g.L - 1) rc = lp_to_f32(s, g.R * wout, h->Z[l], b.Zf[l]);
+    if (!rc) rc = lp_to_bf16_pad(s, g.R, win, act_in(h, l), win, b.Hb[l], ldw(win));
+    if (!rc) rc = lp_transpose(s, h->rm, g.R, win, act_in(h, l), 0, win, b.HbT[l], b.Rp, b.Rp, 1);
+    if (!rc && l >= 1 && l < g.L - 1) {
+      rc = lp_to_bf16_pad(s, wout, win, Wp(h, theta, l), win, b.Wb[l], ldw(win));
+      if (!rc)
+        rc = lp_transpose(s, h->rm, wout, win, Wp(h, theta, l), 0, win, b.WTb[l], ldw(wout),
+                          ldw(wout), 0);
+    }
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+// w = J (J^T p) + lambda p with bf16 GEMMs (FP32 accumulation); t: n FP64
+// scratch (receives J^T p). Requires lp_prepare() at theta.
+int kvp_lp(dngd_problem* h, const double* theta, double lambda, const LowpBufs& b,
+           const double* p, double* t, double* w, hipStream_t s) {
+  const Geometry& g = h->g;
+  const int L = g.L;
+  // reverse pass: t = J^T p
+  int rc = net_seeds(s, h->rm, h->U, Bp(h, theta, L - 1), p, 0, h->seed);
+  if (!rc) rc = lp_seed_row(s, g.R, b.Rp, h->seed, b.seedT);
+  if (rc) return rc;
+  for (int hl = L - 2; hl >= 0; --hl) {
+    const int w_ = g.widths[hl + 1], win = g.widths[hl];
+    const int64_t ldz = ldw(w_);
+    rc = lp_act_adjoint(s, h->rm, w_, ldz, b.Zf[hl], hl == L - 2 ? nullptr : b.F, h->seed,
+                        Wp(h, theta, L - 1), b.Zb);
+    if (!rc) rc = lp_transpose(s, h->rm, g.R, w_, b.Zb, 1, ldz, b.ZbT, b.Rp, b.Rp, 0);
+    // W-bar_hl = Zb^T H_hl, with the bias gradient as the marker column
+    if (!rc)
+      rc = gemm_bf16_nt_split(s, w_, win + 1, b.ZbT, b.Rp, b.HbT[hl], b.Rp, b.Rp,
+                              t + g.w_off[hl], win, win, t + g.b_off[hl], b.part, b.part_bytes);
+    // A-bar of the layer below = Zb W_hl
+    if (!rc && hl > 0)
+      rc = gemm_bf16_nt(s, g.R, win, b.Zb, ldz, b.WTb[hl], ldz, ldz, nullptr, 0, nullptr, 0, 0,
+                        b.F, win);
+    if (rc) return rc;
+  }
+  const int wl = g.widths[L - 1];
+  rc = gemm_bf16_nt_split(s, 1, wl + 1, b.seedT, b.Rp, b.HbT[L - 1], b.Rp, b.Rp, t + g.w_off[L - 1],
+                          wl, wl, t + g.b_off[L - 1], b.part, b.part_bytes);
+  if (rc) return rc;
+  // forward tangent along t: w = J t
+  for (int l = 0; l < L - 1; ++l) {
+    const int win = g.widths[l], wout = g.widths[l + 1];
+    rc = lp_to_bf16_pad(s, wout, win, t + g.w_off[l], win, b.Vb[l], ldw(win));
+    if (!rc)
+      rc = (l == 0) ? gemm_bf16_nt(s, g.R, wout, b.Hb[0], ldw(win), b.Vb[0], ldw(win), ldw(win),
+                                   nullptr, 0, nullptr, 0, 0, b.F, wout)
+                    : gemm_bf16_nt(s, g.R, wout, b.Hb[l], ldw(win), b.Vb[l], ldw(win), ldw(win),
+                                   b.A1, ldw(win), b.Wb[l], ldw(win), ldw(win), b.F, wout);
+    if (!rc) rc = lp_tangent_act(s, h->rm, wout, ldw(wout), t + g.b_off[l], b.Zf[l], b.F, b.A1);
+    if (rc) return rc;
+  }
+  rc = lp_rowdot(s, g.R, wl, ldw(wl), b.A1, Wp(h, theta, L - 1), b.Hb[L - 1], t + g.w_off[L - 1],
+                 h->U);
+  if (!rc) rc = net_linear_residual(s, h->rm, h->U, t + g.b_off[L - 1], w);
+  if (!rc && lambda != 0.0) rc = axpy(s, g.m, lambda, p, w);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
 // step workspace: vectors of m and n doubles plus reduction scratch
 
 struct StepVecs {
@@ -605,6 +746,10 @@ size_t footprint_bytes(const Geometry& g, const dngd_step_opts* o) {
     b += (size_t)ell * ldM * 8 + (size_t)ell * ell * 8 + 2 * (size_t)ell * 8 +
          chol_solve_aux_bytes(ell);
     b += gram_workspace_bytes(ell, g.m, DNGD_F64, 1, nullptr);
+    if (o->pcg_kvp == DNGD_BF16) {
+      LowpBufs lb;
+      b += lp_layout(g, lb, nullptr);
+    }
   }
   return b;
 }
@@ -1179,40 +1324,70 @@ int read_scalars(double* host, const double* dev, int n, hipStream_t s) {
   return 0;
 }
 
+struct PcgResult {
+  int iters = 0;          // kernel-vector products of the iteration (either precision)
+  double relres = 1.0;    // final ||r|| / ||b||: the true residual when one was formed last
+  int kvp_f64 = 0;        // FP64 products (true residuals and FP64 iterations)
+  int replacements = 0;   // recursive residuals replaced by true ones
+  int escalated = 0;      // 1: the bf16 products stopped reducing the true residual
+};
+
 // PCG (appendix algorithm) on (J J^T + lam I) y = b from y = 0.
 // Work vectors: y -> x (output); r = v.s; z = v.tmpm; p = v.rownorm2; Ap = v.alpha;
-// the kernel-vector product uses v.t. b is read only before the first iteration.
+// the kernel-vector product uses v.t. b is read by every true residual.
+//
+// With lp (bf16 products), the recursion runs on the bf16 operator, whose
+// error (~2^-8 of ||K|| per product) the recursive residual does not see.
+// So whenever the recursive residual reaches tol (or has fallen 2^10-fold
+// since the last replacement), the true residual b - A y is formed with the
+// FP64 product; if it meets tol the solve has converged, else it replaces the
+// recursive one and the recursion restarts from y (residual replacement).
+// When a replacement shows that the true residual fell less than 8-fold
+// since the previous one, the bf16 error (about 2^-8 ||K|| per product)
+// dominates at this damping (lambda small against 2^-8 ||K||: the components
+// of the residual along K's small eigenvalues are not reduced) and the
+// remaining iterations use the FP64 product, which at such a rate of
+// contraction needs fewer FP64 products than further replacements would.
 int pcg_solve(dngd_problem* h, const double* theta, const Precond& P, const StepVecs& v,
               const Small& sm, const double* b, double* x, double tol, int64_t maxit,
-              int* iters, double* relres, hipStream_t s) {
+              PcgResult* res, hipStream_t s, const LowpBufs* lp = nullptr) {
   const Geometry& g = h->g;
   double* r = v.s;
   double* z = v.tmpm;
   double* p = v.rownorm2;
   double* Ap = v.alpha;
   double* tlv = P.tl;
+  *res = PcgResult();
   int rc = fill(s, g.m, 0.0, x);
   if (!rc) rc = copy(s, g.m, b, r);
-  if (!rc) rc = precond_apply(h, P, v, sm, r, z, tlv, s);
-  if (!rc) rc = copy(s, g.m, z, p);
-  if (!rc) rc = dot(s, g.m, r, z, v.scal + 0, v.red);
   if (!rc) rc = sumsq(s, g.m, b, v.scal + 1, v.red);
   if (rc) return rc;
-  double hs[2];
-  rc = read_scalars(hs, v.scal, 2, s);
+  double nb2;
+  rc = read_scalars(&nb2, v.scal + 1, 1, s);
   if (rc) return rc;
-  double rho = hs[0];
-  const double nb = std::sqrt(hs[1]);
-  *iters = 0;
-  *relres = 1.0;
+  const double nb = std::sqrt(nb2);
   if (nb == 0.0) {
-    *relres = 0.0;
+    res->relres = 0.0;
     return DNGD_OK;
   }
+  bool f64 = (lp == nullptr);
+  double last_true = nb;  // norm of the last true (or initial) residual
+  double rho = 0.0;
+  auto restart = [&]() -> int {
+    int e = precond_apply(h, P, v, sm, r, z, tlv, s);
+    if (!e) e = copy(s, g.m, z, p);
+    if (!e) e = dot(s, g.m, r, z, v.scal + 0, v.red);
+    if (!e) e = read_scalars(&rho, v.scal + 0, 1, s);
+    return e;
+  };
+  rc = restart();
+  if (rc) return rc;
   for (int64_t j = 0; j < maxit; ++j) {
-    rc = kvp(h, theta, P.lambda, v, p, Ap, s);
+    rc = f64 ? kvp(h, theta, P.lambda, v, p, Ap, s)
+             : kvp_lp(h, theta, P.lambda, *lp, p, v.t, Ap, s);
     if (!rc) rc = dot(s, g.m, p, Ap, v.scal + 2, v.red);
     if (rc) return rc;
+    if (f64) ++res->kvp_f64;
     double pAp;
     rc = read_scalars(&pAp, v.scal + 2, 1, s);
     if (rc) return rc;
@@ -1225,9 +1400,32 @@ int pcg_solve(dngd_problem* h, const double* theta, const Precond& P, const Step
     double rr;
     rc = read_scalars(&rr, v.scal + 3, 1, s);
     if (rc) return rc;
-    *iters = (int)(j + 1);
-    *relres = std::sqrt(rr) / nb;
-    if (std::sqrt(rr) <= tol * nb) return DNGD_OK;
+    res->iters = (int)(j + 1);
+    const double rn = std::sqrt(rr);
+    res->relres = rn / nb;
+    if (!f64 && (rn <= tol * nb || rn <= last_true * 0x1p-10)) {
+      // true residual with the FP64 product: r = b - A x
+      rc = kvp(h, theta, P.lambda, v, x, Ap, s);
+      if (!rc) rc = copy(s, g.m, b, r);
+      if (!rc) rc = axpy(s, g.m, -1.0, Ap, r);
+      if (!rc) rc = sumsq(s, g.m, r, v.scal + 3, v.red);
+      if (!rc) rc = read_scalars(&rr, v.scal + 3, 1, s);
+      if (rc) return rc;
+      ++res->kvp_f64;
+      const double tn = std::sqrt(rr);
+      res->relres = tn / nb;
+      if (tn <= tol * nb) return DNGD_OK;
+      if (!(tn < 0.125 * last_true)) {
+        f64 = true;
+        res->escalated = 1;
+      }
+      last_true = tn;
+      ++res->replacements;
+      rc = restart();
+      if (rc) return rc;
+      continue;
+    }
+    if (rn <= tol * nb) return DNGD_OK;
     rc = precond_apply(h, P, v, sm, r, z, tlv, s);
     if (!rc) rc = dot(s, g.m, r, z, v.scal + 4, v.red);
     if (rc) return rc;
@@ -1267,19 +1465,40 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda, const 
   Precond P;
   rc = pcg_build(h, theta, lambda, landmarks, ell, P, s);
   if (rc) return rc;
-  int its = 0;
-  double rel = 1.0;
-  const int st = pcg_solve(h, theta, P, v, sm, b, x, tol, maxit, &its, &rel, s);
+  PcgResult pr;
+  const int st = pcg_solve(h, theta, P, v, sm, b, x, tol, maxit, &pr, s);
   if (st < 0) return st;
   DNGD_HIP(hipStreamSynchronize(s));
   if (stats) {
-    stats->pcg_iterations = its;
+    stats->pcg_iterations = pr.iters;
     stats->pcg_converged = (st == DNGD_OK);
-    stats->pcg_rel_residual = rel;
+    stats->pcg_rel_residual = pr.relres;
     stats->nystrom_shift = P.delta;
     stats->nystrom_reused = 0;
+    stats->pcg_kvp_f64 = pr.kvp_f64;
   }
   return st;
+}
+
+int dngd_kvp(dngd_problem* h, const double* theta, double lambda, const double* p, double* w,
+             int32_t dtype, void* stream) {
+  DNGD_REQUIRE(h && theta && p && w, "dngd_kvp: null argument");
+  DNGD_REQUIRE(p != w, "dngd_kvp: w must not alias p");
+  DNGD_REQUIRE(dtype == DNGD_F64 || dtype == DNGD_BF16, "dngd_kvp: dtype DNGD_F64 or DNGD_BF16");
+  DNGD_REQUIRE(std::isfinite(lambda), "dngd_kvp: lambda must be finite");
+  DNGD_REQUIRE(h->g.pde != DNGD_NAVIER_STOKES || dtype == DNGD_F64,
+               "dngd_kvp: bf16 products for scalar residual classes only");
+  hipStream_t s = S(stream);
+  CallScope scope(h, s);
+  StepVecs v;
+  int rc = carve_vecs(h, v);
+  if (!rc) rc = forward(h, theta, nullptr, s);
+  if (rc) return rc;
+  if (dtype == DNGD_F64) return kvp(h, theta, lambda, v, p, w, s);
+  LowpBufs b;
+  rc = lp_prepare(h, theta, b, s);
+  if (rc) return rc;
+  return kvp_lp(h, theta, lambda, b, p, v.t, w, s);
 }
 
 int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_step_opts* opts,
@@ -1295,6 +1514,8 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
                "bad solver");
   DNGD_REQUIRE(o.ir_sweeps >= 0 && o.ir_sweeps <= 8, "ir_sweeps must be in [0, 8]");
   DNGD_REQUIRE(o.nystrom_chunk_rows >= 0 && o.nystrom_reuse >= 0, "bad Nystrom options");
+  DNGD_REQUIRE(o.pcg_kvp == DNGD_F64 || o.pcg_kvp == DNGD_BF16,
+               "pcg_kvp must be DNGD_F64 or DNGD_BF16");
   DNGD_REQUIRE(o.gram_passes == 0 || o.gram_passes == 1 || o.gram_passes == 3 ||
                    o.gram_passes == 4 || o.gram_passes == DNGD_GRAM_F64,
                "bad gram_passes");
@@ -1339,11 +1560,18 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     st.nystrom_shift = P.delta;
     st.nystrom_reused = reuse ? 1 : 0;
     DNGD_HIP(hipEventRecord(h->ev[2], s));
+    // bf16 products: the per-step copies of the activations and weights
+    LowpBufs lpb;
+    const LowpBufs* lp = nullptr;
+    if (o.pcg_kvp == DNGD_BF16) {
+      rc = lp_prepare(h, theta, lpb, s);
+      if (rc) return rc;
+      lp = &lpb;
+    }
     // the dual solution alpha goes to v.fvv (pcg_solve works in s, tmpm, rownorm2, alpha)
-    int its = 0;
-    double rel = 1.0;
+    PcgResult pr, pr_ga;
     const int pst =
-        pcg_solve(h, theta, P, v, sm, v.r, v.fvv, o.pcg_tol, o.pcg_maxit, &its, &rel, s);
+        pcg_solve(h, theta, P, v, sm, v.r, v.fvv, o.pcg_tol, o.pcg_maxit, &pr, s, lp);
     if (pst < 0) return pst;
     if (o.alpha_out) {
       rc = copy(s, g.m, v.fvv, o.alpha_out);
@@ -1358,15 +1586,14 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     DNGD_HIP(hipEventRecord(h->ev[3], s));
     // GA (Section 3.2, with the same preconditioner, Remark 3.5): f_vv along v,
     // beta from a second PCG solve, a = -J^T beta, combined as in the dense path
-    int its_ga = 0, pst_ga = DNGD_OK;
-    double rel_ga = 0.0;
+    int pst_ga = DNGD_OK;
     if (o.ga) {
       rc = tangent(h, theta, v.v, 2, v.fvv, s);
       if (!rc && o.fvv_out) rc = copy(s, g.m, v.fvv, o.fvv_out);
       if (rc) return rc;
       DNGD_HIP(hipEventRecord(h->ev[5], s));
-      pst_ga = pcg_solve(h, theta, P, v, sm, v.fvv, v.beta, o.pcg_tol, o.pcg_maxit, &its_ga,
-                         &rel_ga, s);
+      pst_ga = pcg_solve(h, theta, P, v, sm, v.fvv, v.beta, o.pcg_tol, o.pcg_maxit, &pr_ga, s,
+                         lp);
       if (pst_ga < 0 && pst_ga != DNGD_ENOCONV) return pst_ga;
       if (pst_ga == DNGD_OK) {
         rc = vjp(h, theta, v.beta, v.t, s);
@@ -1411,10 +1638,13 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     st.vnorm = std::sqrt(nv[0]);
     st.anorm = std::sqrt(nv[1]);
     st.ga_accepted = (o.ga && pst_ga == DNGD_OK) ? gaf : 0;
-    st.pcg_iterations = its;
-    st.pcg_iterations_ga = its_ga;
+    st.pcg_iterations = pr.iters;
+    st.pcg_iterations_ga = pr_ga.iters;
     st.pcg_converged = (pst == DNGD_OK);
-    st.pcg_rel_residual = rel;
+    st.pcg_rel_residual = pr.relres;
+    st.pcg_kvp_f64 = pr.kvp_f64 + pr_ga.kvp_f64;
+    st.pcg_replacements = pr.replacements + pr_ga.replacements;
+    st.pcg_escalated = (pr.escalated || pr_ga.escalated) ? 1 : 0;
     if (stats) *stats = st;
     if (pst == DNGD_OK && (!std::isfinite(st.vnorm) || !std::isfinite(st.anorm))) {
       set_error("non-finite step");

@@ -254,4 +254,35 @@ int net_nystrom_combine(hipStream_t s, const RowMap& rm, int64_t p0, int64_t np,
 int net_colsum_value_rows(hipStream_t s, const RowMap& rm, int w, const double* Zbar, double* out,
                           double* work);
 
+
+// ---------------------------------------------------------------------------
+// bf16 GEMMs with FP32 accumulation (gemm_bf16.hip). Operands bf16 (raw
+// uint16 storage), row-major, K-contiguous: C = A0 B0^T + A1 B1^T (segment 1
+// optional, K1 = 0), K0, K1 multiples of 32, leading dimensions multiples of
+// 8, 16-byte aligned bases.
+int gemm_bf16_nt(hipStream_t s, int64_t M, int64_t N, const uint16_t* A0, int64_t lda0,
+                 const uint16_t* B0, int64_t ldb0, int64_t K0, const uint16_t* A1, int64_t lda1,
+                 const uint16_t* B1, int64_t ldb1, int64_t K1, float* C, int64_t ldc);
+// Split-K variant (long K): FP64 sums of the split partials into C (ldc);
+// column bias_col (if >= 0) goes to bias[row] instead.
+int gemm_bf16_nt_split(hipStream_t s, int64_t M, int64_t N, const uint16_t* A, int64_t lda,
+                       const uint16_t* B, int64_t ldb, int64_t K, double* C, int64_t ldc,
+                       int64_t bias_col, double* bias, float* work, size_t work_bytes);
+size_t gemm_bf16_split_work_bytes(int64_t M, int64_t N, int64_t K);
+
+// low-precision product helpers (lowp.hip)
+int lp_to_f32(hipStream_t s, int64_t n, const double* x, float* y);
+int lp_to_bf16_pad(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds,
+                   uint16_t* dst, int64_t ldd);
+int lp_transpose(hipStream_t s, const RowMap& rm, int64_t rows, int64_t cols, const void* src,
+                 int src_bf16, int64_t lds, uint16_t* dst, int64_t ldd, int64_t rpad,
+                 int indicator);
+int lp_seed_row(hipStream_t s, int64_t R, int64_t rpad, const double* seed, uint16_t* out);
+int lp_act_adjoint(hipStream_t s, const RowMap& rm, int w, int64_t ldz, const float* Zf,
+                   const float* Ab, const double* seed, const double* wL, uint16_t* Zb);
+int lp_tangent_act(hipStream_t s, const RowMap& rm, int w, int64_t lda, const double* b1,
+                   const float* Zf, const float* Z1, uint16_t* A1);
+int lp_rowdot(hipStream_t s, int64_t R, int w, int64_t ld, const uint16_t* X, const double* wx,
+              const uint16_t* Y, const double* wy, double* out);
+
 }  // namespace dngd

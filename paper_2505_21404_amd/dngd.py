@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdngd.so")
 
 OK, ENOCONV, EINVAL, ENOMEM, EHIP, ENOTPD, ENAN = 0, 1, -1, -2, -3, -4, -5
-F64, F32 = 0, 1
+F64, F32, BF16 = 0, 1, 2
 GRAM_F64 = 64   # gram_passes value: FP64-product Gram of an FP32 J
 POISSON, HEAT, NAVIER_STOKES = 0, 1, 2
 PLAIN, MIXED = 0, 1
@@ -48,7 +48,7 @@ class StepOpts(C.Structure):
                 ("pcg_tol", C.c_double), ("pcg_maxit", C.c_int64), ("ir_tol", C.c_double),
                 ("alpha_out", C.c_void_p), ("fvv_out", C.c_void_p),
                 ("nystrom_chunk_rows", C.c_int64), ("nystrom_reuse", C.c_int32),
-                ("reserved_opts", C.c_int32)]
+                ("pcg_kvp", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -62,7 +62,8 @@ class StepStats(C.Structure):
                 ("ms_gram_kernel", C.c_double), ("gram_attempts", C.c_int32),
                 ("pcg_iterations_ga", C.c_int32), ("primal", C.c_int32),
                 ("ga_early_reject", C.c_int32), ("nystrom_shift", C.c_double),
-                ("nystrom_reused", C.c_int32), ("reserved3", C.c_int32)]
+                ("nystrom_reused", C.c_int32), ("pcg_kvp_f64", C.c_int32),
+                ("pcg_replacements", C.c_int32), ("pcg_escalated", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ir_residual"}
@@ -86,7 +87,7 @@ EXPORTS = [
     "dngd_problem_destroy", "dngd_num_params", "dngd_num_residuals", "dngd_jacobian_ld",
     "dngd_footprint", "dngd_residual_jacobian", "dngd_gram", "dngd_cholesky_solve", "dngd_fvv",
     "dngd_jvp", "dngd_vjp", "dngd_losses", "dngd_nystrom_pcg", "dngd_step", "dngd_iterate",
-    "dngd_footprint_desc", "dngd_cholesky_solve_noalloc",
+    "dngd_footprint_desc", "dngd_cholesky_solve_noalloc", "dngd_kvp",
 ]
 
 
@@ -115,6 +116,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "dngd_fvv": (C.c_int, [vp, vp, vp, vp, vp]),
         "dngd_jvp": (C.c_int, [vp, vp, vp, vp, vp]),
         "dngd_vjp": (C.c_int, [vp, vp, vp, vp, vp]),
+        "dngd_kvp": (C.c_int, [vp, vp, dbl, vp, vp, i32, vp]),
         "dngd_losses": (C.c_int, [vp, vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl), vp]),
         "dngd_nystrom_pcg": (C.c_int, [vp, vp, dbl, vp, i64, dbl, i64, vp, vp,
                                        C.POINTER(StepStats), vp]),
@@ -159,7 +161,7 @@ def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0
               landmarks: Optional[torch.Tensor] = None, pcg_tol=1e-6, pcg_maxit=500,
               ir_tol: Optional[float] = None, alpha_out: Optional[torch.Tensor] = None,
               fvv_out: Optional[torch.Tensor] = None, nystrom_chunk_rows: int = 0,
-              nystrom_reuse: int = 0, no_lookahead: bool = False) -> StepOpts:
+              nystrom_reuse: int = 0, no_lookahead: bool = False, pcg_kvp: int = F64) -> StepOpts:
     o = StepOpts()
     _lib.dngd_step_opts_default(C.byref(o))
     o.precision, o.solver, o.ga = precision, solver, int(bool(ga))
@@ -171,6 +173,7 @@ def step_opts(precision=MIXED, solver=DENSE, ga=True, ir_sweeps=2, gram_passes=0
     o.pcg_tol, o.pcg_maxit = pcg_tol, pcg_maxit
     o.nystrom_chunk_rows, o.nystrom_reuse = int(nystrom_chunk_rows), int(nystrom_reuse)
     o.no_lookahead = int(bool(no_lookahead))
+    o.pcg_kvp = int(pcg_kvp)
     if ir_tol is not None:
         o.ir_tol = ir_tol
     for name, t in (("alpha_out", alpha_out), ("fvv_out", fvv_out)):
@@ -266,6 +269,15 @@ class Problem:
         pp = _dev_f64(p, self.device)
         out = torch.empty(self.n, dtype=torch.float64, device=self.device)
         _check(_lib.dngd_vjp(self._h, _ptr(th), _ptr(pp), _ptr(out), _stream(stream)))
+        return out
+
+    def kvp(self, theta, lam: float, p, dtype: int = F64, stream=None) -> torch.Tensor:
+        """w = J (J^T p) + lam p (dngd_kvp), FP64 or bf16 products."""
+        th = self._theta(theta)
+        pp = _dev_f64(p, self.device)
+        out = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        _check(_lib.dngd_kvp(self._h, _ptr(th), float(lam), _ptr(pp), _ptr(out), int(dtype),
+                             _stream(stream)))
         return out
 
     def losses(self, theta, dtheta, etas, stream=None):
