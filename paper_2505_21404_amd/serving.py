@@ -51,6 +51,7 @@ class JobResult:
     losses: List[float] = field(default_factory=list)
     theta: object = None
     error: Optional[str] = None
+    slot: int = -1          # the slot the job ran in (0 .. max_slots-1)
 
 
 def percentile(xs, q):
@@ -103,6 +104,7 @@ class Server:
                          key=lambda j: (j.arrival, j.job_id))
         in_use = 0
         active = 0
+        free_slots = list(range(self.max_slots))
         threads = []
         t_start = self._clock()
 
@@ -116,6 +118,8 @@ class Server:
                 res.finished = self._clock() - t_start
                 in_use -= res.footprint
                 active -= 1
+                free_slots.append(res.slot)
+                free_slots.sort()
                 self.events.append((res.finished, "finish", spec.job_id, in_use, active))
                 self._lock.notify_all()
 
@@ -132,6 +136,7 @@ class Server:
                         in_use + fps[queue[0].job_id] <= self.budget:
                     spec = queue.pop(0)
                     res = JobResult(spec.job_id, spec.arrival, now, 0.0, fps[spec.job_id])
+                    res.slot = free_slots.pop(0)
                     results[spec.job_id] = res
                     in_use += res.footprint
                     active += 1

@@ -122,3 +122,29 @@ def test_results_identical_alone_and_in_mix():
     for s in specs:
         a, b = alone[s.job_id].theta, rep["results"][s.job_id].theta
         assert np.array_equal(a, b), (s.job_id, np.abs(a - b).max())
+
+
+def test_scheduler_assigns_distinct_slots():
+    """Jobs that run at the same time hold distinct slot indices in
+    [0, max_slots) (the CU partition a job's stream is confined to)."""
+    active = {}
+    lock = threading.Lock()
+    clash = []
+
+    def run_job(spec, res):
+        with lock:
+            if res.slot in active.values() or not (0 <= res.slot < 3):
+                clash.append((spec.job_id, res.slot, dict(active)))
+            active[spec.job_id] = res.slot
+        time.sleep(0.02)
+        with lock:
+            del active[spec.job_id]
+        res.step_ms = [1.0]
+
+    specs = [SV.JobSpec(i, 0.0, None, None, 1) for i in range(12)]
+    srv = SV.Server(budget_bytes=10 ** 9, max_slots=3, run_job=run_job, footprint=lambda s: 1)
+    rep = srv.run(specs, realtime=False)
+    assert not clash, clash
+    assert srv.peak_slots == 3 and rep["steps"] == 12
+    assert {r.slot for r in rep["results"].values()} == {0, 1, 2}
+
