@@ -226,6 +226,8 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
         bh[j] = frag(Bh, rb_, sl);
         if (LO) bl[j] = frag(Bl, rb_, sl);
       }
+      // all fragment reads of the slice issue before its products
+      __builtin_amdgcn_sched_group_barrier(0x100, LO ? 12 : 6, 0);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
