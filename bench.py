@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--pcg-kvp", choices=["f64", "bf16"], default="f64",
                     help="with --pcg: kernel-vector products in FP64 or with bf16 GEMM operands "
                          "(FP32 accumulation, FP64 true residuals)")
+    ap.add_argument("--factor-compare", action="store_true",
+                    help="instead: time the dense Cholesky beside the vendor library's dpotrf")
     ap.add_argument("--kvp", type=int, default=-1, metavar="CFG",
                     help="instead: time the kernel-vector product (FP64 and bf16) on workload CFG")
     ap.add_argument("--pcg-reuse", type=int, default=0,
@@ -417,6 +419,65 @@ def kvp_run(cfg, a, torch):
             "bf16_vs_f64_rel_err": err}
 
 
+def factor_compare_run(a, torch):
+    """The dense factorisation K = L L^T (the Cholesky step of the dense dual
+    solve) through dngd_cholesky_solve (factor only, no right-hand side),
+    beside the vendor library's dpotrf (rocSOLVER, loaded with ctypes for
+    this comparison only; the step never calls it), on the same SPD matrices
+    (diagonal m, off-diagonal 1 / (1 + i + j)): median ms over --steps after
+    --warmup. K is symmetric, so row-major lower and column-major lower hold
+    the same factor."""
+    import ctypes as C
+    import numpy as np
+    from paper_2505_21404_amd import dngd as D
+    roc = None
+    try:
+        rb = C.CDLL("librocblas.so")
+        rs = C.CDLL("librocsolver.so")
+        handle = C.c_void_p()
+        if rb.rocblas_create_handle(C.byref(handle)) == 0:
+            roc = (rb, rs, handle)
+    except OSError:
+        pass
+    out = {"metric": "dense Cholesky factorisation ms", "unit": "ms", "higher_is_better": False,
+           "n_gpus": 1, "sizes": {}}
+    for m in (2000, 5000, 8192):
+        i = torch.arange(m, device="cuda", dtype=torch.float64)
+        K0 = 1.0 / (1.0 + i[:, None] + i[None, :])
+        K0.diagonal().fill_(float(m))
+        K = torch.empty_like(K0)
+        B = torch.empty((0, m), dtype=torch.float64, device="cuda")
+        ts, tr = [], []
+        info = C.c_int32()
+        dinfo = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for k in range(a.warmup + a.steps):
+            K.copy_(K0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            assert D.cholesky_solve(K, B) == 0
+            torch.cuda.synchronize()
+            if k >= a.warmup:
+                ts.append((time.perf_counter() - t0) * 1e3)
+            if roc is not None:
+                rb, rs, handle = roc
+                K.copy_(K0)
+                rb.rocblas_set_stream(handle, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = rs.rocsolver_dpotrf(handle, 122, m, C.c_void_p(K.data_ptr()), m,
+                                         C.c_void_p(dinfo.data_ptr()))
+                torch.cuda.synchronize()
+                if st != 0 or int(dinfo.item()) != 0:
+                    raise RuntimeError(f"rocsolver_dpotrf status {st}, info {int(dinfo.item())}")
+                if k >= a.warmup:
+                    tr.append((time.perf_counter() - t0) * 1e3)
+        out["sizes"][m] = {"dngd_ms": float(np.median(ts)),
+                           "rocsolver_dpotrf_ms": float(np.median(tr)) if tr else None}
+        progress(f"factor m={m}: {out['sizes'][m]}")
+    out["value"] = out["sizes"][5000]["dngd_ms"]
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -444,6 +505,9 @@ def main():
                                      "tol": a.pcg_tol, "iterations": a.pcg_iters},
                           "rows": rows}), flush=True)
         return 0
+    if a.factor_compare:
+        print(json.dumps(factor_compare_run(a, torch)), flush=True)
+        return
     if a.kvp >= 0:
         print(json.dumps(kvp_run(a.kvp, a, torch)), flush=True)
         return

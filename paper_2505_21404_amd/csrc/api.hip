@@ -742,7 +742,8 @@ size_t footprint_bytes(const Geometry& g, const dngd_step_opts* o) {
     const int64_t ldM = round_up(g.m, 4);
     const int64_t RI = nystrom_rows_bound(g, ell);
     const int64_t RC = nystrom_chunk_rows(g, RI);
-    b += (size_t)(RI + ell + 1) * 8 + 2 * (size_t)RI * g.max_width * 8 + 2 * (size_t)RC * RI * 8;
+    b += (size_t)round_up(RI + ell + 1, 32) * 8 + 2 * (size_t)round_up(RI * g.max_width, 32) * 8 +
+         2 * (size_t)round_up(RC * RI, 32) * 8;
     b += (size_t)ell * ldM * 8 + (size_t)ell * ell * 8 + 2 * (size_t)ell * 8 +
          chol_solve_aux_bytes(ell);
     b += gram_workspace_bytes(ell, g.m, DNGD_F64, 1, nullptr);
@@ -1203,16 +1204,20 @@ int pcg_build(dngd_problem* h, const double* theta, double lambda, const int64_t
   const int64_t RC = chunk_rows > 0 ? std::max<int64_t>(chunk_rows, g.C_int)
                                     : nystrom_chunk_rows(g, RI);
   // work (h->J): landmark row lists, gathered G_I and H_I, chunk products Gp, Hp
-  const size_t bRows = (size_t)(RI + ell + 1) * 8, bGath = 2 * (size_t)RI * g.max_width * 8;
-  const size_t bProd = 2 * (size_t)RC * RI * 8;
+  // the gathered rows start 256-byte aligned (the faster product kernel needs
+  // 16-byte aligned operands)
+  const size_t bRows = (size_t)round_up(RI + ell + 1, 32) * 8;
+  const int64_t gath = round_up(RI * g.max_width, 32), prod = round_up(RC * RI, 32);
+  const size_t bGath = 2 * (size_t)gath * 8;
+  const size_t bProd = 2 * (size_t)prod * 8;
   int rc = ensure(h, h->J, bRows + bGath + bProd);
   if (rc) return rc;
   int64_t* dRows = static_cast<int64_t*>(h->J.p);
   int64_t* dQoff = dRows + RI;
-  double* GI = reinterpret_cast<double*>(dQoff + ell + 1);
-  double* HI = GI + (size_t)RI * g.max_width;
-  double* Gp = HI + (size_t)RI * g.max_width;
-  double* Hp = Gp + (size_t)RC * RI;
+  double* GI = reinterpret_cast<double*>(dRows + round_up(RI + ell + 1, 32));
+  double* HI = GI + gath;
+  double* Gp = HI + gath;
+  double* Hp = Gp + prod;
   // Mt (ell x ldM), G (ell x ell), index scratch, ell vector, solve workspace
   const size_t bMt = (size_t)ell * ldM * 8, bG = (size_t)ell * ell * 8;
   rc = ensure(h, h->K, bMt + bG + (size_t)ell * 8 + (size_t)ell * 8 + chol_solve_aux_bytes(ell));
