@@ -192,7 +192,9 @@ def main(argv=None):
               "--cmd", "--out"):
         t.add_argument(a, required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
-    t.add_argument("--copy-kernel", default="")
+    # the calibration run also launches torch's fill of the source tensor,
+    # which fetches nothing: average over the copy kernel's dispatches only
+    t.add_argument("--copy-kernel", default="__amd_rocclr_copyBuffer")
     t.add_argument("--title", default="HBM traffic per dispatch (rocprofv3 --pmc)")
     t.add_argument("--extra", nargs="*", default=[], help="key=value pairs to record")
     a = ap.parse_args(argv)
