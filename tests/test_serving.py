@@ -148,3 +148,26 @@ def test_scheduler_assigns_distinct_slots():
     assert srv.peak_slots == 3 and rep["steps"] == 12
     assert {r.slot for r in rep["results"].values()} == {0, 1, 2}
 
+
+
+@pytest.mark.gpu
+def test_serving_stream_jobs_identical_alone_and_in_mix():
+    """The first six jobs of the serving stream itself (heat and Poisson,
+    widths 64-256, m 2199-5742), three iterations each, arriving 4 per second
+    (compressed 10-fold so that they overlap): every job's parameters are
+    bitwise the same alone and in the mix."""
+    torch = pytest.importorskip("torch")
+    jobs = W.serving_jobs(n_jobs=6, rate=4.0, steps=3)
+    for j in jobs:
+        j.arrival *= 0.1
+    specs = SV.specs_from_workloads(jobs)
+    alone = {s.job_id: SV.run_alone(s) for s in specs}
+    free, _ = torch.cuda.mem_get_info()
+    srv = SV.Server(budget_bytes=int(0.5 * free), max_slots=4)
+    rep = srv.run(specs, realtime=True)
+    print("serving stream jobs", {k: v for k, v in rep.items() if k != "results"}, flush=True)
+    assert not rep["errors"], rep["errors"]
+    assert srv.peak_slots >= 2
+    for s in specs:
+        a, b = alone[s.job_id].theta, rep["results"][s.job_id].theta
+        assert np.array_equal(a, b), (s.job_id, np.abs(a - b).max())
