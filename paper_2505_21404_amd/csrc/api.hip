@@ -1481,6 +1481,8 @@ int dngd_nystrom_pcg(dngd_problem* h, const double* theta, double lambda, const 
     stats->nystrom_shift = P.delta;
     stats->nystrom_reused = 0;
     stats->pcg_kvp_f64 = pr.kvp_f64;
+    stats->pcg_replacements = 0;  // FP64 products: the recursive residual is the true one
+    stats->pcg_escalated = 0;
   }
   return st;
 }
