@@ -168,6 +168,47 @@ def test_autograd_gradcheck_and_oracle_gradient():
     prob.close()
 
 
+def test_autograd_backward_directional_fd_heat_full_size():
+    """The heat workload at full size (MLP 3-1024x4-1, n = 3,153,921,
+    m = 8192): the backward of the autograd.Function (theta_bar = J^T r_bar,
+    dngd_vjp) against central differences of r_bar . r(theta + eps u) along
+    three directions: the gradient's own direction (where the derivative is
+    ||J^T r_bar||) and two random ones. A full gradcheck (n forward passes) is
+    out of reach at this size; directional derivatives test the same map."""
+    from paper_2505_21404_amd import autograd as AG
+    d = D()
+    p = W.config(2)
+    th0 = W.glorot_theta(p.widths, 0)
+    say("case autograd directional FD, heat full size: n", th0.size, "m", p.m)
+    prob = d.Problem.from_workload(p)
+    th = torch.tensor(th0, device="cuda", requires_grad=True)
+    rbar = torch.tensor(W.random_direction(p.m, 5), device="cuda")
+    r = AG.residual(prob, th)
+    (g,) = torch.autograd.grad(r, th, rbar)
+    g = g.detach()
+    gn = float(torch.linalg.norm(g))
+    base = th.detach()
+    dirs = [g / gn] + [torch.tensor(W.random_direction(th0.size, 20 + k), device="cuda")
+                       for k in range(2)]
+    def central(u, eps):
+        fp = float(rbar @ prob.residual(base + eps * u))
+        fm = float(rbar @ prob.residual(base - eps * u))
+        return (fp - fm) / (2 * eps)
+
+    for k, u in enumerate(dirs):
+        u = u / torch.linalg.norm(u)
+        # Richardson extrapolation of two central differences: truncation O(eps^4),
+        # cancellation ~1e-16 |r_bar . r| / eps, both far below 1e-6 ||J^T r_bar||
+        eps = 2e-4
+        fd = (4.0 * central(u, eps / 2) - central(u, eps)) / 3.0
+        an = float(g @ u)
+        say(f"  direction {k}: extrapolated central difference {fd:.12g}, J^T r_bar . u "
+            f"{an:.12g}, difference / ||J^T r_bar|| {abs(fd - an) / gn:.2e}")
+        assert abs(fd - an) <= 1e-6 * gn
+    assert abs(float(g @ dirs[0]) - gn) <= 1e-12 * gn
+    prob.close()
+
+
 # --------------------------------------------------------------------------
 # Nystrom-PCG (a10 - a12)
 
