@@ -104,7 +104,7 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
                                                         const float* __restrict__ J, int64_t ldJ,
                                                         float* __restrict__ work,
                                                         int64_t k_per_split, int64_t ntiles,
-                                                        int64_t per_xcd, int splits,
+                                                        int splits,
                                                         int64_t split0,
                                                         const float* __restrict__ Jt) {
   constexpr bool LO = (PASSES >= 3);
@@ -117,13 +117,19 @@ __global__ __launch_bounds__(512) void gram_bf16_kernel(int64_t m, int64_t n,
   // stage s: A hi, B hi, A lo, B lo
   __shared__ __attribute__((aligned(16))) char lds[2][LO ? 4 : 2][PLANE];
 
-  // launch index -> (split, tile): each XCD gets a contiguous run of tiles of one split
+  // launch index -> (split, tile): workgroups go round-robin over the XCDs;
+  // each XCD owns a band of consecutive tiles and walks it split after split,
+  // so all XCDs work on the same split at a time (its slab of J stays in the
+  // memory-side cache) and tiles of one band share row panels in the XCD's L2
   const int64_t lin = blockIdx.x;
-  const int64_t slt = (lin % NXCD) * per_xcd + lin / NXCD;
-  if (slt >= ntiles * (int64_t)splits) return;  // padding slots
-  const int64_t lsplit = slt / ntiles;           // split within this launch
-  const int64_t split = split0 + lsplit;         // split of the whole K range
-  const int64_t logical = slt % ntiles;
+  const int64_t xcd = lin % NXCD, kx = lin / NXCD;
+  const int64_t q = ntiles / NXCD, rr = ntiles % NXCD;
+  const int64_t tb = q + (xcd < rr ? 1 : 0);            // tiles in this XCD's band
+  const int64_t t0 = xcd * q + min(xcd, rr);
+  if (tb == 0 || kx >= tb * (int64_t)splits) return;   // padding slots
+  const int64_t lsplit = kx / tb;                       // split within this launch
+  const int64_t split = split0 + lsplit;                // split of the whole K range
+  const int64_t logical = t0 + kx % tb;
   int64_t ti, tj;
   tri_decode_g(logical, ti, tj);
   const int64_t kbeg = split * k_per_split;
@@ -457,20 +463,20 @@ int gram_launch(hipStream_t st, int64_t m, int64_t n, const void* J, int64_t ldJ
   const int sk = gram_step_len(ldJ);
   for (int64_t s0 = 0; s0 < splits; s0 += kSplitBatch) {
     const int sb = (int)std::min<int64_t>(kSplitBatch, splits - s0);
-    const int64_t per_xcd = cdiv(nt * sb, NXCD);
+    const int64_t per_xcd = (int64_t)sb * cdiv(nt, NXCD);  // slots of the largest band
     // one workgroup per (split, tile); the kernel derives both from blockIdx.x
     const dim3 grid((unsigned)(per_xcd * NXCD));
     float* w = static_cast<float*>(work);
     const float* Jf = static_cast<const float*>(J);
     if (passes == 4)
       hipLaunchKernelGGL((sk == 16 ? gram_bf16_kernel<4, 16> : gram_bf16_kernel<4, 32>), grid,
-                         dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt, per_xcd, sb, s0, Jt);
+                         dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt, sb, s0, Jt);
     else if (passes == 3)
       hipLaunchKernelGGL((sk == 16 ? gram_bf16_kernel<3, 16> : gram_bf16_kernel<3, 32>), grid,
-                         dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt, per_xcd, sb, s0, Jt);
+                         dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt, sb, s0, Jt);
     else
       hipLaunchKernelGGL((sk == 16 ? gram_bf16_kernel<1, 16> : gram_bf16_kernel<1, 32>), grid,
-                         dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt, per_xcd, sb, s0, Jt);
+                         dim3(512), 0, st, m, n, Jf, ldJ, w, kps, nt, sb, s0, Jt);
     DNGD_LAUNCH_CHECK();
     if (ev_end && s0 + sb >= splits) DNGD_HIP(hipEventRecord(ev_end, st));
     hipLaunchKernelGGL((gram_reduce_kernel<float, BT>), dim3((unsigned)nt, BT * BT / 1024),
