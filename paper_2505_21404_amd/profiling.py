@@ -101,6 +101,7 @@ def traffic_summary(kernel: str, source: str, fetch: str, write: str, copy_fetch
         "fetch_dispatches": f_n,
         "write_kib_per_dispatch": f"{w_kib:.1f}",
         "write_dispatches": w_n,
+        "copy_kernel": copy_kernel,
         "copy_bytes_per_launch": copy_bytes,
         "copy_fetch_kib_per_launch": f"{cf_kib:.1f}",
         "copy_write_kib_per_launch": f"{cw_kib:.1f}",
