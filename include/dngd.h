@@ -272,6 +272,34 @@ int dngd_cholesky_solve_noalloc(int64_t m, double* K, int64_t ldK, int32_t facto
                                 int64_t nrhs, double* B, int64_t ldB, int64_t* info,
                                 void* stream);
 
+/* The operator that iterative refinement solves against: A = J J^T + lambda I
+ * with J as given (Section 4.1, the refinement of the dense dual solve). */
+typedef struct {
+  const void* J;    /* device, m x ldJ row-major, 16-byte aligned */
+  int64_t n;        /* columns of J (parameters), >= 1 */
+  int64_t ldJ;      /* row stride in elements, >= n and a multiple of 4 */
+  int32_t j_dtype;  /* DNGD_F32 or DNGD_F64 */
+  int32_t sweeps;   /* refinement sweeps per right-hand side, 0 .. 16 */
+  double lambda;    /* damping, finite and >= 0 */
+} dngd_refine;
+
+/* Dense dual solve with iterative refinement (Section 4.1; the
+ * DenseDualSolve algorithm): B <- A^{-1} B for A = J J^T + lambda I, with the
+ * Cholesky factor of K ~ A (typically the reduced-precision Gram of J plus
+ * lambda I) as the inner solver. Per right-hand side b: x = K^{-1} b, then
+ * `sweeps` times s = b - (J (J^T x) + lambda x) (J read in its own precision,
+ * FP64 accumulation), x += K^{-1} s. K, ldK, factored, nrhs, B, ldB and info
+ * as in dngd_cholesky_solve; refine must not be NULL. rel_res: host,
+ * nrhs * sweeps doubles or NULL; rel_res[j * sweeps + k] = ||s|| / ||b|| of
+ * sweep k of right-hand side j (a zero b gives 0). Scratch comes from the
+ * stream-ordered allocator and is released before returning. Synchronises
+ * `stream`. Errors: DNGD_EINVAL for bad sizes, a null J, an unaligned J or
+ * ldJ, sweeps out of range or a non-finite lambda (nothing enqueued);
+ * DNGD_ENOTPD as dngd_cholesky_solve (B invalid). */
+int dngd_cholesky_solve_refine(int64_t m, double* K, int64_t ldK, int32_t factored,
+                               int64_t nrhs, double* B, int64_t ldB, const dngd_refine* refine,
+                               double* rel_res, int64_t* info, void* stream);
+
 /* Second directional derivative of the residual along v (Section 3.2):
  * fvv = d^2/dt^2 r(theta + t v) at t = 0. theta, v: device n FP64;
  * fvv: device m FP64. */

@@ -1032,6 +1032,75 @@ int dngd_cholesky_solve_noalloc(int64_t m, double* K, int64_t ldK, int32_t facto
   return cholesky_solve_impl(m, K, ldK, factored, nrhs, B, ldB, info, S(stream), buf);
 }
 
+int dngd_cholesky_solve_refine(int64_t m, double* K, int64_t ldK, int32_t factored,
+                               int64_t nrhs, double* B, int64_t ldB, const dngd_refine* refine,
+                               double* rel_res, int64_t* info, void* stream) {
+  int rc = cholesky_solve_check(m, K, ldK, nrhs, B, ldB, info);
+  if (rc) return rc;
+  DNGD_REQUIRE(refine != nullptr && refine->J != nullptr,
+               "dngd_cholesky_solve_refine: refine and refine->J must not be null");
+  const dngd_refine R = *refine;
+  DNGD_REQUIRE(R.j_dtype == DNGD_F32 || R.j_dtype == DNGD_F64,
+               "dngd_cholesky_solve_refine: j_dtype must be DNGD_F32 or DNGD_F64");
+  DNGD_REQUIRE(R.n >= 1 && R.ldJ >= R.n && R.ldJ % 4 == 0 &&
+                   reinterpret_cast<uintptr_t>(R.J) % 16 == 0,
+               "dngd_cholesky_solve_refine: J needs n >= 1, ldJ >= n, ldJ %% 4 == 0 and a "
+               "16-byte aligned base");
+  DNGD_REQUIRE(R.sweeps >= 0 && R.sweeps <= 16, "dngd_cholesky_solve_refine: sweeps in 0..16");
+  DNGD_REQUIRE(std::isfinite(R.lambda) && R.lambda >= 0.0,
+               "dngd_cholesky_solve_refine: lambda must be finite and >= 0");
+  hipStream_t s = S(stream);
+  // scratch: the Cholesky call's, then (256-byte aligned) b, s (m each),
+  // J^T x (n), the sums of squares, the reduction and gemv_t workspaces
+  const int64_t nss = (int64_t)std::max<int64_t>(1, nrhs) * (R.sweeps + 1);
+  const size_t base = round_up((int64_t)cholesky_solve_scratch_bytes(m), 256);
+  const size_t vec = (size_t)(2 * round_up(m, 32) + round_up(R.n, 32) + round_up(nss, 32)) *
+                     sizeof(double);
+  const size_t bytes = base + vec + kReduceWorkBytes + gemv_t_workspace_bytes(m, R.n);
+  char* buf = nullptr;
+  DNGD_HIP(hipMallocAsync((void**)&buf, bytes, s));
+  double* bcopy = reinterpret_cast<double*>(buf + base);
+  double* sres = bcopy + round_up(m, 32);
+  double* tN = sres + round_up(m, 32);
+  double* ss = tN + round_up(R.n, 32);
+  double* red = ss + round_up(nss, 32);
+  double* gw = red + kReduceWorkBytes / sizeof(double);
+  // factor (and read info back), then the solves with refinement
+  rc = cholesky_solve_impl(m, K, ldK, factored, 0, B, ldB, info, s, buf);
+  double* aux = reinterpret_cast<double*>(buf + 256);
+  if (!rc && nrhs > 0) rc = chol_prepare_solve(s, m, K, ldK, aux);
+  for (int64_t j = 0; j < nrhs && !rc; ++j) {
+    double* x = B + j * ldB;
+    double* ssj = ss + j * (R.sweeps + 1);
+    rc = copy(s, m, x, bcopy);
+    if (!rc) rc = sumsq(s, m, bcopy, ssj, red);
+    if (!rc) rc = chol_solve(s, m, K, ldK, aux, x);
+    for (int k = 0; k < R.sweeps && !rc; ++k) {
+      rc = gemv_t(s, m, R.n, R.J, R.ldJ, R.j_dtype, x, 1.0, tN, gw);
+      if (!rc) rc = gemv_n_residual(s, m, R.n, R.J, R.ldJ, R.j_dtype, tN, bcopy, x, R.lambda, sres);
+      if (!rc) rc = sumsq(s, m, sres, ssj + 1 + k, red);
+      if (!rc) rc = chol_solve(s, m, K, ldK, aux, sres);
+      if (!rc) rc = axpy(s, m, 1.0, sres, x);
+    }
+  }
+  std::vector<double> hss;
+  if (!rc && rel_res && nrhs > 0 && R.sweeps > 0) {
+    hss.resize((size_t)nss);
+    hipError_t e = hipMemcpyAsync(hss.data(), ss, nss * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) rc = hip_fail(e, "rel_res readback", __FILE__, __LINE__);
+  }
+  hipError_t e = hipFreeAsync(buf, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (rc) return rc;
+  DNGD_HIP(e);
+  for (int64_t j = 0; j < (int64_t)hss.size() / (R.sweeps + 1); ++j) {
+    const double bb = hss[j * (R.sweeps + 1)];
+    for (int k = 0; k < R.sweeps; ++k)
+      rel_res[j * R.sweeps + k] = bb > 0.0 ? std::sqrt(hss[j * (R.sweeps + 1) + 1 + k] / bb) : 0.0;
+  }
+  return DNGD_OK;
+}
+
 int dngd_fvv(dngd_problem* h, const double* theta, const double* v, double* fvv, void* stream) {
   DNGD_REQUIRE(h && theta && v && fvv, "dngd_fvv: null argument");
   hipStream_t s = S(stream);

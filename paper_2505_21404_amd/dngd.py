@@ -11,6 +11,7 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,6 +52,11 @@ class StepOpts(C.Structure):
                 ("pcg_kvp", C.c_int32)]
 
 
+class Refine(C.Structure):
+    _fields_ = [("J", C.c_void_p), ("n", C.c_int64), ("ldJ", C.c_int64), ("j_dtype", C.c_int32),
+                ("sweeps", C.c_int32), ("lam", C.c_double)]
+
+
 class StepStats(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_residual_jacobian", C.c_double),
                 ("ms_gram", C.c_double), ("ms_factor", C.c_double), ("ms_solve_v", C.c_double),
@@ -88,6 +94,7 @@ EXPORTS = [
     "dngd_footprint", "dngd_residual_jacobian", "dngd_gram", "dngd_cholesky_solve", "dngd_fvv",
     "dngd_jvp", "dngd_vjp", "dngd_losses", "dngd_nystrom_pcg", "dngd_step", "dngd_iterate",
     "dngd_footprint_desc", "dngd_cholesky_solve_noalloc", "dngd_kvp",
+    "dngd_cholesky_solve_refine",
 ]
 
 
@@ -113,6 +120,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "dngd_cholesky_solve": (C.c_int, [i64, vp, i64, i32, i64, vp, i64, C.POINTER(i64), vp]),
         "dngd_cholesky_solve_noalloc": (C.c_int, [i64, vp, i64, i32, i64, vp, i64,
                                                   C.POINTER(i64), vp]),
+        "dngd_cholesky_solve_refine": (C.c_int, [i64, vp, i64, i32, i64, vp, i64,
+                                                 C.POINTER(Refine), vp, C.POINTER(i64), vp]),
         "dngd_fvv": (C.c_int, [vp, vp, vp, vp, vp]),
         "dngd_jvp": (C.c_int, [vp, vp, vp, vp, vp]),
         "dngd_vjp": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -344,6 +353,28 @@ def gram(J: torch.Tensor, n: int, lam: float, passes: int = 1, stream=None) -> t
     _check(_lib.dngd_gram(m, n, _ptr(J), ldJ, jd, passes, float(lam), _ptr(K), m,
                           _stream(stream)))
     return K
+
+
+def cholesky_solve_refine(K: torch.Tensor, B: torch.Tensor, J: torch.Tensor, n: int, lam: float,
+                          sweeps: int, factored: bool = False, stream=None):
+    """B <- (J J^T + lam I)^{-1} B with the Cholesky factor of K (lower
+    triangle, factored in place unless ``factored``) as the inner solver and
+    ``sweeps`` refinement sweeps against J (m x ldJ, FP32 or FP64). B is
+    (nrhs, m) or (m,) FP64. Returns (info, rel_res) with rel_res an
+    (nrhs, sweeps) array of ||b - A x|| / ||b|| per sweep."""
+    m = K.shape[0]
+    assert B.dtype == torch.float64 and B.is_contiguous() and J.is_contiguous()
+    nrhs, ldB = (1, m) if B.dim() == 1 else (B.shape[0], B.shape[1])
+    jd = F64 if J.dtype == torch.float64 else F32
+    R = Refine(_ptr(J), int(n), J.shape[1], jd, int(sweeps), float(lam))
+    rel = (C.c_double * max(1, nrhs * sweeps))()
+    info = C.c_int64()
+    rc = _lib.dngd_cholesky_solve_refine(m, _ptr(K), K.stride(0), int(factored), nrhs, _ptr(B),
+                                         ldB, C.byref(R), rel, C.byref(info), _stream(stream))
+    if rc == ENOTPD:
+        return int(info.value), None
+    _check(rc)
+    return 0, np.array(rel[:nrhs * sweeps], dtype=np.float64).reshape(nrhs, sweeps)
 
 
 def cholesky_solve(K: torch.Tensor, B: torch.Tensor, factored: bool = False, stream=None,

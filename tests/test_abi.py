@@ -63,6 +63,19 @@ def test_argument_validation_without_gpu():
                                            ctypes.c_void_p(8), 2049, ctypes.byref(info),
                                            None) == dngd.EINVAL
     assert b"2048" in lib.dngd_last_error()
+    # the refined solve: a refinement description is required and checked
+    K, B = ctypes.c_void_p(256), ctypes.c_void_p(256)
+    assert lib.dngd_cholesky_solve_refine(4, K, 4, 0, 1, B, 4, None, None, ctypes.byref(info),
+                                          None) == dngd.EINVAL
+    good = dict(J=256, n=8, ldJ=8, j_dtype=dngd.F32, sweeps=2, lam=1e-3)
+    for change, word in ((dict(J=None), b"null"), (dict(J=264), b"aligned"),
+                         (dict(ldJ=6), b"ldJ"), (dict(n=0), b"n >= 1"),
+                         (dict(j_dtype=dngd.BF16), b"j_dtype"), (dict(sweeps=17), b"sweeps"),
+                         (dict(lam=float("nan")), b"lambda")):
+        R = dngd.Refine(**{**good, **change})
+        assert lib.dngd_cholesky_solve_refine(4, K, 4, 0, 1, B, 4, ctypes.byref(R), None,
+                                              ctypes.byref(info), None) == dngd.EINVAL, change
+        assert word in lib.dngd_last_error(), (change, lib.dngd_last_error())
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libdngd.so not built")

@@ -20,6 +20,7 @@ int main(void) {
   printf("dngd_step_stats size %zu\n", sizeof(dngd_step_stats));
   printf("dngd_iter_stats size %zu\n", sizeof(dngd_iter_stats));
   printf("dngd_problem_desc size %zu\n", sizeof(dngd_problem_desc));
+  printf("dngd_refine size %zu\n", sizeof(dngd_refine));
   P(dngd_step_opts, eps_norm) P(dngd_step_opts, landmarks) P(dngd_step_opts, ir_tol)
   P(dngd_step_opts, fvv_out) P(dngd_step_opts, nystrom_chunk_rows) P(dngd_step_opts, nystrom_reuse)
   P(dngd_step_stats, ga_accepted) P(dngd_step_stats, ir_residual)
@@ -27,6 +28,7 @@ int main(void) {
   P(dngd_step_stats, nystrom_shift) P(dngd_step_stats, nystrom_reused)
   P(dngd_iter_stats, eta_index) P(dngd_iter_stats, step)
   P(dngd_problem_desc, kappa) P(dngd_problem_desc, x_int) P(dngd_problem_desc, g_init)
+  P(dngd_refine, n) P(dngd_refine, j_dtype) P(dngd_refine, sweeps) P(dngd_refine, lambda)
   return 0;
 }
 """
@@ -48,7 +50,8 @@ def test_struct_layout_matches_header():
         t, f, v = line.split()
         got[(t, f)] = int(v)
     py = {"dngd_step_opts": D.StepOpts, "dngd_step_stats": D.StepStats,
-          "dngd_iter_stats": D.IterStats, "dngd_problem_desc": D.ProblemDesc}
+          "dngd_iter_stats": D.IterStats, "dngd_problem_desc": D.ProblemDesc,
+          "dngd_refine": D.Refine}
     rename = {"lambda": "lam"}
     for (t, f), v in got.items():
         cls = py[t]
