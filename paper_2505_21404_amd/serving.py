@@ -52,6 +52,10 @@ class JobResult:
     theta: object = None
     error: Optional[str] = None
     slot: int = -1          # the slot the job ran in (0 .. max_slots-1)
+    # start of each step in seconds after the start of the run, read from
+    # ``now`` (the server's clock, set at admission) by the executor
+    step_start: List[float] = field(default_factory=list)
+    now: Optional[Callable[[], float]] = None
 
 
 def percentile(xs, q):
@@ -137,6 +141,7 @@ class Server:
                     spec = queue.pop(0)
                     res = JobResult(spec.job_id, spec.arrival, now, 0.0, fps[spec.job_id])
                     res.slot = free_slots.pop(0)
+                    res.now = lambda: self._clock() - t_start
                     results[spec.job_id] = res
                     in_use += res.footprint
                     active += 1
@@ -170,6 +175,24 @@ def report(results: Dict[int, JobResult], makespan: float, server: Server) -> Di
     # apart from the spread of job sizes
     norm = [x / statistics.median(r.step_ms) for r in served if r.step_ms for x in r.step_ms]
     steps = len(lat)
+    # each step against the median of the same job's steps that ran beside the
+    # same set of other jobs: the tail of interference alone, without the
+    # changes of company as jobs finish and others are admitted
+    same = float("nan")
+    timed = [r for r in served if r.step_ms]
+    if timed and all(len(r.step_start) == len(r.step_ms) for r in timed):
+        span = {r.job_id: (r.admitted, r.finished) for r in served}
+        ratios = []
+        for r in timed:
+            groups: Dict[tuple, List[float]] = {}
+            for t, x in zip(r.step_start, r.step_ms):
+                key = tuple(sorted(k for k, (a, f) in span.items()
+                                   if k != r.job_id and a <= t < f))
+                groups.setdefault(key, []).append(x)
+            for xs in groups.values():
+                med = statistics.median(xs)
+                ratios += [x / med for x in xs]
+        same = percentile(ratios, 0.99)
     return {
         "jobs": len(results),
         "rejected": len(results) - len(served),
@@ -183,6 +206,7 @@ def report(results: Dict[int, JobResult], makespan: float, server: Server) -> Di
         "steady_p50_step_ms": percentile(steady, 0.50),
         "steady_p99_step_ms": percentile(steady, 0.99),
         "p99_over_job_median": percentile(norm, 0.99),
+        "p99_over_same_company_median": same,
         "mean_step_ms": statistics.fmean(lat) if lat else float("nan"),
         "admission_wait_p50_s": percentile(waits, 0.50),
         "admission_wait_max_s": max(waits) if waits else float("nan"),
@@ -229,6 +253,8 @@ def gpu_executor(device: str = "cuda", opts_fn: Optional[Callable] = None,
                 stream.synchronize()
                 opts = make_opts(spec)
                 for _ in range(spec.steps):
+                    if res.now is not None:
+                        res.step_start.append(res.now())
                     t0 = time.perf_counter()
                     st = prob.iterate(theta, ETA_GRID, lam_cap=spec.lam_cap, opts=opts,
                                       stream=stream)

@@ -126,7 +126,7 @@ def test_results_identical_alone_and_in_mix():
 
 def test_scheduler_assigns_distinct_slots():
     """Jobs that run at the same time hold distinct slot indices in
-    [0, max_slots) (the CU partition a job's stream is confined to)."""
+    [0, max_slots) (JobResult.slot)."""
     active = {}
     lock = threading.Lock()
     clash = []
@@ -148,6 +148,38 @@ def test_scheduler_assigns_distinct_slots():
     assert srv.peak_slots == 3 and rep["steps"] == 12
     assert {r.slot for r in rep["results"].values()} == {0, 1, 2}
 
+
+
+def test_tail_with_and_without_changes_of_company():
+    """A job's step time that depends only on how many jobs run beside it
+    has a tail over its own median (company changes as jobs come and go)
+    but none over the median of steps taken beside the same jobs."""
+    live = set()
+    lock = threading.Lock()
+
+    def run_job(spec, res):
+        with lock:
+            live.add(spec.job_id)
+        for _ in range(spec.steps):
+            # start time and company read together: a job joins `live` after
+            # its admission time and leaves it before its finish time, so a
+            # step can only see less company than its interval says (ratio < 1)
+            with lock:
+                res.step_start.append(res.now())
+                k = len(live)
+            time.sleep(0.004 * k)
+            res.step_ms.append(4.0 * k)  # the step's nominal time: 4 ms per resident job
+        with lock:
+            live.discard(spec.job_id)
+
+    # job 0 runs alone, then beside the two jobs arriving after it
+    specs = [SV.JobSpec(0, 0.0, None, None, 40), SV.JobSpec(1, 0.06, None, None, 5),
+             SV.JobSpec(2, 0.06, None, None, 5)]
+    srv = SV.Server(budget_bytes=10, max_slots=3, run_job=run_job, footprint=lambda s: 1)
+    rep = srv.run(specs, realtime=True)
+    assert all(len(r.step_start) == len(r.step_ms) for r in rep["results"].values())
+    assert rep["p99_over_job_median"] >= 2.0
+    assert rep["p99_over_same_company_median"] <= 1.5
 
 
 @pytest.mark.gpu
