@@ -17,9 +17,10 @@
  *     workspace it allocates (from the stream-ordered allocator, on the
  *     stream of the call that first needs it) and frees it in
  *     dngd_problem_destroy. Stateless
- *     calls (dngd_gram, dngd_cholesky_solve) take their scratch from the
- *     stream-ordered allocator of the stream's device and release it before
- *     returning; dngd_cholesky_solve_noalloc uses a static device array.
+ *     calls (dngd_gram, dngd_cholesky_solve, dngd_cholesky_solve_refine)
+ *     take their scratch from the stream-ordered allocator of the stream's
+ *     device and release it before returning; dngd_cholesky_solve_noalloc
+ *     uses a static device array.
  *   - A dngd_problem is not thread-safe; use one per job and one stream per
  *     problem at a time.
  *

@@ -23,6 +23,7 @@ int main(void) {
   printf("dngd_refine size %zu\n", sizeof(dngd_refine));
   P(dngd_step_opts, eps_norm) P(dngd_step_opts, landmarks) P(dngd_step_opts, ir_tol)
   P(dngd_step_opts, fvv_out) P(dngd_step_opts, nystrom_chunk_rows) P(dngd_step_opts, nystrom_reuse)
+  P(dngd_step_opts, pcg_kvp)
   P(dngd_step_stats, ga_accepted) P(dngd_step_stats, ir_residual)
   P(dngd_step_stats, ms_gram_kernel) P(dngd_step_stats, gram_attempts)
   P(dngd_step_stats, nystrom_shift) P(dngd_step_stats, nystrom_reused)
