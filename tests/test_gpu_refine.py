@@ -144,3 +144,30 @@ def test_refined_solve_edge_cases():
     Kn[6, 6] = -1.0
     info, res = d.cholesky_solve_refine(Kn, torch.tensor(b, device="cuda"), Jt, n, lam, 2)
     assert info == 7 and res is None
+
+
+def test_refined_solve_composes_the_mixed_step_at_full_size():
+    """At the 5-D Poisson workload (m = 5000, n = 133,377): residual and
+    FP32 J, the 3-pass bf16 Gram and the refined solve with 2 sweeps give the
+    dual solution of dngd_step (same Gram passes and sweeps, no look-ahead)
+    bit for bit, since they run the same kernels in the same order."""
+    d = D()
+    p = W.config(1)
+    th = torch.tensor(W.glorot_theta(p.widths, 0), device="cuda")
+    say("case refine composed vs step: m", p.m, "n", p.n_params)
+    prob = d.Problem.from_workload(p)
+    lam = 1e-5
+    alpha = torch.empty(p.m, dtype=torch.float64, device="cuda")
+    o = d.step_opts(precision=d.MIXED, ga=False, gram_passes=3, ir_sweeps=2, no_lookahead=True,
+                    alpha_out=alpha)
+    _, st = prob.step(th, lam, o)
+    r, J = prob.residual_jacobian(th, d.F32)
+    K = d.gram(J, prob.n, lam, passes=3)
+    x = r.clone()
+    info, res = d.cholesky_solve_refine(K, x, J, prob.n, lam, 2)
+    say(f"  step IR residuals {list(st.ir_residual)[:2]}, refined solve {res.tolist()}")
+    assert info == 0
+    assert torch.equal(x, alpha)
+    for k in range(2):  # the same per-sweep residuals, ||s_k|| / ||r||
+        assert abs(res[0, k] - st.ir_residual[k]) <= 1e-12 * st.ir_residual[k]
+    prob.close()
