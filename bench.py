@@ -617,7 +617,11 @@ def main():
     tr = read_traffic(TRAFFIC_RECORD, ROOT)
     if tr is not None and int(tr.get("gram_passes", "-1")) == stats[-1]["gram_passes_used"]:
         out["roofline"]["traffic"] = float(tr["traffic_bytes_per_dispatch"])
-        out["roofline"]["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        out["roofline"]["traffic_unit"] = ("bytes per launch (FETCH_SIZE + WRITE_SIZE, "
+                                           "copy-calibrated; L2 misses, memory-side cache "
+                                           "hits included)")
+    # what the contraction must move: J read once, the lower triangle of K written
+    out["roofline"]["algorithmic_bytes"] = float(4 * m * n + 8 * m * (m + 1) // 2)
 
     if not a.no_plain:
         plain = D.step_opts(precision=D.PLAIN, ga=True)
