@@ -129,7 +129,12 @@ typedef struct {
                            with 1 if 2^-8 sqrt(D / lambda) <= 0.02, else 3 if
                            2^-16 D <= lambda / 10, else 4; then escalate (3 -> 4 ->
                            DNGD_GRAM_F64, 1 -> 4) when the factorisation fails or the
-                           refinement residual of the v solve stays above ir_tol. */
+                           refinement residual of the v solve stays above ir_tol. The
+                           handle remembers the tier a step escalated to and the damping
+                           it did so at; a later auto step of the same system (dual or
+                           primal) with damping at or below that one starts at that tier
+                           instead of repeating the attempts that failed, and a larger
+                           damping clears the memory. */
   int32_t no_lookahead;  /* dense: 1 = factor without the side-stream look-ahead (default 0) */
   double eps_norm;      /* GA guard: GA only if ||v|| > eps_norm (default 0) */
   /* PCG (solver == DNGD_PCG) */
@@ -194,6 +199,8 @@ typedef struct {
   int32_t pcg_replacements;   /* PCG with bf16 products: recursive residuals replaced by
                                  FP64 true residuals (both solves) */
   int32_t pcg_escalated;      /* PCG with bf16 products: 1 if a solve switched to FP64 products */
+  int32_t gram_start_passes;  /* mixed dense: the Gram tier the step started at (the auto
+                                 choice, or the handle's remembered escalation) */
 } dngd_step_stats;
 
 const char* dngd_last_error(void);

@@ -83,6 +83,12 @@ struct dngd_problem {
   // steps; -1 when K's buffer holds something else
   Precond pc;
   int pc_age = -1;
+  // Gram tier that the adaptive mixed step last escalated to, with the
+  // damping and system (dual or primal) it escalated at: a later step on the
+  // same system with damping at or below starts at that tier
+  int gram_hint = 0;
+  double gram_hint_lambda = 0.0;
+  bool gram_hint_primal = false;
   // Device memory comes from the stream-ordered allocator on the stream of
   // the call in progress (astream), so that growing a buffer mid-job or
   // destroying a handle never waits for the whole device (other jobs'
@@ -1904,6 +1910,15 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   double* K = static_cast<double*>(h->K.p);
   const int ir = (jd == DNGD_F32) ? o.ir_sweeps : 0;
   const bool adaptive = (jd == DNGD_F32 && o.gram_passes == 0);
+  if (adaptive && h->gram_hint != 0) {
+    // tiers are ordered 1 < 3 < 4 < DNGD_GRAM_F64 by value; a smaller damping
+    // only makes the system harder, a larger one drops the memory
+    if (h->gram_hint_primal == primal && lambda <= h->gram_hint_lambda)
+      passes = std::max(passes, h->gram_hint);
+    else
+      h->gram_hint = 0;
+  }
+  st.gram_start_passes = passes;
   int64_t info = 0;
   int attempts = 0;
   for (;;) {
@@ -1956,6 +1971,11 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
   }
   st.gram_passes_used = passes;
   st.gram_attempts = attempts;
+  if (adaptive && attempts > 1) {
+    h->gram_hint = passes;
+    h->gram_hint_lambda = lambda;
+    h->gram_hint_primal = primal;
+  }
   // v = -J^T alpha (dual) or v = -x (primal)
   if (primal) {
     rc = fill(s, g.n, 0.0, v.v);

@@ -69,7 +69,8 @@ class StepStats(C.Structure):
                 ("pcg_iterations_ga", C.c_int32), ("primal", C.c_int32),
                 ("ga_early_reject", C.c_int32), ("nystrom_shift", C.c_double),
                 ("nystrom_reused", C.c_int32), ("pcg_kvp_f64", C.c_int32),
-                ("pcg_replacements", C.c_int32), ("pcg_escalated", C.c_int32)]
+                ("pcg_replacements", C.c_int32), ("pcg_escalated", C.c_int32),
+                ("gram_start_passes", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ir_residual"}

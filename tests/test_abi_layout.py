@@ -27,6 +27,7 @@ int main(void) {
   P(dngd_step_stats, ga_accepted) P(dngd_step_stats, ir_residual)
   P(dngd_step_stats, ms_gram_kernel) P(dngd_step_stats, gram_attempts)
   P(dngd_step_stats, nystrom_shift) P(dngd_step_stats, nystrom_reused)
+  P(dngd_step_stats, pcg_escalated) P(dngd_step_stats, gram_start_passes)
   P(dngd_iter_stats, eta_index) P(dngd_iter_stats, step)
   P(dngd_problem_desc, kappa) P(dngd_problem_desc, x_int) P(dngd_problem_desc, g_init)
   P(dngd_refine, n) P(dngd_refine, j_dtype) P(dngd_refine, sweeps) P(dngd_refine, lambda)

@@ -327,6 +327,57 @@ def test_mixed_step_escalates_on_stiff_job():
     prob.close()
 
 
+def test_stiff_job_remembers_its_gram_tier():
+    """The handle remembers the Gram tier its adaptive step escalated to and
+    the damping it escalated at. On the same stiff serving job: once a step
+    has escalated, later steps at that damping or below start at the
+    remembered tier (one attempt for the FP64 tier) and still match the
+    oracle; the step equals a fresh handle's step bit for bit when both end
+    on the same tier; a larger damping clears the memory."""
+    from paper_2505_21404_amd import serving as SV
+    d = D()
+    spec = SV.specs_from_workloads(W.serving_jobs(n_jobs=37, rate=4.0, steps=3))[36]
+    p = spec.problem
+    prob = d.Problem.from_workload(p)
+    theta = torch.tensor(spec.theta0, device="cuda")
+    dbuf = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    opts = d.step_opts(precision=d.MIXED, ga=True)
+    hint, hint_lam = 0, 0.0
+    for k in range(4):
+        th_k = theta.cpu().numpy().copy()
+        st = prob.iterate(theta, SV.ETA_GRID, lam_cap=spec.lam_cap, opts=opts, dtheta_out=dbuf)
+        s_ = st.step
+        say(f"iter {k} lam {st.lam:.3g} start {s_.gram_start_passes} used {s_.gram_passes_used} "
+            f"attempts {s_.gram_attempts}")
+        if hint and st.lam <= hint_lam:
+            assert s_.gram_start_passes == hint
+            if hint == d.GRAM_F64:
+                assert s_.gram_attempts == 1
+            e = rel(dbuf.cpu().numpy(), S.dense_step(p, th_k, st.lam, ga=True).dtheta)
+            say(f"  remembered tier, rel err {e:.2e}")
+            assert e <= 1e-4
+        if s_.gram_attempts > 1:
+            hint, hint_lam = s_.gram_passes_used, st.lam
+    assert hint != 0, "the job did not escalate"
+    # a fresh handle at the same theta and damping: same step when the tier agrees
+    d1, st1 = prob.step(theta, hint_lam, opts)
+    fresh = d.Problem.from_workload(p)
+    d2, st2 = fresh.step(theta, hint_lam, opts)
+    say(f"hinted: start {st1.gram_start_passes} used {st1.gram_passes_used} attempts "
+        f"{st1.gram_attempts}; fresh: start {st2.gram_start_passes} used "
+        f"{st2.gram_passes_used} attempts {st2.gram_attempts}")
+    assert st1.gram_start_passes == hint and st2.gram_start_passes <= hint
+    if st2.gram_passes_used == st1.gram_passes_used:
+        assert torch.equal(d1, d2)
+    fresh.close()
+    # a larger damping starts from the auto choice and clears the memory
+    st3 = prob.step(theta, 1e3 * hint_lam, opts)[1]
+    if st3.gram_attempts == 1:
+        st4 = prob.step(theta, hint_lam, opts)[1]
+        assert st4.gram_start_passes == st2.gram_start_passes
+    prob.close()
+
+
 def test_gram_f64_products_of_fp32_jacobian():
     """dngd_gram with FP32 J and passes = DNGD_GRAM_F64: the exact Gram of the
     FP32 values up to FP64 rounding."""
