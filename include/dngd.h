@@ -117,7 +117,9 @@ typedef struct dngd_problem dngd_problem;
 typedef struct {
   int32_t precision;    /* DNGD_PLAIN: FP64 J, FP64-MFMA Gram.
                            DNGD_MIXED: FP32 J, BF16-MFMA Gram with FP32
-                           accumulation, FP64 Cholesky and refinement. */
+                           accumulation, FP64 Cholesky and refinement; f_vv
+                           with FP32 matrix-core layer products (FP64 jet
+                           rules; dngd_fvv itself stays FP64). */
   int32_t solver;       /* dngd_solver: DNGD_DENSE (default), DNGD_PCG, DNGD_PRIMAL,
                            DNGD_DENSE_AUTO, DNGD_STRUCTURED */
   int32_t ga;           /* 1: geodesic acceleration (Section 3.2), 0: off */

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdngd.so")
 SOURCES = ["api.hip", "net.hip", "gemm_f64.hip", "gram.hip", "chol.hip", "blas1.hip",
-           "gemm_bf16.hip", "lowp.hip"]
+           "gemm_bf16.hip", "lowp.hip", "gemm_f32.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DNGD_OFFLOAD_ARCH", "gfx950")

@@ -249,7 +249,7 @@ int ensure_tangent(dngd_problem* h) {
 // Forward t-tangent streams along direction dir (requires forward() at theta).
 // order 1: out = J dir.  order 2: out = d^2/dt^2 r(theta + t dir).
 int tangent(dngd_problem* h, const double* theta, const double* dir, int order, double* out,
-            hipStream_t s) {
+            hipStream_t s, bool f32 = false) {
   const Geometry& g = h->g;
   int rc = ensure_tangent(h);
   if (rc) return rc;
@@ -259,6 +259,33 @@ int tangent(dngd_problem* h, const double* theta, const double* dir, int order, 
   for (int l = 0; l < g.L - 1; ++l) {
     const int win = g.widths[l], wout = g.widths[l + 1];
     const double* a0 = act_in(h, l);
+    if (f32 && win >= 16) {
+      // FP32 matrix-core products, each tangent order one launch:
+      // Z1 = a0 V^T (+ a1 W^T), Z2 = a2 W^T + 2 a1 V^T
+      const int64_t ld[2] = {win, win}, kk[2] = {win, win};
+      const double one2[2] = {1.0, 1.0}, z2a[2] = {1.0, 2.0};
+      const double* A1[2] = {a0, a1p};
+      const double* B1[2] = {Wp(h, dir, l), Wp(h, theta, l)};
+      rc = gemm_f32_nt(s, g.R, wout, a1p ? 2 : 1, A1, ld, B1, ld, kk, one2, 0.0, h->Z1, wout);
+      if (rc) return rc;
+      if (order >= 2) {
+        if (a1p) {
+          const double* A2[2] = {a2p, a1p};
+          const double* B2[2] = {Wp(h, theta, l), Wp(h, dir, l)};
+          rc = gemm_f32_nt(s, g.R, wout, 2, A2, ld, B2, ld, kk, z2a, 0.0, h->Z2, wout);
+        } else {
+          rc = fill(s, g.R * wout, 0.0, h->Z2);
+        }
+        if (rc) return rc;
+      }
+      rc = net_tangent_act(s, h->rm, wout, Bp(h, dir, l), h->Z[l], h->Z1, h->Z2, h->A1[cur],
+                           h->A2[cur], order);
+      if (rc) return rc;
+      a1p = h->A1[cur];
+      a2p = h->A2[cur];
+      cur ^= 1;
+      continue;
+    }
     // Z1 = a1 W^T + a0 V^T
     rc = gemm_f64(s, GEMM_FULL, true, true, g.R, wout, win, 1.0, a0, win, Wp(h, dir, l), win, 0.0,
                   h->Z1, wout);
@@ -1989,8 +2016,9 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
 
   if (o.ga) {
     // f_vv along v (Section 3.2); a = -J^T (K + lam I)^{-1} f_vv (dual) or
-    // a = -(J^T J + lam I)^{-1} J^T f_vv (primal)
-    rc = tangent(h, theta, v.v, 2, v.fvv, s);
+    // a = -(J^T J + lam I)^{-1} J^T f_vv (primal). The mixed step takes the
+    // hidden layers' products in FP32 on the matrix cores (jet rules in FP64).
+    rc = tangent(h, theta, v.v, 2, v.fvv, s, jd == DNGD_F32);
     if (!rc && o.fvv_out) rc = copy(s, g.m, v.fvv, o.fvv_out);
     if (rc) return rc;
     DNGD_HIP(hipEventRecord(h->ev[5], s));

@@ -260,6 +260,12 @@ int net_colsum_value_rows(hipStream_t s, const RowMap& rm, int w, const double* 
 // uint16 storage), row-major, K-contiguous: C = A0 B0^T + A1 B1^T (segment 1
 // optional, K1 = 0), K0, K1 multiples of 32, leading dimensions multiples of
 // 8, 16-byte aligned bases.
+// C (M x N, FP64) = sum_s alpha_s A_s (M x K_s) B_s (N x K_s)^T + beta C for
+// nseg = 1 or 2 segments of FP64 operands, row-major along K; operands are
+// rounded to FP32 and multiplied on the FP32 matrix cores (gemm_f32.hip)
+int gemm_f32_nt(hipStream_t s, int64_t M, int64_t N, int nseg, const double* const* A,
+                const int64_t* lda, const double* const* B, const int64_t* ldb, const int64_t* K,
+                const double* alpha, double beta, double* C, int64_t ldc);
 int gemm_bf16_nt(hipStream_t s, int64_t M, int64_t N, const uint16_t* A0, int64_t lda0,
                  const uint16_t* B0, int64_t ldb0, int64_t K0, const uint16_t* A1, int64_t lda1,
                  const uint16_t* B1, int64_t ldb1, int64_t K1, float* C, int64_t ldc);
