@@ -11,11 +11,13 @@
 // Z = a0 V^T + a1 W^T run as one product with one store.
 //
 // Tile: 128 x 128 per workgroup of 4 waves (2 x 2), each wave 64 x 64 = 2 x 2
-// accumulators. K advances 16 per step: each thread fetches 8 elements of each
-// operand a step ahead into registers and stores them, converted, into a
-// double-buffered LDS stage whose rows are padded to 17 floats (the 32 rows a
+// accumulators. K advances 32 per step: each thread fetches 16 elements of
+// each operand a step ahead into registers (as FP64, so the current step's
+// products run while they are in flight) and stores them, converted, into a
+// double-buffered LDS stage whose rows are padded to 33 floats (the 32 rows a
 // fragment read touches fall in distinct banks). Rows beyond M or N read the
-// last row and are not stored; K beyond K_s reads zeros.
+// last row and are not stored; K beyond K_s reads zeros. (16-element steps, or
+// converting as the loads return, were 1-5% slower.)
 #include "common.h"
 
 namespace dngd {
@@ -25,7 +27,7 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int TM = 128;          // tile edge
-constexpr int KS = 16;           // K per step
+constexpr int KS = 32;           // K per step
 constexpr int RS = KS + 1;       // LDS row stride in floats
 constexpr int NTH = 256;
 constexpr int PER = TM * KS / NTH;  // elements of one operand per thread and step
@@ -49,33 +51,35 @@ __global__ __launch_bounds__(256) void gemm_f32_nt_kernel(int64_t M, int64_t N, 
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  // element q of a step: row (q NTH + t) / KS, column (q NTH + t) % KS
-  float ra[PER], rb[PER];
+  // element q of a step: row (q NTH + t) / KS, column (q NTH + t) % KS. The
+  // loads land in registers as FP64 and are converted only when stored, so
+  // the products of the current step run while they are in flight.
+  double ra[PER], rb[PER];
+  int64_t kend = 0;   // elements of the loaded step's K range in its segment
+  double al = 1.0;    // its segment's alpha
   auto gload = [&](int64_t step) {
     const int s = step < sg.steps0 ? 0 : 1;
     const int64_t k0 = (step - (s ? sg.steps0 : 0)) * KS;
     const double* A = sg.A[s];
     const double* B = sg.B[s];
     const int64_t lda = sg.lda[s], ldb = sg.ldb[s], K = sg.K[s];
-    const double al = sg.alpha[s];
+    kend = K - k0;
+    al = sg.alpha[s];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = q * NTH + t, r = e / KS, c = e % KS;
-      const int64_t k = k0 + c;
-      const bool in = k < K;
-      const int64_t kc = in ? k : K - 1;
-      const double a = A[min(ti * TM + r, M - 1) * lda + kc];
-      const double b = B[min(tj * TM + r, N - 1) * ldb + kc];
-      ra[q] = in ? (float)a : 0.0f;
-      rb[q] = in ? (float)(al * b) : 0.0f;
+      const int64_t kc = min(k0 + c, K - 1);
+      ra[q] = A[min(ti * TM + r, M - 1) * lda + kc];
+      rb[q] = B[min(tj * TM + r, N - 1) * ldb + kc];
     }
   };
   auto lstore = [&](int st) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = q * NTH + t, r = e / KS, c = e % KS;
-      la[st][r * RS + c] = ra[q];
-      lb[st][r * RS + c] = rb[q];
+      const bool in = c < kend;
+      la[st][r * RS + c] = in ? (float)ra[q] : 0.0f;
+      lb[st][r * RS + c] = in ? (float)(al * rb[q]) : 0.0f;
     }
   };
   f32x16 acc[2][2];
