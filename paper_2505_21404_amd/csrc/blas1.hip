@@ -279,9 +279,11 @@ __global__ void ga_combine_kernel(int64_t n, const double* __restrict__ v, const
   const double vn = sqrt(norms2[0]);
   const double an = sqrt(norms2[1]);
   const bool acc = (vn > eps) && (2.0 * an <= 0.5 * vn);
-  const double coef = acc ? 0.5 : 0.0;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) dtheta[i] = v[i] + coef * a[i];
+  // a rejected correction leaves v exactly and never reads a (which the
+  // early rejection does not compute: 0 * a would turn stale non-finite
+  // values into NaN)
+  if (i < n) dtheta[i] = acc ? v[i] + 0.5 * a[i] : v[i];
   if (i == 0 && flag_out) *flag_out = acc ? 1 : 0;
 }
 

@@ -2,7 +2,9 @@
 DNGD_ENAN on every solver, PCG stopped at maxit gives DNGD_ENOCONV with a
 finite last iterate, and the serving loop queues jobs when the memory budget
 admits one at a time and rejects jobs that can never fit. Every kernel runs
-to its normal end in these cases."""
+to its normal end in these cases. A step that fails (a Gram precision fixed
+too low for the damping: DNGD_ENOTPD) leaves the handle usable: the next
+step is finite and the same as on a fresh handle."""
 import numpy as np
 import pytest
 
@@ -115,3 +117,37 @@ def test_serving_budget_forces_queueing_and_rejection():
     srv = SV.Server(budget_bytes=fps[0] - 1, max_slots=4)
     rep = srv.run(specs, realtime=False)
     assert rep["rejected"] == len(specs) and rep["steps"] == 0
+
+
+def test_failed_step_leaves_the_handle_usable():
+    """A stiff 2-D Poisson job of the serving stream (m = 5742, width 256):
+    a mixed step with the 3-pass Gram fixed (indefinite by about 2^-16
+    max ||J_i||^2, far above lambda) fails to factor (DNGD_ENOTPD) and
+    runs to its end with a non-finite factor. The next automatic step on the
+    handle (whose GA correction is rejected before the acceleration is
+    formed) must be finite and equal, bit for bit, to the same step on a
+    fresh handle, which escalates to the same Gram tier."""
+    from paper_2505_21404_amd import serving as SV
+    d = D()
+    sp = SV.specs_from_workloads(W.serving_jobs(n_jobs=8, rate=4.0, steps=200))[4]
+    p = sp.problem
+    assert p.pde == 0 and p.m == 5742
+    auto = d.step_opts(precision=d.MIXED, ga=True, no_lookahead=True)
+    prob = d.Problem.from_workload(p)
+    th = torch.tensor(sp.theta0, device="cuda")
+    st = prob.iterate(th, SV.ETA_GRID, lam_cap=sp.lam_cap, opts=auto)
+    lam = st.lam
+    with pytest.raises(d.DngdError) as err:
+        prob.step(th, lam, d.step_opts(precision=d.MIXED, ga=True, no_lookahead=True,
+                                       gram_passes=3))
+    assert err.value.status == d.ENOTPD
+    d1, s1 = prob.step(th, lam, auto)
+    fresh = d.Problem.from_workload(p)
+    d2, s2 = fresh.step(th, lam, auto)
+    say(f"after the failed step: finite {bool(torch.isfinite(d1).all())}, tier "
+        f"{s1.gram_passes_used} (fresh handle {s2.gram_passes_used}), early GA rejection "
+        f"{s1.ga_early_reject}")
+    assert torch.isfinite(d1).all()
+    assert s1.gram_passes_used == s2.gram_passes_used and torch.equal(d1, d2)
+    fresh.close()
+    prob.close()
