@@ -171,3 +171,29 @@ def test_refined_solve_composes_the_mixed_step_at_full_size():
     for k in range(2):  # the same per-sweep residuals, ||s_k|| / ||r||
         assert abs(res[0, k] - st.ir_residual[k]) <= 1e-12 * st.ir_residual[k]
     prob.close()
+
+
+def test_refined_solve_degenerate_sizes():
+    """No right-hand sides (factor only, nothing else written) and a single
+    residual (m = 1: K = ||J_1||^2 + lam, x = b / K) with FP32 and FP64 J."""
+    d = D()
+    p, th, Jt, Jd, n, lam, kappa = setup(torch.float32, 1e-3, seed=6)
+    m = Jd.shape[0]
+    say("case refine degenerate sizes: m", m, "n", n)
+    K = d.gram(Jt, n, lam, passes=3)
+    K0 = K.clone()
+    info, res = d.cholesky_solve_refine(K, torch.empty(0, m, dtype=torch.float64, device="cuda"),
+                                        Jt, n, lam, 2)
+    assert info == 0 and res.shape == (0, 2)
+    Kf = K0.clone()
+    assert d.cholesky_solve(Kf, torch.empty(0, m, dtype=torch.float64, device="cuda")) == 0
+    assert torch.equal(torch.tril(K), torch.tril(Kf))  # the same factor, lower triangle
+    for dt in (torch.float32, torch.float64):
+        J1 = Jt[:1].to(dt).contiguous()
+        k11 = float((J1[0, :n].double() ** 2).sum()) + lam
+        K1 = d.gram(J1, n, lam, passes=3 if dt == torch.float32 else 1)
+        b = torch.tensor([0.7], dtype=torch.float64, device="cuda")
+        info, res = d.cholesky_solve_refine(K1, b, J1, n, lam, 3)
+        say(f"  m = 1 ({dt}): x {float(b[0]):.17g} against {0.7 / k11:.17g}, residuals {res.tolist()}")
+        assert info == 0
+        assert abs(float(b[0]) - 0.7 / k11) <= 1e-14 * abs(0.7 / k11)
