@@ -284,18 +284,26 @@ __device__ inline int ntoff(int r, int c) { return r * (KS * 8) + ((c ^ ntsw<KS>
 // CU-owning SYRK instance cannot have two for its LDS, and says so)
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Wpass-failed"
-template <int BM, int MODE, int KS = NTK>
+// TI = float: FP32 operands (the FP64-product Gram of an FP32 Jacobian). A
+// stage of KS = 32 floats has the byte layout of 16 doubles; each lane reads
+// the FP32 pair of its k pair (8 bytes) and widens it before the FP64 MFMAs.
+// Needs lda, ldb multiples of 4 and 16-byte aligned A, B.
+template <int BM, int MODE, int KS = NTK, typename TI = double>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_f64_nt_kernel(
-    int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
-    const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
+    int64_t M, int64_t N, int64_t K, double alpha, const TI* __restrict__ A, int64_t lda,
+    const TI* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
     double* __restrict__ work, int64_t k_per_split, int64_t ntiles) {
+  constexpr bool F32 = sizeof(TI) == 4;
+  static_assert(!F32 || KS == 32, "FP32 operands take 32-element stages");
+  constexpr int SWK = F32 ? KS / 2 : KS;  // the swizzle of a 128- or 256-byte plane row
   constexpr int BN = BM;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int CH = KS / 2;          // 16-byte chunks per plane row
+  constexpr int EPC = 16 / (int)sizeof(TI);  // elements per 16-byte chunk
+  constexpr int CH = KS / EPC;        // 16-byte chunks per plane row
   constexpr int RPI = 64 / CH;        // plane rows per DMA instruction (1 KB)
   constexpr int JPT = BM / RPI / 4;   // DMA instructions per wave per operand per stage
-  constexpr int PLANE = BM * KS * 8;
+  constexpr int PLANE = BM * KS * (int)sizeof(TI);
   __shared__ __attribute__((aligned(16))) char sA0[PLANE];
   __shared__ __attribute__((aligned(16))) char sB0[PLANE];
   __shared__ __attribute__((aligned(16))) char sA1[PLANE];
@@ -332,12 +340,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 #pragma unroll
       for (int j = 0; j < JPT; ++j) {
         const int r = (wave * JPT + j) * RPI + lane / CH;
-        const int64_t k = k0 + 2 * ((lane % CH) ^ ntsw<KS>(r));
+        const int64_t k = k0 + EPC * ((lane % CH) ^ ntsw<SWK>(r));
         const int64_t kk = (k < K) ? k : 0;  // in bounds; k >= kend is masked at the read
-        __builtin_amdgcn_global_load_lds(A + min(m0 + r, M - 1) * lda + kk,
+        // byte addresses: an argument whose type depends on TI would leave the
+        // device builtin to template instantiation, which the host pass does
+        // not complete (the kernel's host stub is then never emitted)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(A) +
+                                             (min(m0 + r, M - 1) * lda + kk) * (int64_t)sizeof(TI),
                                          (lds_void_t*)(dA + (wave * JPT + j) * 1024), 16, 0, 0);
         if (!same)
-          __builtin_amdgcn_global_load_lds(B + min(n0 + r, N - 1) * ldb + kk,
+          __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(B) +
+                                               (min(n0 + r, N - 1) * ldb + kk) * (int64_t)sizeof(TI),
                                            (lds_void_t*)(dB + (wave * JPT + j) * 1024), 16, 0, 0);
       }
     };
@@ -359,16 +372,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
           ok0 = k0 + 2 * c < kend;
           ok1 = k0 + 2 * c + 1 < kend;
         }
+        // the k pair (2 c, 2 c + 1) of a plane row: a 16-byte chunk of
+        // doubles, or half of one (chunk c / 2, 8-byte half c % 2) of floats
+        auto frag = [&](const char* S, int row) -> double2 {
+          if constexpr (F32) {
+            const float2 f = *reinterpret_cast<const float2*>(
+                S + ntoff<SWK>(row, c >> 1) + ((c & 1) << 3));
+            return double2{(double)f.x, (double)f.y};
+          } else {
+            return *reinterpret_cast<const double2*>(S + ntoff<SWK>(row, c));
+          }
+        };
         double2 a[TM], b[TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
-          a[i] = *reinterpret_cast<const double2*>(SA + ntoff<KS>(wm * WM + i * 16 + (lane & 15), c));
+          a[i] = frag(SA, wm * WM + i * 16 + (lane & 15));
           if (!ok0) a[i].x = 0.0;
           if (!ok1) a[i].y = 0.0;
         }
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          b[j] = *reinterpret_cast<const double2*>(SB + ntoff<KS>(wn * WN + j * 16 + (lane & 15), c));
+          b[j] = frag(SB, wn * WN + j * 16 + (lane & 15));
           if (!ok0) b[j].x = 0.0;
           if (!ok1) b[j].y = 0.0;
         }
@@ -519,8 +543,8 @@ int gemm_f64_batched(hipStream_t s, bool a_kcontig, bool b_kcontig, int64_t M, i
   return -1;
 }
 
-int gemm_f64_syrk_partial_f32(hipStream_t s, int64_t M, int64_t K, const float* A, int64_t lda,
-                              double* work, int splits) {
+static int gemm_f64_syrk_partial_f32_generic(hipStream_t s, int64_t M, int64_t K, const float* A,
+                                             int64_t lda, double* work, int splits) {
   if (M <= 0) return 0;
   const int64_t ntiles = lower_tiles(M, 128);
   const int64_t kps = round_up(cdiv(K, splits), KS);
@@ -542,12 +566,12 @@ namespace {
 // dynamic LDS) has its CU to itself
 constexpr size_t kLdsPerCu = 160 * 1024;
 
-template <int BM, int MODE, int KS = NTK>
-int launch_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+template <int BM, int MODE, int KS = NTK, typename TI = double>
+int launch_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const TI* A,
+              int64_t lda, const TI* B, int64_t ldb, double beta, double* C, int64_t ldc,
               double* work, int splits, int own_cus = 0) {
-  const size_t static_lds = 4 * (size_t)BM * KS * 8;
-  static_assert(4 * (size_t)BM * KS * 8 <= kLdsPerCu, "LDS planes exceed a CU");
+  const size_t static_lds = 4 * (size_t)BM * KS * sizeof(TI);
+  static_assert(4 * (size_t)BM * KS * sizeof(TI) <= kLdsPerCu, "LDS planes exceed a CU");
   const size_t dyn = own_cus > 0 ? kLdsPerCu - static_lds : 0;
   dim3 grid;
   int64_t ntiles = 0, kps = K;
@@ -566,7 +590,7 @@ int launch_nt(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, cons
     const int64_t rounds = cdiv(grid.x, own_cus);
     grid.x = (unsigned)cdiv(grid.x, rounds);
   }
-  hipLaunchKernelGGL((gemm_f64_nt_kernel<BM, MODE, KS>), grid, dim3(256), (unsigned)dyn, s, M, N, K,
+  hipLaunchKernelGGL((gemm_f64_nt_kernel<BM, MODE, KS, TI>), grid, dim3(256), (unsigned)dyn, s, M, N, K,
                      alpha, A, lda, B, ldb, beta, C, ldc, work, kps, ntiles);
   DNGD_LAUNCH_CHECK();
   if (MODE == kPartialFull) {
@@ -659,6 +683,18 @@ int gemm_f64(hipStream_t s, GemmMode mode, bool a_kcontig, bool b_kcontig, int64
   DNGD_GEMM_CASE(false, false)
 #undef DNGD_GEMM_CASE
   return -1;
+}
+
+// FP64 products of an FP32 matrix: the K-contiguous kernel (widening at the
+// LDS read) when A is 16-byte aligned with lda % 4 == 0, else the generic one.
+// Both write the same partial-tile layout (lower 128 x 128 tiles by split).
+int gemm_f64_syrk_partial_f32(hipStream_t s, int64_t M, int64_t K, const float* A, int64_t lda,
+                              double* work, int splits) {
+  if (M <= 0) return 0;
+  if (lda % 4 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0)
+    return launch_nt<128, GEMM_PARTIAL_LOWER, 32, float>(s, M, M, K, 1.0, A, lda, A, lda, 0.0,
+                                                         nullptr, 0, work, splits);
+  return gemm_f64_syrk_partial_f32_generic(s, M, K, A, lda, work, splits);
 }
 
 }  // namespace dngd

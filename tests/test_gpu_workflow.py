@@ -378,14 +378,17 @@ def test_stiff_job_remembers_its_gram_tier():
     prob.close()
 
 
-def test_gram_f64_products_of_fp32_jacobian():
+@pytest.mark.parametrize("m,n,ld", [(300, 7001, 7004), (129, 5, 8), (700, 33, 36), (1, 64, 64),
+                                    (257, 3000, 3000)])
+def test_gram_f64_products_of_fp32_jacobian(m, n, ld):
     """dngd_gram with FP32 J and passes = DNGD_GRAM_F64: the exact Gram of the
-    FP32 values up to FP64 rounding."""
+    FP32 values up to FP64 rounding, on the K-contiguous kernel that widens
+    FP32 at the LDS read (ragged 128-row tiles, K below one 32-element stage,
+    a partial last stage, a single row). An FP32 J whose row stride is not a
+    multiple of 4 is rejected."""
     d = D()
-    rng = np.random.default_rng(4)
-    m, n = 300, 7001
+    rng = np.random.default_rng(4 + m)
     J = (rng.standard_normal((m, n)) * rng.uniform(0.1, 3.0, size=(m, 1))).astype(np.float32)
-    ld = (n + 3) // 4 * 4
     Jp = np.zeros((m, ld), dtype=np.float32)
     Jp[:, :n] = J
     K = d.gram(torch.tensor(Jp, device="cuda"), n, 0.5, passes=d.GRAM_F64).cpu().numpy()
@@ -393,6 +396,10 @@ def test_gram_f64_products_of_fp32_jacobian():
     ref = J64 @ J64.T + 0.5 * np.eye(m)
     low = np.tril_indices(m)
     assert np.abs(K[low] - ref[low]).max() <= 1e-13 * np.abs(ref).max()
+    if n % 4:
+        with pytest.raises(d.DngdError) as err:
+            d.gram(torch.tensor(J, device="cuda"), n, 0.5, passes=d.GRAM_F64)
+        assert err.value.status == d.EINVAL
 
 
 def test_pcg_heat_all_landmarks_and_partial():
