@@ -342,16 +342,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         const int r = (wave * JPT + j) * RPI + lane / CH;
         const int64_t k = k0 + EPC * ((lane % CH) ^ ntsw<SWK>(r));
         const int64_t kk = (k < K) ? k : 0;  // in bounds; k >= kend is masked at the read
-        // byte addresses: an argument whose type depends on TI would leave the
-        // device builtin to template instantiation, which the host pass does
-        // not complete (the kernel's host stub is then never emitted)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(A) +
-                                             (min(m0 + r, M - 1) * lda + kk) * (int64_t)sizeof(TI),
-                                         (lds_void_t*)(dA + (wave * JPT + j) * 1024), 16, 0, 0);
-        if (!same)
-          __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(B) +
-                                               (min(n0 + r, N - 1) * ldb + kk) * (int64_t)sizeof(TI),
-                                           (lds_void_t*)(dB + (wave * JPT + j) * 1024), 16, 0, 0);
+        // the source pointer is cast to its concrete type: an argument whose
+        // type depends on TI would leave the device builtin to template
+        // instantiation, which the host pass does not complete (the kernel's
+        // host stub is then never emitted)
+        const int64_t ia = min(m0 + r, M - 1) * lda + kk, ib = min(n0 + r, N - 1) * ldb + kk;
+        char* la = dA + (wave * JPT + j) * 1024;
+        char* lb = dB + (wave * JPT + j) * 1024;
+        if constexpr (F32) {
+          __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>(A) + ia,
+                                           (lds_void_t*)la, 16, 0, 0);
+          if (!same)
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>(B) + ib,
+                                             (lds_void_t*)lb, 16, 0, 0);
+        } else {
+          __builtin_amdgcn_global_load_lds(reinterpret_cast<const double*>(A) + ia,
+                                           (lds_void_t*)la, 16, 0, 0);
+          if (!same)
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const double*>(B) + ib,
+                                             (lds_void_t*)lb, 16, 0, 0);
+        }
       }
     };
 
