@@ -14,8 +14,8 @@ precision steps/s (FP32 J, BF16-MFMA Gram, FP64 Cholesky + 2 refinement
 sweeps); the plain FP64 path is timed on the same GPU and reported beside it,
 as are the 31-point line search and the resulting optimiser iterations/s.
 
-Prints one JSON line. ``--gpus N`` with N > 1 is refused: this build runs on
-one GPU.
+Prints one JSON line. ``--gpus N`` with N > 1 is refused: the library runs the
+step on one GPU (there is no multi-GPU path).
 """
 from __future__ import annotations
 
@@ -481,7 +481,7 @@ def factor_compare_run(a, torch):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: --gpus {a.gpus} refused: this build runs the D-NGD step on one GPU "
+        print(f"bench.py: --gpus {a.gpus} refused: libdngd runs the D-NGD step on one GPU "
               "only (no multi-GPU path).", file=sys.stderr)
         return 2
     import numpy as np
