@@ -150,7 +150,7 @@ def test_gram_bf16_four_products_is_semidefinite():
     assert ev[0] >= -n ** 0.5 * 2.0 ** -22 * dmax
 
 
-@pytest.mark.parametrize("m", [1, 2, 63, 64, 65, 130, 700])
+@pytest.mark.parametrize("m", [1, 2, 63, 64, 65, 130, 700, 1000])
 def test_cholesky_solve(m):
     say("case cholesky_solve", m)
     rng = np.random.default_rng(m)
