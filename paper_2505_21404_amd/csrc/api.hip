@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
 #include <vector>
 
@@ -96,6 +97,8 @@ struct dngd_problem {
   hipStream_t astream = nullptr;
   hipEvent_t last_use = nullptr;
   bool last_use_valid = false;
+  // pinned host staging of the small device-to-host readbacks (read_back)
+  void* hstage = nullptr;
 };
 
 namespace {
@@ -111,6 +114,35 @@ int dmalloc(dngd_problem* h, void** p, size_t bytes) {
     return hip_fail(e, "hipMallocAsync", __FILE__, __LINE__);
   }
   h->owned.push_back(*p);
+  return 0;
+}
+
+// Readback of several small device arrays with one wait: the copies land in
+// the handle's pinned staging buffer (a copy into pageable memory holds the
+// calling thread until it completes, one round trip per copy) and are moved
+// to their destinations after the stream has been waited for.
+constexpr size_t kHostStageBytes = 1024;
+struct Readback {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+
+int read_back(dngd_problem* h, hipStream_t s, std::initializer_list<Readback> items) {
+  char* stage = static_cast<char*>(h->hstage);
+  size_t off = 0;
+  for (const Readback& it : items) {
+    DNGD_REQUIRE(off + it.bytes <= kHostStageBytes, "read_back: %zu bytes exceed the stage",
+                 off + it.bytes);
+    if (it.bytes) DNGD_HIP(hipMemcpyAsync(stage + off, it.src, it.bytes, hipMemcpyDeviceToHost, s));
+    off += (it.bytes + 7) & ~size_t(7);
+  }
+  DNGD_HIP(hipStreamSynchronize(s));
+  off = 0;
+  for (const Readback& it : items) {
+    if (it.bytes) std::memcpy(it.dst, stage + off, it.bytes);
+    off += (it.bytes + 7) & ~size_t(7);
+  }
   return 0;
 }
 
@@ -948,6 +980,10 @@ int dngd_problem_create(const dngd_problem_desc* d, dngd_problem** out) {
     if (hipEventCreate(&h->ev[e]) != hipSuccess) rc = DNGD_EHIP;
   for (int e = 0; e < 2 && !rc; ++e)
     if (hipEventCreateWithFlags(&h->cev[e], hipEventDisableTiming) != hipSuccess) rc = DNGD_EHIP;
+  if (!rc && hipHostMalloc(&h->hstage, kHostStageBytes, hipHostMallocDefault) != hipSuccess) {
+    h->hstage = nullptr;
+    rc = DNGD_EHIP;
+  }
   if (!rc) {  // the activation buffers are allocated once creation returns
     hipError_t e = hipStreamSynchronize(h->side);
     if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
@@ -975,6 +1011,7 @@ int dngd_problem_destroy(dngd_problem* h) {
   for (auto& e : h->cev)
     if (e) hipEventDestroy(e);
   if (h->side) hipStreamDestroy(h->side);
+  if (h->hstage) hipHostFree(h->hstage);
   delete h;
   return DNGD_OK;
 }
@@ -1725,10 +1762,9 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     DNGD_HIP(hipEventRecord(h->ev[7], s));
     double nv[2] = {0, 0};
     int gaf = 0;
-    DNGD_HIP(hipMemcpyAsync(nv, v.scal, sizeof(nv), hipMemcpyDeviceToHost, s));
-    if (o.ga && pst_ga == DNGD_OK)
-      DNGD_HIP(hipMemcpyAsync(&gaf, sm.ga_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    DNGD_HIP(hipStreamSynchronize(s));
+    rc = read_back(h, s, {{nv, v.scal, sizeof(nv)},
+                          {&gaf, sm.ga_flag, (o.ga && pst_ga == DNGD_OK) ? sizeof(int) : 0}});
+    if (rc) return rc;
     float ms = 0;
     hipEventElapsedTime(&ms, h->ev[0], h->ev[7]);
     st.ms_total = ms;
@@ -1819,10 +1855,9 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     double sc[2] = {0, 0};
     int gaf = 0;
     int64_t info = 0;
-    DNGD_HIP(hipMemcpyAsync(sc, v.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
-    DNGD_HIP(hipMemcpyAsync(&info, sm.info, 8, hipMemcpyDeviceToHost, s));
-    DNGD_HIP(hipMemcpyAsync(&gaf, sm.ga_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    DNGD_HIP(hipStreamSynchronize(s));
+    rc = read_back(h, s, {{sc, v.scal, sizeof(sc)}, {&info, sm.info, 8},
+                          {&gaf, sm.ga_flag, sizeof(int)}});
+    if (rc) return rc;
     float ms = 0;
     hipEventElapsedTime(&ms, h->ev[0], h->ev[6]);
     st.ms_total = ms;
@@ -1909,8 +1944,10 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     rc = vmax(s, op.M, diag, v.scal + 31, v.red);
     if (rc) return rc;
     double rd[2];
-    DNGD_HIP(hipMemcpyAsync(rd, v.scal + 30, sizeof(rd), hipMemcpyDeviceToHost, s));
-    DNGD_HIP(hipStreamSynchronize(s));
+    {
+      const int rb_ = read_back(h, s, {{rd, v.scal + 30, sizeof(rd)}});
+      if (rb_) return rb_;
+    }
     const double dmax = std::max(rd[1], 0.0);
     st.max_row_norm2 = rd[1];
     if (!std::isfinite(rd[0]) || !std::isfinite(rd[1])) {
@@ -1965,8 +2002,10 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
     if (rc) return rc;
     const bool can_escalate = adaptive && passes != DNGD_GRAM_F64;
     if (can_escalate) {
-      DNGD_HIP(hipMemcpyAsync(&info, sm.info, 8, hipMemcpyDeviceToHost, s));
-      DNGD_HIP(hipStreamSynchronize(s));
+      {
+        const int rb_ = read_back(h, s, {{&info, sm.info, 8}});
+        if (rb_) return rb_;
+      }
       if (info != 0) {  // K~ + lam I not positive definite in this precision
         passes = (passes == 4) ? DNGD_GRAM_F64 : 4;
         continue;
@@ -1985,8 +2024,10 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
       double sc2[9];
       rc = sumsq(s, op.M, rhs1, v.scal + 15, v.red);
       if (rc) return rc;
-      DNGD_HIP(hipMemcpyAsync(sc2, v.scal + 15, sizeof(sc2), hipMemcpyDeviceToHost, s));
-      DNGD_HIP(hipStreamSynchronize(s));
+      {
+        const int rb_ = read_back(h, s, {{sc2, v.scal + 15, sizeof(sc2)}});
+        if (rb_) return rb_;
+      }
       const double nr = std::sqrt(sc2[0]);
       const double last = nr > 0 ? std::sqrt(sc2[1 + std::min(ir, 8) - 1]) / nr : 0.0;
       if (!(last <= o.ir_tol)) {
@@ -2047,8 +2088,10 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
       if (!rc) rc = sumsq(s, g.m, op.sM, v.scal + 2, v.red);
       if (rc) return rc;
       double nr[3];
-      DNGD_HIP(hipMemcpyAsync(nr, v.scal, sizeof(nr), hipMemcpyDeviceToHost, s));
-      DNGD_HIP(hipStreamSynchronize(s));
+      {
+        const int rb_ = read_back(h, s, {{nr, v.scal, sizeof(nr)}});
+        if (rb_) return rb_;
+      }
       const double nv = std::sqrt(nr[0]);
       const double a_low = std::sqrt(nr[1]) - std::sqrt(nr[2]) / (2.0 * std::sqrt(lambda));
       if (nv > o.eps_norm && 2.0 * a_low > 0.5 * nv) {
@@ -2090,10 +2133,9 @@ int dngd_step(dngd_problem* h, const double* theta, double lambda, const dngd_st
 
   double sc[32];
   int gaf = 0;
-  DNGD_HIP(hipMemcpyAsync(sc, v.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
-  DNGD_HIP(hipMemcpyAsync(&info, sm.info, 8, hipMemcpyDeviceToHost, s));
-  DNGD_HIP(hipMemcpyAsync(&gaf, sm.ga_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  DNGD_HIP(hipStreamSynchronize(s));
+  rc = read_back(h, s, {{sc, v.scal, sizeof(sc)}, {&info, sm.info, 8},
+                        {&gaf, sm.ga_flag, sizeof(int)}});
+  if (rc) return rc;
   float ms = 0;
   hipEventElapsedTime(&ms, h->ev[0], h->ev[6]);
   st.ms_total = ms;
@@ -2162,8 +2204,10 @@ int dngd_iterate(dngd_problem* h, double* theta, double lambda_cap, double lambd
   if (!rc) rc = sumsq(s, g.m, v.tmpm, v.scal + 56, v.red);
   if (rc) return rc;
   double rr = 0.0;
-  DNGD_HIP(hipMemcpyAsync(&rr, v.scal + 56, 8, hipMemcpyDeviceToHost, s));
-  DNGD_HIP(hipStreamSynchronize(s));
+  {
+    const int rb_ = read_back(h, s, {{&rr, v.scal + 56, 8}});
+    if (rb_) return rb_;
+  }
   const double L0 = 0.5 * rr;
   DNGD_REQUIRE(std::isfinite(L0), "dngd_iterate: non-finite loss at theta");
   double lam = (lambda_fixed > 0.0) ? lambda_fixed : std::min(L0, lambda_cap);
