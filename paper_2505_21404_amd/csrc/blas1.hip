@@ -9,6 +9,7 @@
 // per-band partial sums are added in FP64 in band order by a second kernel.
 // J t: 4 rows per workgroup so each slab of t (FP64, 2x the bytes of an FP32
 // row slab) is loaded once for 4 rows, with enough workgroups to fill the chip.
+// Both read J once per call, through nontemporal (streaming) loads.
 #include "common.h"
 
 namespace dngd {
@@ -23,6 +24,12 @@ struct Vec4<float> {
     const float4 x = *reinterpret_cast<const float4*>(p);
     v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
   }
+  // J read once per call: a streaming (nontemporal) load
+  __device__ static inline void stream(const float* p, double (&v)[4]) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 x = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+    v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+  }
 };
 template <>
 struct Vec4<double> {
@@ -30,6 +37,12 @@ struct Vec4<double> {
     const double2 x = *reinterpret_cast<const double2*>(p);
     const double2 y = *reinterpret_cast<const double2*>(p + 2);
     v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+  }
+  __device__ static inline void stream(const double* p, double (&v)[4]) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 x = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+    const d2 y = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p + 2));
+    v[0] = x[0]; v[1] = x[1]; v[2] = y[0]; v[3] = y[1];
   }
 };
 
@@ -45,7 +58,7 @@ __global__ __launch_bounds__(256) void gemv_t_partial_kernel(int64_t m, int64_t 
   if (c < n) {
     for (int64_t r = r0; r < r1; ++r) {
       double v[4];
-      Vec4<T>::load(J + r * ldJ + c, v);
+      Vec4<T>::stream(J + r * ldJ + c, v);
       const double xr = x[r];
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[e] += v[e] * xr;
@@ -88,7 +101,7 @@ __global__ __launch_bounds__(256) void gemv_n_kernel(int64_t m, int64_t n, const
     if (k + 3 < n) {
       Vec4<double>::load(t + k, tv);
 #pragma unroll
-      for (int q = 0; q < GN_ROWS; ++q) Vec4<T>::load(J + min(row0 + q, m - 1) * ldJ + k, v[q]);
+      for (int q = 0; q < GN_ROWS; ++q) Vec4<T>::stream(J + min(row0 + q, m - 1) * ldJ + k, v[q]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
