@@ -365,8 +365,9 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t m, const P* __
   double s[4] = {0, 0, 0, 0};
   for (int sp = 0; sp < splits; ++sp) {
     const P* p = work + ((int64_t)sp * ntiles + blockIdx.x) * (T * T) + rl * T + cl0;
+    // each partial is read once: streaming (nontemporal) loads
 #pragma unroll
-    for (int e = 0; e < 4; ++e) s[e] += (double)p[e];
+    for (int e = 0; e < 4; ++e) s[e] += (double)__builtin_nontemporal_load(p + e);
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
